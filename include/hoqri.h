@@ -1,0 +1,158 @@
+/*
+ * hoqri.h — C ABI of the MI355X (gfx950) HOQRI library.
+ *
+ * HOQRI (higher-order QR iteration) computes a low multilinear rank (Tucker)
+ * approximation X ~ G x {U} of a sparse N-way tensor X by maximising
+ * ||X x {U^T}||^2 over factors U^(n) with orthonormal columns (§2.2). Each
+ * iteration sweeps n = 1..N (Alg. 2): A^(n) = TTMcTC(X, {U}, n), then U^(n) =
+ * an orthonormal basis of A^(n) by QR. TTMcTC is A^(n) = Y_(n) G_(n)^T where
+ * Y = X x_{-n} {U^T} and G = X x {U^T} (definition in §4.1); Y is never formed.
+ *
+ * Conventions used by every entry point:
+ *  - Pointers named d_* are device (HBM) memory owned by the caller; this
+ *    library never frees them. Host arrays are read during the call only.
+ *  - Indices are 0-based int32. A sparse tensor is given as coordinates
+ *    d_idx[N][nnz] (structure of arrays: mode m's indices at d_idx + m*nnz) and
+ *    values d_vals[nnz] (float32).
+ *  - A factor U^(n) is row-major I_n x K_n float32. The core G is a dense
+ *    K_1 x ... x K_N float32 array in C order (last mode fastest), so its
+ *    mode-n unfolding G_(n) has the other modes ascending, last fastest.
+ *  - Every call is asynchronous on `stream` unless documented otherwise and
+ *    returns a hoqri_status; argument errors are detected on the host before
+ *    any launch and leave outputs untouched. No C++ exception crosses the ABI.
+ *  - Calls on one plan must not overlap (they share its scratch memory);
+ *    distinct plans may run concurrently on distinct streams.
+ *  - Results are deterministic: the same inputs give bitwise-identical outputs
+ *    (fixed-order reductions, no floating-point atomics).
+ */
+#ifndef HOQRI_H
+#define HOQRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HOQRI_OK = 0,
+  HOQRI_ERR_ARG = -1,         /* invalid argument (null pointer, bad order/size, nnz < 1, ...) */
+  HOQRI_ERR_INDEX = -2,       /* a coordinate lies outside [0, I_n) */
+  HOQRI_ERR_RANK = -3,        /* K_n outside [1, I_n], or K_n > prod_{m!=n} K_m */
+  HOQRI_ERR_BREAKDOWN = -4,   /* A^(n) numerically rank deficient: no orthonormal basis */
+  HOQRI_ERR_NOMEM = -5,       /* caller workspace too small */
+  HOQRI_ERR_HIP = -6,         /* a HIP runtime call failed (no device, launch failure, ...) */
+  HOQRI_ERR_UNSUPPORTED = -7  /* shape not supported by the compiled kernels (see limits below) */
+} hoqri_status;
+
+/* Operand precision of the Kronecker x core contraction. Accumulation is always
+ * float32; Gram matrices, Cholesky factors and scalars are float64. */
+typedef enum {
+  HOQRI_FP32 = 1,  /* float32 operands on the float32 matrix cores */
+  HOQRI_BF16 = 2,  /* bfloat16 operands (round to nearest even), float32 accumulate */
+  HOQRI_FP16 = 3   /* float16 operands with a power-of-two scale per factor, float32 accumulate */
+} hoqri_prec;
+
+/* Limits of this build: 2 <= N <= 4; 1 <= K_n <= 32; prod_{m!=n} K_m <= 2048;
+ * nnz < 2^31; every I_n < 2^31 and I_n * K_n * 4 bytes < 2^32. */
+#define HOQRI_MAX_ORDER 4
+#define HOQRI_MAX_RANK 32
+
+typedef struct hoqri_plan hoqri_plan; /* opaque; host object pointing into the caller's workspace */
+
+/* Exact device workspace (bytes) that hoqri_plan_create needs for this shape.
+ * nnz is the number of stored coordinates before duplicates are merged.
+ * Host-side only apart from querying the device's sort temporary size; needs a
+ * visible HIP device (HOQRI_ERR_HIP otherwise). Used for admission by footprint. */
+hoqri_status hoqri_plan_workspace_size(int32_t order, const int64_t* dims, const int32_t* ranks,
+                                       int64_t nnz, size_t* bytes);
+
+/* Builds the plan for tensor X with target ranks K (§2.2): merges duplicate
+ * coordinates by summing their values, computes ||X||^2 in float64, and for each
+ * mode n keeps a copy of the nonzeros stably sorted by i_n together with the
+ * table of nonempty index sets I^(n)_{i_n} (Table 1: the nonzeros whose mode-n
+ * index is i_n). d_idx and d_vals are read only during this call and may be
+ * freed afterwards. d_ws (ws_bytes >= hoqri_plan_workspace_size) must stay
+ * allocated until hoqri_plan_destroy. Synchronises `stream` twice (index check
+ * and sizes). Errors: HOQRI_ERR_INDEX for a coordinate out of range,
+ * HOQRI_ERR_RANK for invalid ranks, HOQRI_ERR_NOMEM for a short workspace. */
+hoqri_status hoqri_plan_create(hoqri_plan** plan, int32_t order, const int64_t* dims,
+                               const int32_t* ranks, int64_t nnz, const int32_t* d_idx,
+                               const float* d_vals, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Information about a built plan (host values): number of distinct coordinates,
+ * ||X||^2 and, if R is not NULL, the number of nonempty mode-n slices R[n]. */
+hoqri_status hoqri_plan_info(const hoqri_plan* plan, int64_t* nnz_coalesced, double* norm_x2, int64_t* R);
+
+/* Releases the host object. Frees nothing the caller owns. */
+void hoqri_plan_destroy(hoqri_plan* plan);
+
+/* Core G = X x {U^T} (§2.2; first line of Alg. 3): G(k) = sum over nonzeros of
+ * x(i) prod_m U^(m)(i_m, k_m). d_U is a HOST array of N device pointers (factor
+ * m row-major I_m x K_m). Writes all prod K_m entries of d_G (C order). If
+ * d_f is not NULL, writes f = ||G||^2 (float64, device) there. */
+hoqri_status hoqri_core(hoqri_plan* plan, const float* const* d_U, float* d_G, double* d_f,
+                        hoqri_prec prec, hipStream_t stream);
+
+/* TTMcTC (definition in §4.1; Alg. 3): A^(n) = Y_(n) G_(n)^T with
+ * Y = X x_{-n} {U^T}, i.e. A(i_n, k_n) = sum over nonzeros with mode-n index
+ * i_n and over k_{-n} of x(i) G(k) prod_{m!=n} U^(m)(i_m, k_m). Y is never
+ * formed. d_G is the core (C order) the caller supplies, usually hoqri_core's
+ * output for the same factors. d_A (I_n x K_n row-major) is fully overwritten;
+ * rows of empty slices are zero. */
+hoqri_status hoqri_ttmctc(hoqri_plan* plan, int32_t mode, const float* const* d_U, const float* d_G,
+                          float* d_A, hoqri_prec prec, hipStream_t stream);
+
+/* Device workspace bytes hoqri_orth needs for `rows` x `cols`. Host only. */
+size_t hoqri_orth_workspace_size(int64_t rows, int32_t cols);
+
+/* Orthonormal basis of A (the QR step of Alg. 2) by CholeskyQR2 with float64
+ * Gram matrices and Cholesky factors: W1 = A^T A, R1 = chol(W1), Q1 = A R1^-1,
+ * W2 = Q1^T Q1, R2 = chol(W2), U = A (R2 R1)^-1. This is the thin QR with a
+ * positive diagonal of R. d_A: rows x cols float32 row-major, cols <= 32 <= ...
+ * d_U: output, may alias d_A. d_R: optional (NULL allowed) cols x cols float64
+ * upper-triangular R = R2 R1 (row-major). d_status: device int32 set to 0 on
+ * success or HOQRI_ERR_BREAKDOWN when a Cholesky pivot is <= 1e-13 * trace(W)
+ * (A numerically rank deficient); then d_U is left unchanged. */
+hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A, float* d_U, double* d_R,
+                        int32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+typedef struct {
+  int32_t max_sweeps;   /* sweeps over all N modes (one sweep = one HOQRI iteration) */
+  double tol;           /* stop when |f_t - f_{t-1}| <= tol * f_t (0 disables) */
+  hoqri_prec prec;      /* operand precision of the segment passes */
+  int32_t check_every;  /* read f back every this many sweeps (>= 1) */
+  int32_t orthonormalize_input; /* nonzero: first replace each U^(n) by its orthonormal basis */
+} hoqri_run_opts;
+
+typedef struct {
+  int32_t sweeps;       /* sweeps performed */
+  double norm_x2;       /* ||X||^2 */
+  double f;             /* ||G||^2 for the returned factors */
+  double fit;           /* 1 - sqrt(max(||X||^2 - f, 0)) / ||X|| */
+  double rel_change;    /* |f_t - f_{t-1}| / f_t at the last sweep */
+  double orth_err_max;  /* max_n ||U^(n)T U^(n) - I||_F of the returned factors */
+} hoqri_run_stats;
+
+/* HOQRI (Alg. 2): for each sweep, for n = 1..N: G from the current factors,
+ * A^(n) = TTMcTC, U^(n) = orthonormal basis of A^(n) (Gauss-Seidel order).
+ * d_U_inout: host array of N device pointers, read as the start and overwritten
+ * with the result (orthonormal columns required unless orthonormalize_input).
+ * d_G_out: receives G = X x {U^T} for the returned factors (last line of
+ * Alg. 2). d_f_hist (optional, device, max_sweeps * N doubles) receives f
+ * before every mode update. stats (host) is filled at the end. Synchronises
+ * `stream` every check_every sweeps and at the end. Returns
+ * HOQRI_ERR_BREAKDOWN if some A^(n) is rank deficient. */
+hoqri_status hoqri_run(hoqri_plan* plan, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
+                       const hoqri_run_opts* opts, hoqri_run_stats* stats, hipStream_t stream);
+
+/* Human-readable name of a status code (static string). */
+const char* hoqri_status_string(hoqri_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOQRI_H */

@@ -1,0 +1,255 @@
+"""ctypes binding of libhoqri.so (include/hoqri.h).
+
+Argument marshalling only: every step of HOQRI runs in the library's HIP
+kernels. PyTorch provides device memory (tensors, including the plan
+workspace) and the stream (the current torch stream). If the library is not
+built, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhoqri.so")
+
+HOQRI_OK = 0
+STATUS = {
+    0: "HOQRI_OK", -1: "HOQRI_ERR_ARG", -2: "HOQRI_ERR_INDEX", -3: "HOQRI_ERR_RANK",
+    -4: "HOQRI_ERR_BREAKDOWN", -5: "HOQRI_ERR_NOMEM", -6: "HOQRI_ERR_HIP", -7: "HOQRI_ERR_UNSUPPORTED",
+}
+PREC = {"fp32": 1, "bf16": 2, "fp16": 3}
+
+# every symbol the header declares
+EXPORTS = (
+    "hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_plan_destroy",
+    "hoqri_core", "hoqri_ttmctc", "hoqri_orth_workspace_size", "hoqri_orth", "hoqri_run",
+    "hoqri_status_string",
+)
+
+
+class HoqriError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class RunOpts(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("prec", ctypes.c_int),
+                ("check_every", ctypes.c_int32), ("orthonormalize_input", ctypes.c_int32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("norm_x2", ctypes.c_double), ("f", ctypes.c_double),
+                ("fit", ctypes.c_double), ("rel_change", ctypes.c_double), ("orth_err_max", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libhoqri.so and declares the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    P = ctypes.POINTER
+    L.hoqri_plan_workspace_size.argtypes = [i32, P(i64), P(i32), i64, P(sz)]
+    L.hoqri_plan_create.argtypes = [P(vp), i32, P(i64), P(i32), i64, vp, vp, vp, sz, vp]
+    L.hoqri_plan_info.argtypes = [vp, P(i64), P(dbl), P(i64)]
+    L.hoqri_plan_destroy.argtypes = [vp]
+    L.hoqri_plan_destroy.restype = None
+    L.hoqri_core.argtypes = [vp, P(vp), vp, vp, ctypes.c_int, vp]
+    L.hoqri_ttmctc.argtypes = [vp, i32, P(vp), vp, vp, ctypes.c_int, vp]
+    L.hoqri_orth_workspace_size.argtypes = [i64, i32]
+    L.hoqri_orth_workspace_size.restype = sz
+    L.hoqri_orth.argtypes = [i64, i32, vp, vp, vp, vp, vp, sz, vp]
+    L.hoqri_run.argtypes = [vp, P(vp), vp, vp, P(RunOpts), P(RunStats), vp]
+    L.hoqri_status_string.argtypes = [ctypes.c_int]
+    L.hoqri_status_string.restype = ctypes.c_char_p
+    for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
+                 "hoqri_ttmctc", "hoqri_orth", "hoqri_run"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != HOQRI_OK:
+        raise HoqriError(status, where)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _need_cuda(t, dtype, name):
+    import torch
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+def hoqri_status_string(status: int) -> str:
+    return load().hoqri_status_string(int(status)).decode()
+
+
+def hoqri_plan_workspace_size(order: int, dims: Sequence[int], ranks: Sequence[int], nnz: int) -> int:
+    L = load()
+    d = (ctypes.c_int64 * order)(*dims)
+    r = (ctypes.c_int32 * order)(*ranks)
+    out = ctypes.c_size_t(0)
+    _check(L.hoqri_plan_workspace_size(order, d, r, int(nnz), ctypes.byref(out)), "hoqri_plan_workspace_size")
+    return int(out.value)
+
+
+def hoqri_orth_workspace_size(rows: int, cols: int) -> int:
+    return int(load().hoqri_orth_workspace_size(int(rows), int(cols)))
+
+
+class Plan:
+    """A built plan: owns its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, handle, workspace, dims, ranks):
+        self._h = handle
+        self.workspace = workspace
+        self.dims = tuple(int(d) for d in dims)
+        self.ranks = tuple(int(k) for k in ranks)
+        self.order = len(self.dims)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def destroy(self):
+        if self._h is not None:
+            load().hoqri_plan_destroy(self._h)
+            self._h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def hoqri_plan_create(idx, vals, dims: Sequence[int], ranks: Sequence[int], stream=None,
+                      workspace=None) -> Plan:
+    """idx: int32 CUDA tensor [N, nnz]; vals: float32 CUDA tensor [nnz]."""
+    import torch
+    L = load()
+    _need_cuda(idx, torch.int32, "idx")
+    _need_cuda(vals, torch.float32, "vals")
+    N = len(dims)
+    if idx.dim() != 2 or idx.shape[0] != N or vals.numel() != idx.shape[1]:
+        raise ValueError("idx must be [N, nnz] with nnz = len(vals)")
+    nnz = int(vals.numel())
+    nbytes = hoqri_plan_workspace_size(N, dims, ranks, nnz)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=vals.device)
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int64 * N)(*dims)
+    r = (ctypes.c_int32 * N)(*ranks)
+    _check(L.hoqri_plan_create(ctypes.byref(h), N, d, r, nnz, _ptr(idx), _ptr(vals), _ptr(workspace),
+                               workspace.numel(), _stream(stream)), "hoqri_plan_create")
+    return Plan(h, workspace, dims, ranks)
+
+
+def hoqri_plan_info(plan: Plan):
+    """Returns (nnz after merging duplicates, ||X||^2, [R_n nonempty slices])."""
+    L = load()
+    n = ctypes.c_int64()
+    x2 = ctypes.c_double()
+    R = (ctypes.c_int64 * plan.order)()
+    _check(L.hoqri_plan_info(plan.handle, ctypes.byref(n), ctypes.byref(x2), R), "hoqri_plan_info")
+    return int(n.value), float(x2.value), [int(v) for v in R]
+
+
+def hoqri_core(plan: Plan, Us, G=None, f=None, prec: str = "fp32", stream=None):
+    """G = X x {U^T}; returns G (float32, shape K) and, if f is given, fills f[0] = ||G||^2."""
+    import torch
+    L = load()
+    for U in Us:
+        _need_cuda(U, torch.float32, "U")
+    if G is None:
+        G = torch.empty(plan.ranks, dtype=torch.float32, device=Us[0].device)
+    _check(L.hoqri_core(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f) if f is not None else None,
+                        PREC[prec], _stream(stream)), "hoqri_core")
+    return G
+
+
+def hoqri_ttmctc(plan: Plan, mode: int, Us, G, A=None, prec: str = "fp32", stream=None):
+    """A^(n) = Y_(n) G_(n)^T; returns A (float32, I_n x K_n)."""
+    import torch
+    L = load()
+    for U in Us:
+        _need_cuda(U, torch.float32, "U")
+    _need_cuda(G, torch.float32, "G")
+    if A is None:
+        A = torch.empty((plan.dims[mode], plan.ranks[mode]), dtype=torch.float32, device=G.device)
+    _check(L.hoqri_ttmctc(plan.handle, int(mode), _ptr_array(Us), _ptr(G), _ptr(A), PREC[prec],
+                          _stream(stream)), "hoqri_ttmctc")
+    return A
+
+
+def hoqri_orth(A, U=None, R=None, status=None, workspace=None, stream=None):
+    """CholeskyQR2 orthonormal basis of A. Returns (U, status tensor)."""
+    import torch
+    L = load()
+    _need_cuda(A, torch.float32, "A")
+    rows, cols = A.shape
+    if U is None:
+        U = torch.empty_like(A)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if workspace is None:
+        workspace = torch.empty(hoqri_orth_workspace_size(rows, cols), dtype=torch.uint8, device=A.device)
+    _check(L.hoqri_orth(rows, cols, _ptr(A), _ptr(U), _ptr(R) if R is not None else None, _ptr(status),
+                        _ptr(workspace), workspace.numel(), _stream(stream)), "hoqri_orth")
+    return U, status
+
+
+@dataclass
+class Stats:
+    sweeps: int
+    norm_x2: float
+    f: float
+    fit: float
+    rel_change: float
+    orth_err_max: float
+
+
+def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp32", check_every: int = 1,
+              orthonormalize_input: bool = False, G=None, f_hist=None, stream=None):
+    """Runs HOQRI in place on Us. Returns (G, Stats)."""
+    import torch
+    L = load()
+    for U in Us:
+        _need_cuda(U, torch.float32, "U")
+    if G is None:
+        G = torch.empty(plan.ranks, dtype=torch.float32, device=Us[0].device)
+    opts = RunOpts(int(max_sweeps), float(tol), PREC[prec], int(check_every), int(bool(orthonormalize_input)))
+    st = RunStats()
+    _check(L.hoqri_run(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f_hist) if f_hist is not None else None,
+                       ctypes.byref(opts), ctypes.byref(st), _stream(stream)), "hoqri_run")
+    return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max)

@@ -1,0 +1,121 @@
+// Internal declarations shared by the translation units of libhoqri.
+// Everything here is an implementation detail behind include/hoqri.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/hoqri.h"
+
+namespace hoqri {
+
+constexpr int kMaxOrder = HOQRI_MAX_ORDER;
+constexpr int kMaxRank = HOQRI_MAX_RANK;
+constexpr int kWave = 64;
+constexpr int kMaxSweeps = 4096;
+
+// Status helpers -------------------------------------------------------------
+#define HOQRI_HIP_TRY(expr)                                  \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return HOQRI_ERR_HIP;              \
+  } while (0)
+
+#define HOQRI_TRY(expr)                                      \
+  do {                                                       \
+    hoqri_status _s = (expr);                                \
+    if (_s != HOQRI_OK) return _s;                           \
+  } while (0)
+
+// Per-mode data of a plan: the nonzeros stably sorted by their mode-n index,
+// stored as structure of arrays, and the table of nonempty slices.
+struct ModeData {
+  // oidx[m'] for the m'-th other mode (ascending, mode n skipped): the factor
+  // element offset i_m * K_m of each nonzero, in mode-n sorted order.
+  int32_t* oidx[kMaxOrder - 1];
+  float* val;          // values in mode-n sorted order
+  int32_t* seg_row;    // [R]   mode-n index of each nonempty slice (ascending)
+  int32_t* seg_off;    // [R+1] first nonzero of each slice in sorted order
+  int32_t* empty_row;  // [E]   mode-n indices whose slice is empty
+  int64_t R;           // number of nonempty slices
+  int64_t E;           // number of empty slices (I_n - R)
+  int32_t ranges;      // work ranges of the segment passes on this mode
+};
+
+// Scratch regions used by the passes (all inside the caller's workspace).
+struct Scratch {
+  float* A;            // max_n I_n * K_n floats: TTMcTC output inside hoqri_run
+  float* G;            // prod K floats: the core inside hoqri_run
+  float* gpart;        // core partials: core_groups * pad_core floats
+  double* fpart;       // per-block partial sums of ||G||^2
+  float* gtop;         // TTMcTC stage-two operand (core rearranged), <= 2 * pad floats
+  float* carry;        // ranges_max * 2 * 32 floats: partial rows of split slices
+  int32_t* meta;       // ranges_max * 4 ints
+  double* orth_ws;     // CholeskyQR2 workspace (Gram partials, factors)
+  int32_t* status;     // device status flags [4]
+  double* f_dev;       // scalars [64]
+  double* fsweep;      // f after each sweep inside hoqri_run [kMaxSweeps + 1]
+  size_t orth_ws_bytes;
+};
+
+}  // namespace hoqri
+
+struct hoqri_plan {
+  int32_t N;
+  int64_t dims[hoqri::kMaxOrder];
+  int32_t K[hoqri::kMaxOrder];
+  int64_t nnz_in;      // coordinates given
+  int64_t nnz;         // distinct coordinates after merging duplicates
+  double normx2;       // ||X||^2 (float64)
+  int32_t core_mode;   // mode whose sorted copy the core pass reads (fewest slices)
+  int32_t core_groups; // workgroups of the core pass (partials to reduce)
+  hoqri::ModeData md[hoqri::kMaxOrder];
+  hoqri::Scratch sc;
+  void* ws;
+  size_t ws_bytes;
+  int32_t device;
+};
+
+namespace hoqri {
+
+// Layout of the workspace for a shape (computed on the host; sort temporary
+// size needs the device). Offsets are 256-byte aligned.
+struct Layout {
+  size_t total;
+  size_t persistent;   // plan data that lives until destroy
+  size_t build_tmp;    // transient storage during plan creation
+  size_t run_scratch;  // scratch of the passes (overlaps build_tmp)
+  size_t sort_tmp;     // rocPRIM temporary storage
+  int32_t ranges[kMaxOrder];
+  int32_t core_groups;
+};
+
+hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L);
+hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz);
+
+// Segment-pass kernels (segpass_f32.hip).
+hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, double* f_out,
+                             hipStream_t s);
+hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, const float* G,
+                               float* A, hipStream_t s);
+bool segpass_supported(const hoqri_plan* p, int mode);
+
+// CholeskyQR2 (orth.hip).
+size_t orth_ws_bytes(int64_t rows, int32_t cols);
+hoqri_status launch_orth(int64_t rows, int32_t cols, const float* A, float* U, double* R,
+                         int32_t* status, void* ws, size_t ws_bytes, hipStream_t s, bool sticky);
+hoqri_status launch_orth_err(int64_t rows, int32_t cols, const float* U, double* err_out, void* ws,
+                             size_t ws_bytes, hipStream_t s);
+
+// Element offsets of the other modes of `mode` (ascending, mode skipped).
+inline int other_modes(int N, int mode, int* out) {
+  int c = 0;
+  for (int m = 0; m < N; ++m)
+    if (m != mode) out[c++] = m;
+  return c;
+}
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+}  // namespace hoqri

@@ -1,0 +1,613 @@
+// Plan construction: index validation, merging of duplicate coordinates,
+// ||X||^2, and for every mode n a copy of the nonzeros stably sorted by i_n
+// together with the table of nonempty index sets I^(n)_{i_n} (Table 1).
+//
+// Integer and sort dominated; runs once per tensor. Sorting uses rocPRIM's
+// stable radix sort; every other step is a small kernel of this file.
+#include <cstring>
+#include <cstdlib>
+#include <new>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "common.h"
+
+namespace hoqri {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int grid_for(int64_t n, int threads = kThreads, int cap = 65536) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+int bits_for(uint64_t max_value_exclusive) {
+  int b = 0;
+  while (b < 64 && (uint64_t(1) << b) < max_value_exclusive) ++b;
+  return b < 1 ? 1 : b;
+}
+
+struct KeyArgs {
+  const int32_t* idx;
+  int64_t nnz;
+  int32_t N;
+  int64_t dims[kMaxOrder];
+  uint64_t stride[kMaxOrder];
+};
+
+// Range check of every coordinate and the C-order linear key of each nonzero.
+__global__ void k_keys(KeyArgs a, uint64_t* keys, int32_t* pos, int32_t* err) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < a.nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t key = 0;
+    bool bad = false;
+    for (int m = 0; m < a.N; ++m) {
+      int32_t i = a.idx[(int64_t)m * a.nnz + e];
+      bad |= (i < 0) || ((int64_t)i >= a.dims[m]);
+      key += (uint64_t)(i < 0 ? 0 : i) * a.stride[m];
+    }
+    if (bad) atomicOr(err, 1);
+    keys[e] = key;
+    pos[e] = (int32_t)e;
+  }
+}
+
+template <typename T>
+__global__ void k_head_flags(const T* keys, int64_t n, int32_t* head) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    head[e] = (e == 0 || keys[e] != keys[e - 1]) ? 1 : 0;
+}
+
+__global__ void k_count(const int32_t* head, const int32_t* scan, int64_t n, int64_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)scan[n - 1] + head[n - 1];
+}
+
+struct CoalesceArgs {
+  const int32_t* idx;   // original coordinates [N][nnz_in]
+  const float* vals;    // original values
+  const uint64_t* keys; // sorted keys
+  const int32_t* pos;   // original position of each sorted key
+  const int32_t* head;
+  const int32_t* uid;
+  int64_t nnz_in;
+  int32_t N;
+  int32_t* cidx;        // [N][nnz_in] canonical coordinates (first nnz used)
+  float* cval;
+  double* vsq;
+};
+
+// One thread per run of equal keys: sums the run's values in sorted (= stable,
+// input) order in float64, writes the canonical coordinate and value.
+__global__ void k_coalesce(CoalesceArgs a) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < a.nnz_in;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (!a.head[e]) continue;
+    double v = a.vals[a.pos[e]];
+    for (int64_t f = e + 1; f < a.nnz_in && !a.head[f]; ++f) v += a.vals[a.pos[f]];
+    int64_t j = a.uid[e];
+    int32_t src = a.pos[e];
+    for (int m = 0; m < a.N; ++m) a.cidx[(int64_t)m * a.nnz_in + j] = a.idx[(int64_t)m * a.nnz_in + src];
+    float vf = (float)v;
+    a.cval[j] = vf;
+    a.vsq[j] = (double)vf * (double)vf;
+  }
+}
+
+// Deterministic float64 sum: per-block partials, then one block in order.
+__global__ void k_sum_partial(const double* x, const int64_t* n_dev, double* part) {
+  __shared__ double sh[kThreads];
+  int64_t n = *n_dev;
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    acc += x[e];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_final(const double* part, int nparts, double* out) {
+  __shared__ double sh[kThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ void k_mode_keys(const int32_t* cidx_n, int64_t nnz, uint32_t* k32, int32_t* perm) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    k32[j] = (uint32_t)cidx_n[j];
+    perm[j] = (int32_t)j;
+  }
+}
+
+struct GatherArgs {
+  const int32_t* cidx;   // [N][stride]
+  const float* cval;
+  const int32_t* perm;   // null = identity
+  int64_t stride, nnz;
+  int32_t N, mode;
+  int32_t K[kMaxOrder];
+  int32_t* oidx[kMaxOrder - 1];
+  float* val;
+  int32_t* modeidx;
+};
+
+// Mode-n sorted copy: other-mode factor offsets i_m * K_m, values, and i_n.
+__global__ void k_gather_mode(GatherArgs a) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < a.nnz;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t src = a.perm ? a.perm[j] : j;
+    int c = 0;
+    for (int m = 0; m < a.N; ++m) {
+      int32_t i = a.cidx[(int64_t)m * a.stride + src];
+      if (m == a.mode) {
+        a.modeidx[j] = i;
+      } else {
+        a.oidx[c++][j] = i * a.K[m];
+      }
+    }
+    a.val[j] = a.cval[src];
+  }
+}
+
+__global__ void k_segments(const int32_t* modeidx, const int32_t* head, const int32_t* sid, int64_t nnz,
+                           int32_t* seg_row, int32_t* seg_off, int64_t* R_out) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    if (head[j]) {
+      seg_row[sid[j]] = modeidx[j];
+      seg_off[sid[j]] = (int32_t)j;
+    }
+    if (j == nnz - 1) {
+      int64_t R = (int64_t)sid[j] + head[j];
+      seg_off[R] = (int32_t)nnz;
+      *R_out = R;
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* x, int64_t n, int32_t v) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    x[j] = v;
+}
+
+__global__ void k_mark_rows(const int32_t* seg_row, const int64_t* R_dev, int32_t* notempty_inv) {
+  int64_t R = *R_dev;
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < R;
+       s += (int64_t)gridDim.x * blockDim.x)
+    notempty_inv[seg_row[s]] = 0;  // array starts at 1 (= empty)
+}
+
+__global__ void k_empty_rows(const int32_t* is_empty, const int32_t* pos, int64_t In, int32_t* empty_row) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < In;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (is_empty[i]) empty_row[pos[i]] = (int32_t)i;
+}
+
+// Workspace carving ---------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+size_t sort_tmp_bytes(int64_t nnz, int64_t Imax, hipError_t* err) {
+  size_t b64 = 0, b32 = 0, bs = 0, bs2 = 0;
+  *err = rocprim::radix_sort_pairs(nullptr, b64, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
+                                   (int32_t*)nullptr, (size_t)nnz, 0, 64, (hipStream_t)0);
+  if (*err != hipSuccess) return 0;
+  *err = rocprim::radix_sort_pairs(nullptr, b32, (uint32_t*)nullptr, (uint32_t*)nullptr, (int32_t*)nullptr,
+                                   (int32_t*)nullptr, (size_t)nnz, 0, 32, (hipStream_t)0);
+  if (*err != hipSuccess) return 0;
+  *err = rocprim::exclusive_scan(nullptr, bs, (int32_t*)nullptr, (int32_t*)nullptr, 0, (size_t)nnz,
+                                 rocprim::plus<int32_t>(), (hipStream_t)0);
+  if (*err != hipSuccess) return 0;
+  *err = rocprim::exclusive_scan(nullptr, bs2, (int32_t*)nullptr, (int32_t*)nullptr, 0, (size_t)Imax,
+                                 rocprim::plus<int32_t>(), (hipStream_t)0);
+  if (*err != hipSuccess) return 0;
+  size_t m = b64;
+  if (b32 > m) m = b32;
+  if (bs > m) m = bs;
+  if (bs2 > m) m = bs2;
+  return align_up(m);
+}
+
+}  // namespace
+
+hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz) {
+  if (N < 2 || N > kMaxOrder || !dims || !K) return HOQRI_ERR_ARG;
+  if (nnz < 1 || nnz >= (int64_t(1) << 30)) return HOQRI_ERR_ARG;
+  for (int n = 0; n < N; ++n)
+    if (dims[n] < 1 || dims[n] >= (int64_t(1) << 31)) return HOQRI_ERR_ARG;
+  for (int n = 0; n < N; ++n) {
+    if (K[n] < 1 || K[n] > dims[n]) return HOQRI_ERR_RANK;
+    int64_t other = 1;
+    for (int m = 0; m < N; ++m)
+      if (m != n) other *= K[m];
+    if (K[n] > other) return HOQRI_ERR_RANK;
+    if (K[n] > kMaxRank) return HOQRI_ERR_UNSUPPORTED;
+    if (dims[n] * (int64_t)K[n] * 4 >= (int64_t(1) << 32)) return HOQRI_ERR_UNSUPPORTED;
+  }
+  return HOQRI_OK;
+}
+
+// Stage-two operand size (floats) of the TTMcTC pass on mode n and the core
+// partial size (floats) of the core pass on mode n; see segpass_f32.hip.
+static void pass_sizes(int32_t N, const int32_t* K, int n, size_t* gtop, size_t* gpart) {
+  int om[kMaxOrder];
+  int no = other_modes(N, n, om);
+  int64_t krow = 1;
+  for (int c = 0; c < no - 1; ++c) krow *= K[om[c]];
+  int64_t kcol = K[om[no - 1]];
+  int64_t RB = (krow + 15) / 16, CB = (kcol + 15) / 16;
+  int64_t B = RB * CB;
+  int64_t KN2 = (K[n] + 15) / 16;
+  *gtop = (size_t)(B * KN2 * 4096);
+  *gpart = (size_t)(B * 256 * 16 * KN2);
+}
+
+static int32_t choose_ranges(int64_t nnz) {
+  int64_t w = nnz / 3072;
+  if (w < 1) w = 1;
+  if (w > 16384) w = 16384;
+  return (int32_t)w;
+}
+
+static int32_t choose_core_groups(int64_t nnz, int64_t B) {
+  int64_t g = nnz / 16384;
+  int64_t cap = B >= 4 ? 256 : 512;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int32_t)g;
+}
+
+hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L) {
+  HOQRI_TRY(validate_shape(N, dims, K, nnz));
+  int64_t Imax = 0, IKmax = 0, PK = 1;
+  for (int n = 0; n < N; ++n) {
+    if (dims[n] > Imax) Imax = dims[n];
+    if (dims[n] * K[n] > IKmax) IKmax = dims[n] * K[n];
+    PK *= K[n];
+  }
+  hipError_t e;
+  size_t stmp = sort_tmp_bytes(nnz, Imax, &e);
+  if (e != hipSuccess) return HOQRI_ERR_HIP;
+
+  Carver c{nullptr, 0};
+  // persistent
+  for (int n = 0; n < N; ++n) {
+    for (int m = 0; m < N - 1; ++m) c.take<int32_t>(nnz);
+    c.take<float>(nnz);
+    int64_t rmax = dims[n] < nnz ? dims[n] : nnz;
+    c.take<int32_t>(rmax);
+    c.take<int32_t>(rmax + 1);
+    c.take<int32_t>(dims[n]);
+  }
+  size_t persistent = c.off;
+  // build temporaries
+  Carver b{nullptr, 0};
+  b.take<uint64_t>(nnz);
+  b.take<uint64_t>(nnz);
+  b.take<int32_t>(nnz);
+  b.take<int32_t>(nnz);
+  b.take<int32_t>(nnz);
+  b.take<int32_t>(nnz);
+  b.take<int32_t>((size_t)N * nnz);
+  b.take<float>(nnz);
+  b.take<double>(nnz);
+  b.take<int32_t>(nnz);
+  b.take<int32_t>(Imax);
+  b.take<int32_t>(Imax);
+  b.take<double>(65536);
+  b.take<int64_t>(64);
+  b.take<char>(stmp);
+  size_t build = b.off;
+  // run scratch
+  size_t gtop_max = 0, gpart = 0;
+  int64_t Bcore = 1;
+  for (int n = 0; n < N; ++n) {
+    size_t g1, g2;
+    pass_sizes(N, K, n, &g1, &g2);
+    if (g1 > gtop_max) gtop_max = g1;
+    if (g2 > gpart) gpart = g2;
+    int om[kMaxOrder];
+    int no = other_modes(N, n, om);
+    int64_t krow = 1;
+    for (int q = 0; q < no - 1; ++q) krow *= K[om[q]];
+    int64_t B = ((krow + 15) / 16) * ((K[om[no - 1]] + 15) / 16);
+    if (B > Bcore) Bcore = B;
+  }
+  int32_t groups = choose_core_groups(nnz, Bcore);
+  int32_t rmax = 0;
+  for (int n = 0; n < N; ++n) {
+    L->ranges[n] = choose_ranges(nnz);
+    if (L->ranges[n] > rmax) rmax = L->ranges[n];
+  }
+  L->core_groups = groups;
+  Carver r{nullptr, 0};
+  r.take<float>(IKmax);                 // A
+  r.take<float>(PK);                    // G
+  r.take<float>((size_t)groups * gpart);// core partials
+  r.take<double>(4096);                 // fpart
+  r.take<float>(gtop_max);              // stage-two operand
+  r.take<float>((size_t)rmax * 2 * 32); // carries
+  r.take<int32_t>((size_t)rmax * 4);    // range metadata
+  size_t ow = orth_ws_bytes(Imax, kMaxRank);
+  r.take<char>(ow);
+  r.take<int32_t>(64);                  // status
+  r.take<double>(64);                   // scalars
+  r.take<double>(kMaxSweeps + 1);       // f after each sweep
+  size_t run = r.off;
+  L->persistent = persistent;
+  L->build_tmp = build;
+  L->run_scratch = run;
+  L->sort_tmp = stmp;
+  L->total = persistent + (build > run ? build : run);
+  return HOQRI_OK;
+}
+
+}  // namespace hoqri
+
+using namespace hoqri;
+
+extern "C" hoqri_status hoqri_plan_workspace_size(int32_t order, const int64_t* dims, const int32_t* ranks,
+                                                  int64_t nnz, size_t* bytes) {
+  if (!bytes) return HOQRI_ERR_ARG;
+  Layout L;
+  HOQRI_TRY(compute_layout(order, dims, ranks, nnz, &L));
+  *bytes = L.total;
+  return HOQRI_OK;
+}
+
+static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float* d_vals, hipStream_t s,
+                               const Layout& L) {
+  const int N = p->N;
+  const int64_t nnz_in = p->nnz_in;
+  int64_t Imax = 0;
+  for (int n = 0; n < N; ++n)
+    if (p->dims[n] > Imax) Imax = p->dims[n];
+
+  // persistent region
+  Carver c{(char*)p->ws, 0};
+  for (int n = 0; n < N; ++n) {
+    ModeData& md = p->md[n];
+    for (int m = 0; m < N - 1; ++m) md.oidx[m] = c.take<int32_t>(nnz_in);
+    md.val = c.take<float>(nnz_in);
+    int64_t rmax = p->dims[n] < nnz_in ? p->dims[n] : nnz_in;
+    md.seg_row = c.take<int32_t>(rmax);
+    md.seg_off = c.take<int32_t>(rmax + 1);
+    md.empty_row = c.take<int32_t>(p->dims[n]);
+  }
+  // build temporaries (after the persistent region)
+  Carver b{(char*)p->ws + L.persistent, 0};
+  uint64_t* keys = b.take<uint64_t>(nnz_in);
+  uint64_t* keys_s = b.take<uint64_t>(nnz_in);
+  int32_t* pos = b.take<int32_t>(nnz_in);
+  int32_t* pos_s = b.take<int32_t>(nnz_in);
+  int32_t* head = b.take<int32_t>(nnz_in);
+  int32_t* uid = b.take<int32_t>(nnz_in);
+  int32_t* cidx = b.take<int32_t>((size_t)N * nnz_in);
+  float* cval = b.take<float>(nnz_in);
+  double* vsq = b.take<double>(nnz_in);
+  int32_t* modeidx = b.take<int32_t>(nnz_in);
+  int32_t* flag_i = b.take<int32_t>(Imax);
+  int32_t* scan_i = b.take<int32_t>(Imax);
+  double* dpart = b.take<double>(65536);
+  int64_t* small = b.take<int64_t>(64);
+  void* stmp = b.take<char>(L.sort_tmp);
+  int32_t* err = (int32_t*)(small + 32);
+
+  // 1. keys + range check
+  KeyArgs ka{};
+  ka.idx = d_idx;
+  ka.nnz = nnz_in;
+  ka.N = N;
+  uint64_t stride = 1;
+  for (int m = N - 1; m >= 0; --m) {
+    ka.dims[m] = p->dims[m];
+    ka.stride[m] = stride;
+    stride *= (uint64_t)p->dims[m];
+  }
+  HOQRI_HIP_TRY(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+  k_keys<<<grid_for(nnz_in), kThreads, 0, s>>>(ka, keys, pos, err);
+  HOQRI_HIP_TRY(hipGetLastError());
+  int32_t herr = 0;
+  HOQRI_HIP_TRY(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HOQRI_HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return HOQRI_ERR_INDEX;
+
+  // 2. sort by linear key (stable), merge duplicates
+  size_t tb = L.sort_tmp;
+  int keybits = bits_for(stride);
+  HOQRI_HIP_TRY(rocprim::radix_sort_pairs(stmp, tb, keys, keys_s, pos, pos_s, (size_t)nnz_in, 0, keybits, s));
+  k_head_flags<<<grid_for(nnz_in), kThreads, 0, s>>>(keys_s, nnz_in, head);
+  tb = L.sort_tmp;
+  HOQRI_HIP_TRY(rocprim::exclusive_scan(stmp, tb, head, uid, 0, (size_t)nnz_in, rocprim::plus<int32_t>(), s));
+  k_count<<<1, 1, 0, s>>>(head, uid, nnz_in, small);
+  CoalesceArgs ca{d_idx, d_vals, keys_s, pos_s, head, uid, nnz_in, N, cidx, cval, vsq};
+  k_coalesce<<<grid_for(nnz_in), kThreads, 0, s>>>(ca);
+  int np = grid_for(nnz_in, kThreads, 1024);
+  k_sum_partial<<<np, kThreads, 0, s>>>(vsq, small, dpart);
+  k_sum_final<<<1, kThreads, 0, s>>>(dpart, np, (double*)(small + 1));
+  HOQRI_HIP_TRY(hipGetLastError());
+  int64_t hsmall[2];
+  HOQRI_HIP_TRY(hipMemcpyAsync(hsmall, small, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HOQRI_HIP_TRY(hipStreamSynchronize(s));
+  const int64_t nnz = hsmall[0];
+  double nx2;
+  std::memcpy(&nx2, &hsmall[1], sizeof(double));
+  p->nnz = nnz;
+  p->normx2 = nx2;
+
+  // 3. per mode: stable sort by i_n, sorted copy, slice table, empty rows
+  uint32_t* k32 = reinterpret_cast<uint32_t*>(keys);
+  uint32_t* k32s = reinterpret_cast<uint32_t*>(keys_s);
+  for (int n = 0; n < N; ++n) {
+    ModeData& md = p->md[n];
+    const int32_t* perm = nullptr;
+    if (n > 0) {  // canonical order is already sorted by mode 0
+      k_mode_keys<<<grid_for(nnz), kThreads, 0, s>>>(cidx + (int64_t)n * nnz_in, nnz, k32, pos);
+      tb = L.sort_tmp;
+      HOQRI_HIP_TRY(rocprim::radix_sort_pairs(stmp, tb, k32, k32s, pos, pos_s, (size_t)nnz, 0,
+                                              bits_for((uint64_t)p->dims[n]), s));
+      perm = pos_s;
+    }
+    GatherArgs ga{};
+    ga.cidx = cidx;
+    ga.cval = cval;
+    ga.perm = perm;
+    ga.stride = nnz_in;
+    ga.nnz = nnz;
+    ga.N = N;
+    ga.mode = n;
+    for (int m = 0; m < N; ++m) ga.K[m] = p->K[m];
+    for (int m = 0; m < N - 1; ++m) ga.oidx[m] = md.oidx[m];
+    ga.val = md.val;
+    ga.modeidx = modeidx;
+    k_gather_mode<<<grid_for(nnz), kThreads, 0, s>>>(ga);
+    k_head_flags<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, nnz, head);
+    tb = L.sort_tmp;
+    HOQRI_HIP_TRY(rocprim::exclusive_scan(stmp, tb, head, uid, 0, (size_t)nnz, rocprim::plus<int32_t>(), s));
+    k_segments<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, head, uid, nnz, md.seg_row, md.seg_off,
+                                                    small + 2 + n);
+    k_fill_i32<<<grid_for(p->dims[n]), kThreads, 0, s>>>(flag_i, p->dims[n], 1);
+    k_mark_rows<<<grid_for(nnz), kThreads, 0, s>>>(md.seg_row, small + 2 + n, flag_i);
+    tb = L.sort_tmp;
+    HOQRI_HIP_TRY(rocprim::exclusive_scan(stmp, tb, flag_i, scan_i, 0, (size_t)p->dims[n],
+                                          rocprim::plus<int32_t>(), s));
+    k_empty_rows<<<grid_for(p->dims[n]), kThreads, 0, s>>>(flag_i, scan_i, p->dims[n], md.empty_row);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+  int64_t Rh[kMaxOrder];
+  HOQRI_HIP_TRY(hipMemcpyAsync(Rh, small + 2, N * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HOQRI_HIP_TRY(hipStreamSynchronize(s));
+  int best = 0;
+  double best_cost = 0;
+  for (int n = 0; n < N; ++n) {
+    p->md[n].R = Rh[n];
+    p->md[n].E = p->dims[n] - Rh[n];
+    p->md[n].ranges = L.ranges[n];
+    // core pass cost on mode n ~ nnz / K_n + R_n (per unit prod K)
+    double cost = (double)nnz / p->K[n] + (double)Rh[n];
+    if (n == 0 || cost < best_cost) {
+      best = n;
+      best_cost = cost;
+    }
+  }
+  p->core_mode = best;
+  p->core_groups = L.core_groups;
+  return HOQRI_OK;
+}
+
+static void carve_scratch(hoqri_plan* p, const Layout& L) {
+  int64_t IKmax = 0, PK = 1, Imax = 0;
+  for (int n = 0; n < p->N; ++n) {
+    if (p->dims[n] * p->K[n] > IKmax) IKmax = p->dims[n] * p->K[n];
+    if (p->dims[n] > Imax) Imax = p->dims[n];
+    PK *= p->K[n];
+  }
+  size_t gtop_max = 0, gpart = 0;
+  for (int n = 0; n < p->N; ++n) {
+    size_t g1, g2;
+    pass_sizes(p->N, p->K, n, &g1, &g2);
+    if (g1 > gtop_max) gtop_max = g1;
+    if (g2 > gpart) gpart = g2;
+  }
+  int32_t rmax = 0;
+  for (int n = 0; n < p->N; ++n)
+    if (L.ranges[n] > rmax) rmax = L.ranges[n];
+  Carver r{(char*)p->ws + L.persistent, 0};
+  p->sc.A = r.take<float>(IKmax);
+  p->sc.G = r.take<float>(PK);
+  p->sc.gpart = r.take<float>((size_t)L.core_groups * gpart);
+  p->sc.fpart = r.take<double>(4096);
+  p->sc.gtop = r.take<float>(gtop_max);
+  p->sc.carry = r.take<float>((size_t)rmax * 2 * 32);
+  p->sc.meta = r.take<int32_t>((size_t)rmax * 4);
+  size_t ow = orth_ws_bytes(Imax, kMaxRank);
+  p->sc.orth_ws = (double*)r.take<char>(ow);
+  p->sc.orth_ws_bytes = ow;
+  p->sc.status = r.take<int32_t>(64);
+  p->sc.f_dev = r.take<double>(64);
+  p->sc.fsweep = r.take<double>(kMaxSweeps + 1);
+}
+
+extern "C" hoqri_status hoqri_plan_create(hoqri_plan** plan, int32_t order, const int64_t* dims,
+                                          const int32_t* ranks, int64_t nnz, const int32_t* d_idx,
+                                          const float* d_vals, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (!plan || !dims || !ranks || !d_idx || !d_vals || !d_ws) return HOQRI_ERR_ARG;
+  *plan = nullptr;
+  Layout L;
+  HOQRI_TRY(compute_layout(order, dims, ranks, nnz, &L));
+  if (ws_bytes < L.total) return HOQRI_ERR_NOMEM;
+  hoqri_plan* p = new (std::nothrow) hoqri_plan();
+  if (!p) return HOQRI_ERR_NOMEM;
+  p->N = order;
+  for (int n = 0; n < order; ++n) {
+    p->dims[n] = dims[n];
+    p->K[n] = ranks[n];
+  }
+  p->nnz_in = nnz;
+  p->ws = d_ws;
+  p->ws_bytes = ws_bytes;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return HOQRI_ERR_HIP;
+  }
+  hoqri_status st = build_plan(p, d_idx, d_vals, stream, L);
+  if (st != HOQRI_OK) {
+    delete p;
+    return st;
+  }
+  carve_scratch(p, L);
+  *plan = p;
+  return HOQRI_OK;
+}
+
+extern "C" hoqri_status hoqri_plan_info(const hoqri_plan* p, int64_t* nnz_coalesced, double* norm_x2,
+                                        int64_t* R) {
+  if (!p) return HOQRI_ERR_ARG;
+  if (nnz_coalesced) *nnz_coalesced = p->nnz;
+  if (norm_x2) *norm_x2 = p->normx2;
+  if (R)
+    for (int n = 0; n < p->N; ++n) R[n] = p->md[n].R;
+  return HOQRI_OK;
+}
+
+extern "C" void hoqri_plan_destroy(hoqri_plan* p) { delete p; }
+
+extern "C" const char* hoqri_status_string(hoqri_status s) {
+  switch (s) {
+    case HOQRI_OK: return "ok";
+    case HOQRI_ERR_ARG: return "invalid argument";
+    case HOQRI_ERR_INDEX: return "coordinate out of range";
+    case HOQRI_ERR_RANK: return "invalid rank";
+    case HOQRI_ERR_BREAKDOWN: return "rank-deficient update (Cholesky breakdown)";
+    case HOQRI_ERR_NOMEM: return "workspace too small";
+    case HOQRI_ERR_HIP: return "HIP runtime error";
+    case HOQRI_ERR_UNSUPPORTED: return "shape not supported";
+  }
+  return "unknown status";
+}

@@ -1,0 +1,149 @@
+// Public entry points for the core, TTMcTC and the HOQRI loop (Alg. 2).
+//
+// One sweep = one HOQRI iteration: for n = 1..N, the core G from the current
+// factors (first line of Alg. 3), A^(n) = TTMcTC(X, {U}, n), U^(n) = an
+// orthonormal basis of A^(n). Factors updated earlier in the sweep are used by
+// later modes (the single-mode update rule of §5). The core computed after the
+// last mode of a sweep is reused as the first core of the next sweep, so f
+// after every sweep is known without an extra pass, and the core returned at
+// the end belongs to the returned factors (last line of Alg. 2).
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace hoqri {
+namespace {
+
+__global__ void k_fill_i32(int32_t* x, int n, int32_t v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = v;
+}
+
+// hist[t * N + 0] = fsweep[t] for t < T (the first mode of each sweep sees the
+// core of the previous sweep's end).
+__global__ void k_hist_first(const double* fsweep, int T, int N, double* hist) {
+  for (int t = threadIdx.x; t < T; t += blockDim.x) hist[(size_t)t * N] = fsweep[t];
+}
+
+hoqri_status check_plan(const hoqri_plan* p) {
+  if (!p) return HOQRI_ERR_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HOQRI_ERR_HIP;
+  if (dev != p->device) return HOQRI_ERR_ARG;
+  return HOQRI_OK;
+}
+
+hoqri_status check_prec(hoqri_prec prec) {
+  if (prec == HOQRI_FP32) return HOQRI_OK;
+  if (prec == HOQRI_BF16 || prec == HOQRI_FP16) return HOQRI_ERR_UNSUPPORTED;
+  return HOQRI_ERR_ARG;
+}
+
+}  // namespace
+}  // namespace hoqri
+
+using namespace hoqri;
+
+extern "C" hoqri_status hoqri_core(hoqri_plan* p, const float* const* d_U, float* d_G, double* d_f, hoqri_prec prec,
+                                   hipStream_t stream) {
+  HOQRI_TRY(check_plan(p));
+  if (!d_U || !d_G) return HOQRI_ERR_ARG;
+  for (int n = 0; n < p->N; ++n)
+    if (!d_U[n]) return HOQRI_ERR_ARG;
+  HOQRI_TRY(check_prec(prec));
+  return launch_core_f32(p, d_U, d_G, d_f, stream);
+}
+
+extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* const* d_U, const float* d_G,
+                                     float* d_A, hoqri_prec prec, hipStream_t stream) {
+  HOQRI_TRY(check_plan(p));
+  if (mode < 0 || mode >= p->N || !d_U || !d_G || !d_A) return HOQRI_ERR_ARG;
+  for (int n = 0; n < p->N; ++n)
+    if (!d_U[n]) return HOQRI_ERR_ARG;
+  HOQRI_TRY(check_prec(prec));
+  return launch_ttmctc_f32(p, mode, d_U, d_G, d_A, stream);
+}
+
+extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
+                                  const hoqri_run_opts* opts, hoqri_run_stats* stats, hipStream_t stream) {
+  HOQRI_TRY(check_plan(p));
+  if (!d_U_inout || !d_G_out || !opts || !stats) return HOQRI_ERR_ARG;
+  for (int n = 0; n < p->N; ++n)
+    if (!d_U_inout[n]) return HOQRI_ERR_ARG;
+  if (opts->max_sweeps < 0 || opts->max_sweeps > kMaxSweeps || opts->check_every < 1 || !(opts->tol >= 0.0))
+    return HOQRI_ERR_ARG;
+  HOQRI_TRY(check_prec(opts->prec));
+  for (int n = 0; n < p->N; ++n)
+    if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
+
+  const int N = p->N;
+  const float* const* U = d_U_inout;
+  int32_t* status = p->sc.status;
+  double* fsw = p->sc.fsweep;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, status, 4, 0);
+  HOQRI_HIP_TRY(hipGetLastError());
+
+  if (opts->orthonormalize_input) {
+    for (int n = 0; n < N; ++n)
+      HOQRI_TRY(launch_orth(p->dims[n], p->K[n], d_U_inout[n], d_U_inout[n], nullptr, status, p->sc.orth_ws,
+                            p->sc.orth_ws_bytes, stream, true));
+  }
+  // core of the starting factors
+  HOQRI_TRY(launch_core_f32(p, U, d_G_out, fsw + 0, stream));
+
+  int T = 0;
+  double f_last = 0.0, f_prev = 0.0, rel = 0.0;
+  bool have_prev = false;
+  for (int t = 0; t < opts->max_sweeps; ++t) {
+    for (int n = 0; n < N; ++n) {
+      if (n > 0) {
+        double* fdst = d_f_hist ? d_f_hist + (size_t)t * N + n : p->sc.f_dev;
+        HOQRI_TRY(launch_core_f32(p, U, d_G_out, fdst, stream));
+      }
+      HOQRI_TRY(launch_ttmctc_f32(p, n, U, d_G_out, p->sc.A, stream));
+      HOQRI_TRY(launch_orth(p->dims[n], p->K[n], p->sc.A, d_U_inout[n], nullptr, status, p->sc.orth_ws,
+                            p->sc.orth_ws_bytes, stream, true));
+    }
+    HOQRI_TRY(launch_core_f32(p, U, d_G_out, fsw + t + 1, stream));
+    T = t + 1;
+    if (T % opts->check_every == 0 || T == opts->max_sweeps) {
+      double fv[2];
+      int32_t st = 0;
+      HOQRI_HIP_TRY(hipMemcpyAsync(fv, fsw + T - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+      HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HOQRI_HIP_TRY(hipStreamSynchronize(stream));
+      if (st != 0) return HOQRI_ERR_BREAKDOWN;
+      f_prev = fv[0];
+      f_last = fv[1];
+      have_prev = true;
+      rel = f_last > 0 ? std::fabs(f_last - f_prev) / f_last : 0.0;
+      if (opts->tol > 0.0 && std::fabs(f_last - f_prev) <= opts->tol * f_last) break;
+    }
+  }
+  if (d_f_hist && T > 0) {
+    hipLaunchKernelGGL(k_hist_first, dim3(1), dim3(256), 0, stream, fsw, T, N, d_f_hist);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+  // final statistics
+  double errs[kMaxOrder] = {0, 0, 0, 0};
+  for (int n = 0; n < N; ++n)
+    HOQRI_TRY(launch_orth_err(p->dims[n], p->K[n], d_U_inout[n], p->sc.f_dev + 8 + n, p->sc.orth_ws,
+                              p->sc.orth_ws_bytes, stream));
+  double fend = 0.0;
+  int32_t st = 0;
+  HOQRI_HIP_TRY(hipMemcpyAsync(errs, p->sc.f_dev + 8, N * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HOQRI_HIP_TRY(hipMemcpyAsync(&fend, fsw + T, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HOQRI_HIP_TRY(hipStreamSynchronize(stream));
+  if (st != 0) return HOQRI_ERR_BREAKDOWN;
+  (void)have_prev;
+  stats->sweeps = T;
+  stats->norm_x2 = p->normx2;
+  stats->f = fend;
+  stats->fit = 1.0 - std::sqrt(std::fmax(p->normx2 - fend, 0.0)) / std::sqrt(p->normx2);
+  stats->rel_change = rel;
+  double emax = 0.0;
+  for (int n = 0; n < N; ++n) emax = std::fmax(emax, errs[n]);
+  stats->orth_err_max = emax;
+  return HOQRI_OK;
+}

@@ -1,0 +1,725 @@
+// Segment passes for TTMcTC and the core, float32 operands on the gfx950
+// float32 matrix cores (v_mfma_f32_16x16x4f32), float32 accumulation.
+//
+// Both passes walk a copy of the nonzeros sorted by one mode n and, for every
+// nonempty slice i (the index set I^(n)_i of Table 1), form
+//     y_i = sum over nonzeros e of slice i of  x_e * (Kronecker over m != n of U^(m)(i_m^e, :)),
+// the i-th row of Y_(n) with Y = X x_{-n} {U^T} (§4.1), without storing Y.
+// Viewed as a matrix Y_i (rows: the Kronecker product of the first N-2 other
+// modes, columns: the last other mode), Y_i = sum_e (x_e u_row^e)(u_col^e)^T is a
+// product whose inner dimension is the slice's nonzeros, so it maps onto the
+// matrix cores with 4 nonzeros per instruction: each group of 16 lanes gathers
+// one nonzero's factor rows, row-contiguous (64 bytes per factor row at K=16).
+//
+//  - TTMcTC pass (mode n): A^(n)(i, :) = y_i G_(n)^T (definition in §4.1).
+//    Finished y_i are staged in LDS, 16 slices at a time, and multiplied by
+//    G_(n)^T on the matrix cores (the operand is kept in registers).
+//  - Core pass (mode c): G_(c) = sum_i U^(c)(i, :)^T y_i, i.e. G = X x {U^T}
+//    (§2.2) grouped by slices of mode c; run on the mode with the fewest
+//    slices, so the per-slice outer product is negligible.
+//
+// Work split: the sorted nonzeros of a mode are cut into W contiguous ranges
+// of equal nonzero count; slices crossing a range boundary produce partial
+// rows that a fix-up kernel adds in range order. Every sum has a fixed order,
+// so results are bitwise reproducible. Y_i may span several 16x16 blocks
+// (rows > 16 or columns > 16); then each block is handled by its own wave of
+// the workgroup and the TTMcTC partial products are added in LDS.
+#include "common.h"
+
+namespace hoqri {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
+constexpr int YS = 260;                      // LDS floats per staged y_i block (256 + pad)
+constexpr int KIND_COMPLETE = 0, KIND_HEAD = 1, KIND_TAIL = 2;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+// Raw buffer loads: an offset at or beyond the buffer size returns 0.
+__device__ inline float ld_f(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline int32_t ld_i(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ inline i4 ld_i4(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0);
+}
+
+// Orders this wave's LDS writes before its later LDS reads (no cross-wave sync).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+struct SegArgs {
+  const int32_t* oidx[3];   // other-mode element offsets (i_m * K_m), mode-sorted
+  const float* val;
+  const int32_t* seg_off;   // [R+1]
+  const int32_t* seg_row;   // [R]
+  int32_t R;
+  int32_t nnz;
+  int32_t W;                // ranges
+  int32_t B, RB, CB;        // y_i blocks (16x16) per range, as RB x CB
+  int32_t RPW;              // ranges per workgroup
+  const float* U[3];        // factors of the other modes, ascending
+  uint32_t Ubytes[3];
+  int32_t K1;               // rank of the second other mode (row split for N = 4)
+  // TTMcTC
+  const float* gtop;        // stage-two operand [B][KN2][64][64]
+  float* A;
+  int32_t Kn;
+  float* carry;             // [W][2][32]
+  int32_t* meta;            // [W][4]
+  // core
+  const float* Uc;          // factor of the pass mode
+  int32_t Kc;
+  float* gpart;             // [groups][B][16*KN2][256]
+};
+
+__device__ inline int32_t range_lo(int64_t w, int64_t W, int64_t nnz) { return (int32_t)((w * nnz) / W); }
+
+// Largest s in [0, R] with seg_off[s] <= e (seg_off[0] = 0 <= e).
+__device__ inline int32_t find_seg(const int32_t* seg_off, int32_t R, int32_t e) {
+  int32_t lo = 0, hi = R;  // invariant: seg_off[lo] <= e < seg_off[hi] (seg_off[R] = nnz > e)
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    if (seg_off[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Accumulates this wave's 16x16 block of y_i over nonzeros [lo, hi) of the
+// sorted stream. Lane (g = lane/16, q = lane%16) supplies A[q][g] and B[g][q]
+// of each 16x16x4 product; the result D[4g+v][q] is returned in acc[v].
+template <int NM1>
+__device__ inline f4 accumulate_block(const SegArgs& a, __amdgpu_buffer_rsrc_t rI0, __amdgpu_buffer_rsrc_t rI1,
+                                      __amdgpu_buffer_rsrc_t rI2, __amdgpu_buffer_rsrc_t rX,
+                                      __amdgpu_buffer_rsrc_t rU0, __amdgpu_buffer_rsrc_t rU1,
+                                      __amdgpu_buffer_rsrc_t rU2, uint32_t ka4, uint32_t kb4, uint32_t kc4,
+                                      int32_t lo, int32_t hi, int g) {
+  f4 tot = {0.f, 0.f, 0.f, 0.f};
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  // the bounds are wave-uniform; say so, so the loads take scalar offsets
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  int32_t e0 = lo;
+  int inner = 0;
+  const uint32_t goff = (uint32_t)g * 16u;
+  // bulk: 16 nonzeros per step, group g takes e0+4g .. e0+4g+3
+  for (; e0 + 16 <= hi; e0 += 16) {
+    const uint32_t so = (uint32_t)e0 * 4u;
+    // (bit-cast the whole vector: a bit-cast of one element reads element 0)
+    const f4 xv = __builtin_bit_cast(f4, ld_i4(rX, goff, so));
+    i4 i0 = ld_i4(rI0, goff, so);
+    i4 i1 = (NM1 >= 2) ? ld_i4(rI1, goff, so) : i4{0, 0, 0, 0};
+    i4 i2 = (NM1 >= 3) ? ld_i4(rI2, goff, so) : i4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float x = xv[s];
+      float av, bv;
+      if constexpr (NM1 == 1) {
+        av = x;
+        bv = ld_f(rU0, ((uint32_t)i0[s] << 2) + kc4);
+      } else if constexpr (NM1 == 2) {
+        av = x * ld_f(rU0, ((uint32_t)i0[s] << 2) + ka4);
+        bv = ld_f(rU1, ((uint32_t)i1[s] << 2) + kc4);
+      } else {
+        av = x * ld_f(rU0, ((uint32_t)i0[s] << 2) + ka4) * ld_f(rU1, ((uint32_t)i1[s] << 2) + kb4);
+        bv = ld_f(rU2, ((uint32_t)i2[s] << 2) + kc4);
+      }
+      acc = mfma4(av, bv, acc);
+    }
+    if (++inner == 16) {
+      tot += acc;
+      acc = f4{0.f, 0.f, 0.f, 0.f};
+      inner = 0;
+    }
+  }
+  // tail: 4 nonzeros per step, group g takes e0+g
+  for (; e0 < hi; e0 += 4) {
+    const int32_t e = e0 + g;
+    const uint32_t off = (uint32_t)e * 4u;
+    float x = __builtin_bit_cast(float, ld_i(rX, off));
+    x = (e < hi) ? x : 0.f;
+    int32_t j0 = ld_i(rI0, off);
+    float av, bv;
+    if constexpr (NM1 == 1) {
+      av = x;
+      bv = ld_f(rU0, ((uint32_t)j0 << 2) + kc4);
+    } else if constexpr (NM1 == 2) {
+      int32_t j1 = ld_i(rI1, off);
+      av = x * ld_f(rU0, ((uint32_t)j0 << 2) + ka4);
+      bv = ld_f(rU1, ((uint32_t)j1 << 2) + kc4);
+    } else {
+      int32_t j1 = ld_i(rI1, off);
+      int32_t j2 = ld_i(rI2, off);
+      av = x * ld_f(rU0, ((uint32_t)j0 << 2) + ka4) * ld_f(rU1, ((uint32_t)j1 << 2) + kb4);
+      bv = ld_f(rU2, ((uint32_t)j2 << 2) + kc4);
+    }
+    acc = mfma4(av, bv, acc);
+  }
+  return tot + acc;
+}
+
+// Per-lane byte offsets of this lane's row / column inside the gathered factor
+// rows, for block (rb, cb). Padded rows/columns read finite neighbouring data
+// (or 0 beyond the buffer); their products land in padded entries of y_i that
+// the stage-two operand zeroes and the core pass never stores.
+template <int NM1>
+__device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uint32_t* ka4, uint32_t* kb4,
+                                    uint32_t* kc4) {
+  const int r = 16 * rb + q;
+  const int c = 16 * cb + q;
+  if constexpr (NM1 == 3) {
+    *ka4 = (uint32_t)(r / a.K1) * 4u;
+    *kb4 = (uint32_t)(r % a.K1) * 4u;
+  } else {
+    *ka4 = (uint32_t)r * 4u;
+    *kb4 = 0;
+  }
+  *kc4 = (uint32_t)c * 4u;
+}
+
+// ---------------------------------------------------------------------------
+// TTMcTC pass
+// ---------------------------------------------------------------------------
+template <int NM1, int KN2>
+__global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rr = wv / a.B;
+  const int b = wv - rr * a.B;
+  const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
+  const int g = lane >> 4, q = lane & 15;
+  const int32_t w = blockIdx.x * a.RPW + rr;
+  const bool active = w < a.W;
+
+  float* ybat = lds + wv * (16 * YS);
+  float* red = lds + a.B * a.RPW * 16 * YS + rr * (a.B * KN2 * 256);
+  int32_t* slot_row = reinterpret_cast<int32_t*>(lds + a.B * a.RPW * 16 * YS + a.RPW * a.B * KN2 * 256) + rr * 32;
+  int32_t* slot_kind = slot_row + 16;
+
+  // stage-two operand of this block: gt[kb][t] = G_(n)^T[64 g + t][16 kb + q]
+  float gt[KN2][64];
+#pragma unroll
+  for (int kb = 0; kb < KN2; ++kb)
+#pragma unroll
+    for (int t = 0; t < 64; ++t) gt[kb][t] = a.gtop[(((size_t)b * KN2 + kb) * 64 + t) * 64 + lane];
+
+  const uint32_t nb = (uint32_t)a.nnz * 4u;
+  auto rI0 = make_rsrc(a.oidx[0], nb);
+  auto rI1 = make_rsrc(a.oidx[1], NM1 >= 2 ? nb : 0u);
+  auto rI2 = make_rsrc(a.oidx[2], NM1 >= 3 ? nb : 0u);
+  auto rX = make_rsrc(a.val, nb);
+  auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
+  auto rU1 = make_rsrc(a.U[1], NM1 >= 2 ? a.Ubytes[1] : 0u);
+  auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
+  uint32_t ka4, kb4, kc4;
+  lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
+
+  int32_t lo = 0, hi = 0, s_first = 0, s_last = -1;
+  bool head_clip = false, tail_clip = false;
+  if (active) {
+    lo = range_lo(w, a.W, a.nnz);
+    hi = range_lo(w + 1, a.W, a.nnz);
+    s_first = find_seg(a.seg_off, a.R, lo);
+    s_last = find_seg(a.seg_off, a.R, hi - 1);
+    head_clip = a.seg_off[s_first] < lo;
+    tail_clip = a.seg_off[s_last + 1] > hi;
+    if (b == 0 && lane == 0) {
+      a.meta[w * 4 + 0] = s_first;
+      a.meta[w * 4 + 1] = s_last;
+      a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
+      a.meta[w * 4 + 3] = 0;
+    }
+  }
+  const bool multi = a.B > 1;
+  int slot = 0;
+  for (int32_t s = s_first; s <= s_last; ++s) {
+    const int32_t so = a.seg_off[s], se = a.seg_off[s + 1];
+    const int32_t slo = so > lo ? so : lo;
+    const int32_t shi = se < hi ? se : hi;
+    f4 y = accumulate_block<NM1>(a, rI0, rI1, rI2, rX, rU0, rU1, rU2, ka4, kb4, kc4, slo, shi, g);
+    // stage y_i (column-major within the block: j' = c*16 + r)
+    *reinterpret_cast<f4*>(ybat + slot * YS + q * 16 + 4 * g) = y;
+    if (b == 0 && lane == 0) {
+      int kind = KIND_COMPLETE;
+      if (s == s_first && head_clip) kind = KIND_HEAD;
+      else if (s == s_last && tail_clip) kind = KIND_TAIL;
+      slot_row[slot] = a.seg_row[s];
+      slot_kind[slot] = kind;
+    }
+    ++slot;
+    if (slot == 16 || s == s_last) {
+      // stage two: D[slot][kn] = sum_j' ybat[slot][j'] * G_(n)^T[j'][kn]
+      if (!multi) wave_sync();
+      f4 d[KN2];
+#pragma unroll
+      for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        f4 yv = *reinterpret_cast<const f4*>(ybat + q * YS + 64 * g + 4 * u);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int kb = 0; kb < KN2; ++kb) d[kb] = mfma4(yv[v], gt[kb][4 * u + v], d[kb]);
+      }
+      if (multi) {
+#pragma unroll
+        for (int kb = 0; kb < KN2; ++kb)
+          *reinterpret_cast<f4*>(red + (b * KN2 + kb) * 256 + q * 16 + 4 * g) = d[kb];
+        __syncthreads();
+        if (b == 0) {
+#pragma unroll
+          for (int kb = 0; kb < KN2; ++kb) {
+            f4 t = *reinterpret_cast<const f4*>(red + kb * 256 + q * 16 + 4 * g);
+            for (int bb = 1; bb < a.B; ++bb) t += *reinterpret_cast<const f4*>(red + (bb * KN2 + kb) * 256 + q * 16 + 4 * g);
+            d[kb] = t;
+          }
+        }
+      }
+      if (b == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int sl = 4 * g + v;
+          if (sl < slot) {
+            const int32_t row = slot_row[sl];
+            const int kind = slot_kind[sl];
+#pragma unroll
+            for (int kb = 0; kb < KN2; ++kb) {
+              const int kn = 16 * kb + q;
+              if (kn < a.Kn) {
+                const float val = d[kb][v];
+                if (kind == KIND_COMPLETE) a.A[(size_t)row * a.Kn + kn] = val;
+                else a.carry[((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
+              }
+            }
+          }
+        }
+      }
+      if (multi) __syncthreads();
+      else wave_sync();
+      slot = 0;
+    }
+  }
+}
+
+// Adds the partial rows of slices that cross range boundaries, in range order
+// (float64), and writes them. One wave per range; the owner is the range where
+// the slice starts (its tail partial), continued by the head partials of the
+// following ranges.
+__global__ void k_fix_split(const int32_t* meta, const float* carry, const int32_t* seg_row, int32_t W, int32_t Kn,
+                            float* A) {
+  const int lane = threadIdx.x & 63;
+  const int32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= W) return;
+  const int32_t s_first = meta[w * 4 + 0], s_last = meta[w * 4 + 1], flags = meta[w * 4 + 2];
+  const bool head_clip = flags & 1, tail_clip = flags & 2;
+  // does this range hold the first part (tail partial) of a split slice?
+  const bool owner = tail_clip && !(s_first == s_last && head_clip);
+  if (!owner) return;
+  const int32_t s = s_last;
+  double acc = lane < Kn ? (double)carry[((size_t)w * 2 + 1) * 32 + lane] : 0.0;
+  for (int32_t w2 = w + 1; w2 < W; ++w2) {
+    if (meta[w2 * 4 + 0] != s || !(meta[w2 * 4 + 2] & 1)) break;
+    if (lane < Kn) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + lane];
+  }
+  if (lane < Kn) A[(size_t)seg_row[s] * Kn + lane] = (float)acc;
+}
+
+__global__ void k_zero_rows(const int32_t* empty_row, int64_t E, int32_t Kn, float* A) {
+  const int64_t total = E * Kn;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / Kn;
+    A[(size_t)empty_row[r] * Kn + (t - r * Kn)] = 0.f;
+  }
+}
+
+struct PrepArgs {
+  const float* G;
+  float* gtop;
+  int32_t B, CB, KN2, krow, kcol, Kn, mode, N, nm1;
+  int32_t om[3];          // other modes ascending
+  int32_t Ko[3];          // their ranks
+  int64_t gstride[4];     // C-order strides of G
+};
+
+// gtop[b][kb][t][lane] = G_(n)^T[j'][kn] with j' = 64 (lane/16) + t inside block b
+// (j' = c*16 + r), kn = 16 kb + lane%16; zero in padding.
+__global__ void k_prep_gtop(PrepArgs p) {
+  const int64_t total = (int64_t)p.B * p.KN2 * 4096;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(idx & 63);
+    const int t = (int)((idx >> 6) & 63);
+    const int64_t rest = idx >> 12;
+    const int kb = (int)(rest % p.KN2);
+    const int b = (int)(rest / p.KN2);
+    const int rb = b / p.CB, cb = b % p.CB;
+    const int jp = 64 * (lane >> 4) + t;
+    const int c = jp >> 4, r = jp & 15;
+    const int rg = 16 * rb + r, cg = 16 * cb + c;
+    const int kn = 16 * kb + (lane & 15);
+    float v = 0.f;
+    if (rg < p.krow && cg < p.kcol && kn < p.Kn) {
+      int64_t flat = (int64_t)rg * p.kcol + cg;
+      int64_t off = (int64_t)kn * p.gstride[p.mode];
+      for (int m = p.nm1 - 1; m >= 0; --m) {
+        const int64_t k = flat % p.Ko[m];
+        flat /= p.Ko[m];
+        off += k * p.gstride[p.om[m]];
+      }
+      v = p.G[off];
+    }
+    p.gtop[idx] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Core pass
+// ---------------------------------------------------------------------------
+template <int NM1, int KN2>
+__global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rr = wv / a.B;
+  const int b = wv - rr * a.B;
+  const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
+  const int g = lane >> 4, q = lane & 15;
+  const int32_t w = blockIdx.x * a.RPW + rr;
+
+  float gp[16 * KN2][4];
+#pragma unroll
+  for (int k = 0; k < 16 * KN2; ++k) gp[k][0] = gp[k][1] = gp[k][2] = gp[k][3] = 0.f;
+
+  const uint32_t nb = (uint32_t)a.nnz * 4u;
+  auto rI0 = make_rsrc(a.oidx[0], nb);
+  auto rI1 = make_rsrc(a.oidx[1], NM1 >= 2 ? nb : 0u);
+  auto rI2 = make_rsrc(a.oidx[2], NM1 >= 3 ? nb : 0u);
+  auto rX = make_rsrc(a.val, nb);
+  auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
+  auto rU1 = make_rsrc(a.U[1], NM1 >= 2 ? a.Ubytes[1] : 0u);
+  auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
+  uint32_t ka4, kb4, kc4;
+  lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
+
+  if (w < a.W) {
+    const int32_t lo = range_lo(w, a.W, a.nnz);
+    const int32_t hi = range_lo(w + 1, a.W, a.nnz);
+    const int32_t s_first = find_seg(a.seg_off, a.R, lo);
+    const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+    for (int32_t s = s_first; s <= s_last; ++s) {
+      const int32_t so = a.seg_off[s], se = a.seg_off[s + 1];
+      const int32_t slo = so > lo ? so : lo;
+      const int32_t shi = se < hi ? se : hi;
+      f4 y = accumulate_block<NM1>(a, rI0, rI1, rI2, rX, rU0, rU1, rU2, ka4, kb4, kc4, slo, shi, g);
+      const float* urow = a.Uc + (size_t)a.seg_row[s] * a.Kc;
+#pragma unroll
+      for (int k = 0; k < 16 * KN2; ++k) {
+        if (k < a.Kc) {
+          const float u = urow[k];
+          gp[k][0] += u * y[0];
+          gp[k][1] += u * y[1];
+          gp[k][2] += u * y[2];
+          gp[k][3] += u * y[3];
+        }
+      }
+    }
+  }
+  // workgroup sum over its ranges (fixed order), then one partial per block
+  float* buf = lds + b * (16 * KN2 * 256);
+  for (int r2 = 0; r2 < a.RPW; ++r2) {
+    if (rr == r2) {
+#pragma unroll
+      for (int k = 0; k < 16 * KN2; ++k) {
+        f4* dst = reinterpret_cast<f4*>(buf + k * 256 + q * 16 + 4 * g);
+        f4 v = {gp[k][0], gp[k][1], gp[k][2], gp[k][3]};
+        if (r2 == 0) *dst = v;
+        else *dst = *dst + v;
+      }
+    }
+    __syncthreads();
+  }
+  const int total = a.B * 16 * KN2 * 256;
+  float* out = a.gpart + (size_t)blockIdx.x * total;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) out[t] = lds[t];
+}
+
+struct CoreRedArgs {
+  const float* gpart;
+  int32_t groups, B, CB, KN2, krow, kcol, Kc, mode, nm1;
+  int32_t om[3], Ko[3];
+  int64_t gstride[4];
+  float* G;
+  double* fpart;
+};
+
+// Sums the workgroup partials in order (float64), scatters into G (C order),
+// and leaves per-block partial sums of squares for ||G||^2.
+__global__ void k_core_reduce(CoreRedArgs p) {
+  __shared__ double sh[256];
+  const int total = p.B * 16 * p.KN2 * 256;
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int sp = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (e < total)
+    for (int gi = sp; gi < p.groups; gi += 4) acc += (double)p.gpart[(size_t)gi * total + e];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  double sq = 0.0;
+  if (threadIdx.x < 64) {
+    double v = sh[threadIdx.x] + sh[threadIdx.x + 64] + sh[threadIdx.x + 128] + sh[threadIdx.x + 192];
+    if (e < total) {
+      // e = ((b * 16 KN2) + kc) * 256 + j', j' = c*16 + r within block b
+      const int jp = e & 255;
+      const int kc = (e >> 8) % (16 * p.KN2);
+      const int b = (e >> 8) / (16 * p.KN2);
+      const int rb = b / p.CB, cb = b % p.CB;
+      const int rg = 16 * rb + (jp & 15), cg = 16 * cb + (jp >> 4);
+      if (rg < p.krow && cg < p.kcol && kc < p.Kc) {
+        int64_t flat = (int64_t)rg * p.kcol + cg;
+        int64_t off = (int64_t)kc * p.gstride[p.mode];
+        for (int m = p.nm1 - 1; m >= 0; --m) {
+          const int64_t k = flat % p.Ko[m];
+          flat /= p.Ko[m];
+          off += k * p.gstride[p.om[m]];
+        }
+        const float vf = (float)v;
+        p.G[off] = vf;
+        sq = (double)vf * (double)vf;
+      }
+    }
+  }
+  __syncthreads();
+  sh[threadIdx.x] = sq;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) p.fpart[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_f(const double* part, int n, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+struct PassGeom {
+  int nm1;
+  int om[3];
+  int Ko[3];
+  int krow, kcol, RB, CB, B;
+};
+
+PassGeom geom(const hoqri_plan* p, int mode) {
+  PassGeom g{};
+  g.nm1 = other_modes(p->N, mode, g.om);
+  g.krow = 1;
+  for (int c = 0; c < g.nm1; ++c) g.Ko[c] = p->K[g.om[c]];
+  for (int c = 0; c < g.nm1 - 1; ++c) g.krow *= g.Ko[c];
+  g.kcol = g.Ko[g.nm1 - 1];
+  g.RB = (g.krow + 15) / 16;
+  g.CB = (g.kcol + 15) / 16;
+  g.B = g.RB * g.CB;
+  return g;
+}
+
+void fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, const float* const* U) {
+  const ModeData& md = p->md[mode];
+  for (int c = 0; c < 3; ++c) {
+    a.oidx[c] = c < g.nm1 ? md.oidx[c] : md.oidx[0];
+    const int m = c < g.nm1 ? g.om[c] : g.om[0];
+    a.U[c] = U[m];
+    a.Ubytes[c] = (uint32_t)(p->dims[m] * p->K[m] * 4);
+  }
+  a.val = md.val;
+  a.seg_off = md.seg_off;
+  a.seg_row = md.seg_row;
+  a.R = (int32_t)md.R;
+  a.nnz = (int32_t)p->nnz;
+  a.B = g.B;
+  a.RB = g.RB;
+  a.CB = g.CB;
+  a.K1 = g.nm1 >= 2 ? g.Ko[1] : 1;
+}
+
+template <int NM1, int KN2>
+hipError_t launch_ttm_t(const SegArgs& a, int threads, size_t shmem, hipStream_t s) {
+  auto k = k_ttm_f32<NM1, KN2>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  const int grid = (a.W + a.RPW - 1) / a.RPW;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), shmem, s, a);
+  return hipGetLastError();
+}
+
+template <int NM1, int KN2>
+hipError_t launch_core_t(const SegArgs& a, int grid, int threads, size_t shmem, hipStream_t s) {
+  auto k = k_core_f32<NM1, KN2>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), shmem, s, a);
+  return hipGetLastError();
+}
+
+void g_strides(const hoqri_plan* p, int64_t* st) {
+  int64_t s = 1;
+  for (int m = p->N - 1; m >= 0; --m) {
+    st[m] = s;
+    s *= p->K[m];
+  }
+}
+
+}  // namespace
+
+bool segpass_supported(const hoqri_plan* p, int mode) {
+  PassGeom g = geom(p, mode);
+  return g.B <= 8 && p->K[mode] <= 32;
+}
+
+hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, const float* G, float* A,
+                               hipStream_t s) {
+  if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
+  const PassGeom g = geom(p, mode);
+  const int KN2 = (p->K[mode] + 15) / 16;
+  const ModeData& md = p->md[mode];
+  // 1. stage-two operand
+  PrepArgs pa{};
+  pa.G = G;
+  pa.gtop = p->sc.gtop;
+  pa.B = g.B;
+  pa.CB = g.CB;
+  pa.KN2 = KN2;
+  pa.krow = g.krow;
+  pa.kcol = g.kcol;
+  pa.Kn = p->K[mode];
+  pa.mode = mode;
+  pa.N = p->N;
+  pa.nm1 = g.nm1;
+  for (int c = 0; c < 3; ++c) {
+    pa.om[c] = c < g.nm1 ? g.om[c] : 0;
+    pa.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
+  }
+  g_strides(p, pa.gstride);
+  {
+    int64_t total = (int64_t)g.B * KN2 * 4096;
+    int grid = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_prep_gtop, dim3(grid), dim3(256), 0, s, pa);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+  // 2. main pass
+  SegArgs a{};
+  fill_common(a, p, mode, g, U);
+  int64_t W = md.ranges;
+  if (W > p->nnz) W = p->nnz;
+  a.W = (int32_t)W;
+  a.RPW = g.B == 1 ? 4 : 1;
+  a.gtop = p->sc.gtop;
+  a.A = A;
+  a.Kn = p->K[mode];
+  a.carry = p->sc.carry;
+  a.meta = p->sc.meta;
+  const int threads = 64 * g.B * a.RPW;
+  const size_t shmem = (size_t)(g.B * a.RPW * 16 * YS + a.RPW * g.B * KN2 * 256 + a.RPW * 32) * 4;
+  hipError_t e = hipSuccess;
+  switch (g.nm1 * 10 + KN2) {
+    case 11: e = launch_ttm_t<1, 1>(a, threads, shmem, s); break;
+    case 12: e = launch_ttm_t<1, 2>(a, threads, shmem, s); break;
+    case 21: e = launch_ttm_t<2, 1>(a, threads, shmem, s); break;
+    case 22: e = launch_ttm_t<2, 2>(a, threads, shmem, s); break;
+    case 31: e = launch_ttm_t<3, 1>(a, threads, shmem, s); break;
+    case 32: e = launch_ttm_t<3, 2>(a, threads, shmem, s); break;
+    default: return HOQRI_ERR_UNSUPPORTED;
+  }
+  if (e != hipSuccess) return HOQRI_ERR_HIP;
+  // 3. split slices and empty rows
+  hipLaunchKernelGGL(k_fix_split, dim3((unsigned)((W + 3) / 4)), dim3(256), 0, s, p->sc.meta, p->sc.carry,
+                     md.seg_row, a.W, a.Kn, A);
+  if (md.E > 0) {
+    int64_t tot = md.E * a.Kn;
+    int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, md.empty_row, md.E, a.Kn, A);
+  }
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, double* f_out, hipStream_t s) {
+  const int mode = p->core_mode;
+  if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
+  const PassGeom g = geom(p, mode);
+  const int KN2 = (p->K[mode] + 15) / 16;
+  SegArgs a{};
+  fill_common(a, p, mode, g, U);
+  a.RPW = g.B >= 8 ? 1 : 8 / g.B;
+  int64_t groups = p->core_groups;
+  int64_t W = groups * a.RPW;
+  if (W > p->nnz) {
+    W = p->nnz;
+    groups = (W + a.RPW - 1) / a.RPW;
+  }
+  a.W = (int32_t)W;
+  a.Uc = U[mode];
+  a.Kc = p->K[mode];
+  a.gpart = p->sc.gpart;
+  const int threads = 64 * g.B * a.RPW;
+  const size_t shmem = (size_t)g.B * 16 * KN2 * 256 * 4;
+  hipError_t e = hipSuccess;
+  switch (g.nm1 * 10 + KN2) {
+    case 11: e = launch_core_t<1, 1>(a, (int)groups, threads, shmem, s); break;
+    case 12: e = launch_core_t<1, 2>(a, (int)groups, threads, shmem, s); break;
+    case 21: e = launch_core_t<2, 1>(a, (int)groups, threads, shmem, s); break;
+    case 22: e = launch_core_t<2, 2>(a, (int)groups, threads, shmem, s); break;
+    case 31: e = launch_core_t<3, 1>(a, (int)groups, threads, shmem, s); break;
+    case 32: e = launch_core_t<3, 2>(a, (int)groups, threads, shmem, s); break;
+    default: return HOQRI_ERR_UNSUPPORTED;
+  }
+  if (e != hipSuccess) return HOQRI_ERR_HIP;
+  CoreRedArgs r{};
+  r.gpart = p->sc.gpart;
+  r.groups = (int32_t)groups;
+  r.B = g.B;
+  r.CB = g.CB;
+  r.KN2 = KN2;
+  r.krow = g.krow;
+  r.kcol = g.kcol;
+  r.Kc = p->K[mode];
+  r.mode = mode;
+  r.nm1 = g.nm1;
+  for (int c = 0; c < 3; ++c) {
+    r.om[c] = c < g.nm1 ? g.om[c] : 0;
+    r.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
+  }
+  g_strides(p, r.gstride);
+  r.G = G;
+  r.fpart = p->sc.fpart;
+  const int total = g.B * 16 * KN2 * 256;
+  const int nblk = (total + 63) / 64;
+  hipLaunchKernelGGL(k_core_reduce, dim3(nblk), dim3(256), 0, s, r);
+  hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, p->sc.fpart, nblk, f_out ? f_out : p->sc.f_dev);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+}  // namespace hoqri

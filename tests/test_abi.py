@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every symbol include/hoqri.h declares;
+host-side argument validation returns the documented codes before any device
+work (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hoqri.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hoqri_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2510_16930_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libhoqri.so not built")
+    return _lib.load()
+
+
+def test_header_declares_expected_entry_points():
+    from paper_2510_16930_amd import _lib
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    from paper_2510_16930_amd import _lib
+    for code in _lib.STATUS:
+        assert len(_lib.hoqri_status_string(code)) > 0
+
+
+def _ws(lib, order, dims, ranks, nnz):
+    d = (ctypes.c_int64 * max(order, 1))(*dims)
+    r = (ctypes.c_int32 * max(order, 1))(*ranks)
+    out = ctypes.c_size_t(0)
+    return lib.hoqri_plan_workspace_size(order, d, r, nnz, ctypes.byref(out))
+
+
+def test_argument_validation_before_device_work(lib):
+    # order out of range, nnz < 1, bad dims -> ERR_ARG; bad ranks -> ERR_RANK; K > 32 -> UNSUPPORTED
+    assert _ws(lib, 1, [10], [2], 5) == -1
+    assert _ws(lib, 5, [4] * 5, [2] * 5, 5) == -1
+    assert _ws(lib, 3, [10, 10, 10], [2, 2, 2], 0) == -1
+    assert _ws(lib, 3, [10, 0, 10], [2, 2, 2], 5) == -1
+    assert _ws(lib, 3, [10, 10, 10], [11, 2, 2], 5) == -3     # K > I
+    assert _ws(lib, 3, [10, 10, 10], [0, 2, 2], 5) == -3      # K < 1
+    assert _ws(lib, 3, [10, 10, 10], [5, 2, 2], 5) == -3      # K_0 > K_1 K_2
+    assert _ws(lib, 3, [100, 100, 100], [33, 33, 33], 5) == -7
+    assert lib.hoqri_plan_workspace_size(3, None, None, 5, None) == -1
+
+
+def test_null_plan_rejected(lib):
+    assert lib.hoqri_core(None, None, None, None, 1, None) == -1
+    assert lib.hoqri_ttmctc(None, 0, None, None, None, 1, None) == -1
+    assert lib.hoqri_run(None, None, None, None, None, None, None) == -1
+    info = ctypes.c_int64()
+    assert lib.hoqri_plan_info(None, ctypes.byref(info), None, None) == -1
+    lib.hoqri_plan_destroy(None)
+
+
+def test_orth_argument_validation(lib):
+    # cols > rows, cols > 32, null pointers -> ERR_ARG (no device work)
+    assert lib.hoqri_orth(3, 4, None, None, None, None, None, 0, None) == -1
+    assert lib.hoqri_orth(100, 40, None, None, None, None, None, 0, None) == -1
+    assert lib.hoqri_orth_workspace_size(1000, 16) > 0
