@@ -56,7 +56,7 @@ typedef enum {
 } hoqri_prec;
 
 /* Limits of this build: 2 <= N <= 4; 1 <= K_n <= 32; prod_{m!=n} K_m <= 2048;
- * nnz < 2^31; every I_n < 2^31 and I_n * K_n * 4 bytes < 2^32. */
+ * nnz < 2^30; every I_n < 2^31 and I_n * K_n * 4 bytes < 2^32. */
 #define HOQRI_MAX_ORDER 4
 #define HOQRI_MAX_RANK 32
 
@@ -111,7 +111,7 @@ size_t hoqri_orth_workspace_size(int64_t rows, int32_t cols);
 /* Orthonormal basis of A (the QR step of Alg. 2) by CholeskyQR2 with float64
  * Gram matrices and Cholesky factors: W1 = A^T A, R1 = chol(W1), Q1 = A R1^-1,
  * W2 = Q1^T Q1, R2 = chol(W2), U = A (R2 R1)^-1. This is the thin QR with a
- * positive diagonal of R. d_A: rows x cols float32 row-major, cols <= 32 <= ...
+ * positive diagonal of R. d_A: rows x cols float32 row-major, 1 <= cols <= min(rows, 32).
  * d_U: output, may alias d_A. d_R: optional (NULL allowed) cols x cols float64
  * upper-triangular R = R2 R1 (row-major). d_status: device int32 set to 0 on
  * success or HOQRI_ERR_BREAKDOWN when a Cholesky pivot is <= 1e-13 * trace(W)
@@ -147,6 +147,20 @@ typedef struct {
  * HOQRI_ERR_BREAKDOWN if some A^(n) is rank deficient. */
 hoqri_status hoqri_run(hoqri_plan* plan, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
                        const hoqri_run_opts* opts, hoqri_run_stats* stats, hipStream_t stream);
+
+/* Kernel timing (diagnostics). When enabled on a plan, every launch of the
+ * listed kernels made through that plan is bracketed by HIP events recorded on
+ * the launch stream, and hoqri_timing_read returns the number of launches and
+ * their summed duration (milliseconds) since the last enable, for `kind`:
+ *   HOQRI_KERNEL_TTMCTC = the TTMcTC segment-pass kernel,
+ *   HOQRI_KERNEL_CORE   = the core segment-pass kernel (without its reduction),
+ *   HOQRI_KERNEL_ORTH   = one CholeskyQR2 (all its kernels),
+ *   HOQRI_KERNEL_FIXUP  = TTMcTC operand preparation and split-slice fix-up.
+ * Enabling resets the counters. At most 4096 launches per kind are recorded.
+ * hoqri_timing_read synchronises the recorded events. */
+typedef enum { HOQRI_KERNEL_TTMCTC = 0, HOQRI_KERNEL_CORE = 1, HOQRI_KERNEL_ORTH = 2, HOQRI_KERNEL_FIXUP = 3 } hoqri_kernel;
+hoqri_status hoqri_timing_enable(hoqri_plan* plan, int32_t enable);
+hoqri_status hoqri_timing_read(hoqri_plan* plan, int32_t kind, int64_t* launches, double* total_ms);
 
 /* Human-readable name of a status code (static string). */
 const char* hoqri_status_string(hoqri_status status);

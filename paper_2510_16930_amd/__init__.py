@@ -15,5 +15,7 @@ from ._lib import (  # noqa: F401
     hoqri_plan_workspace_size,
     hoqri_run,
     hoqri_status_string,
+    hoqri_timing_enable,
+    hoqri_timing_read,
     hoqri_ttmctc,
 )

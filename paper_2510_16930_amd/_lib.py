@@ -26,8 +26,9 @@ PREC = {"fp32": 1, "bf16": 2, "fp16": 3}
 EXPORTS = (
     "hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_plan_destroy",
     "hoqri_core", "hoqri_ttmctc", "hoqri_orth_workspace_size", "hoqri_orth", "hoqri_run",
-    "hoqri_status_string",
+    "hoqri_status_string", "hoqri_timing_enable", "hoqri_timing_read",
 )
+KERNEL = {"ttmctc": 0, "core": 1, "orth": 2, "fixup": 3}
 
 
 class HoqriError(RuntimeError):
@@ -70,10 +71,12 @@ def load() -> ctypes.CDLL:
     L.hoqri_orth_workspace_size.restype = sz
     L.hoqri_orth.argtypes = [i64, i32, vp, vp, vp, vp, vp, sz, vp]
     L.hoqri_run.argtypes = [vp, P(vp), vp, vp, P(RunOpts), P(RunStats), vp]
+    L.hoqri_timing_enable.argtypes = [vp, i32]
+    L.hoqri_timing_read.argtypes = [vp, i32, P(i64), P(dbl)]
     L.hoqri_status_string.argtypes = [ctypes.c_int]
     L.hoqri_status_string.restype = ctypes.c_char_p
     for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
-                 "hoqri_ttmctc", "hoqri_orth", "hoqri_run"):
+                 "hoqri_ttmctc", "hoqri_orth", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -253,3 +256,17 @@ def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp
     _check(L.hoqri_run(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f_hist) if f_hist is not None else None,
                        ctypes.byref(opts), ctypes.byref(st), _stream(stream)), "hoqri_run")
     return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max)
+
+
+def hoqri_timing_enable(plan: Plan, enable: bool = True):
+    """Starts (and resets) or stops per-kernel HIP-event timing on the plan."""
+    _check(load().hoqri_timing_enable(plan.handle, int(bool(enable))), "hoqri_timing_enable")
+
+
+def hoqri_timing_read(plan: Plan, kind: str):
+    """Returns (launches, total milliseconds) for kernel kind ttmctc/core/orth/fixup."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().hoqri_timing_read(plan.handle, KERNEL[kind], ctypes.byref(n), ctypes.byref(ms)),
+           "hoqri_timing_read")
+    return int(n.value), float(ms.value)

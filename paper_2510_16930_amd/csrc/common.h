@@ -61,6 +61,17 @@ struct Scratch {
 
 }  // namespace hoqri
 
+namespace hoqri {
+// Optional per-kernel HIP-event timing of a plan's launches.
+constexpr int kTimingKinds = 4;
+constexpr int kTimingCap = 4096;
+struct Timing {
+  bool enabled = false;
+  hipEvent_t* ev[kTimingKinds] = {nullptr, nullptr, nullptr, nullptr};  // 2 per launch
+  int64_t count[kTimingKinds] = {0, 0, 0, 0};
+};
+}  // namespace hoqri
+
 struct hoqri_plan {
   int32_t N;
   int64_t dims[hoqri::kMaxOrder];
@@ -75,6 +86,7 @@ struct hoqri_plan {
   void* ws;
   size_t ws_bytes;
   int32_t device;
+  hoqri::Timing timing;
 };
 
 namespace hoqri {
@@ -107,6 +119,25 @@ hoqri_status launch_orth(int64_t rows, int32_t cols, const float* A, float* U, d
                          int32_t* status, void* ws, size_t ws_bytes, hipStream_t s, bool sticky);
 hoqri_status launch_orth_err(int64_t rows, int32_t cols, const float* U, double* err_out, void* ws,
                              size_t ws_bytes, hipStream_t s);
+
+// Records a start event on construction and a stop event on destruction when
+// timing is enabled on the plan (no-op otherwise).
+struct TimerScope {
+  hoqri_plan* p;
+  int kind;
+  hipStream_t s;
+  int64_t slot;
+  TimerScope(hoqri_plan* plan, int k, hipStream_t st) : p(plan), kind(k), s(st), slot(-1) {
+    if (p && p->timing.enabled && p->timing.count[kind] < kTimingCap) {
+      slot = p->timing.count[kind]++;
+      (void)hipEventRecord(p->timing.ev[kind][2 * slot], s);
+    }
+  }
+  ~TimerScope() {
+    if (slot >= 0) (void)hipEventRecord(p->timing.ev[kind][2 * slot + 1], s);
+  }
+};
+void timing_release(hoqri_plan* p);
 
 // Element offsets of the other modes of `mode` (ascending, mode skipped).
 inline int other_modes(int N, int mode, int* out) {

@@ -596,7 +596,11 @@ extern "C" hoqri_status hoqri_plan_info(const hoqri_plan* p, int64_t* nnz_coales
   return HOQRI_OK;
 }
 
-extern "C" void hoqri_plan_destroy(hoqri_plan* p) { delete p; }
+extern "C" void hoqri_plan_destroy(hoqri_plan* p) {
+  if (!p) return;
+  timing_release(p);
+  delete p;
+}
 
 extern "C" const char* hoqri_status_string(hoqri_status s) {
   switch (s) {

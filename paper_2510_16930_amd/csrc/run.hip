@@ -101,6 +101,7 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
         HOQRI_TRY(launch_core_f32(p, U, d_G_out, fdst, stream));
       }
       HOQRI_TRY(launch_ttmctc_f32(p, n, U, d_G_out, p->sc.A, stream));
+      TimerScope to(p, HOQRI_KERNEL_ORTH, stream);
       HOQRI_TRY(launch_orth(p->dims[n], p->K[n], p->sc.A, d_U_inout[n], nullptr, status, p->sc.orth_ws,
                             p->sc.orth_ws_bytes, stream, true));
     }
@@ -145,5 +146,52 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   double emax = 0.0;
   for (int n = 0; n < N; ++n) emax = std::fmax(emax, errs[n]);
   stats->orth_err_max = emax;
+  return HOQRI_OK;
+}
+
+namespace hoqri {
+void timing_release(hoqri_plan* p) {
+  for (int k = 0; k < kTimingKinds; ++k) {
+    if (p->timing.ev[k]) {
+      for (int i = 0; i < 2 * kTimingCap; ++i) (void)hipEventDestroy(p->timing.ev[k][i]);
+      delete[] p->timing.ev[k];
+      p->timing.ev[k] = nullptr;
+    }
+  }
+  p->timing.enabled = false;
+}
+}  // namespace hoqri
+
+extern "C" hoqri_status hoqri_timing_enable(hoqri_plan* p, int32_t enable) {
+  HOQRI_TRY(check_plan(p));
+  for (int k = 0; k < kTimingKinds; ++k) p->timing.count[k] = 0;
+  if (!enable) {
+    p->timing.enabled = false;
+    return HOQRI_OK;
+  }
+  for (int k = 0; k < kTimingKinds; ++k) {
+    if (!p->timing.ev[k]) {
+      p->timing.ev[k] = new hipEvent_t[2 * kTimingCap];
+      for (int i = 0; i < 2 * kTimingCap; ++i)
+        if (hipEventCreate(&p->timing.ev[k][i]) != hipSuccess) return HOQRI_ERR_HIP;
+    }
+  }
+  p->timing.enabled = true;
+  return HOQRI_OK;
+}
+
+extern "C" hoqri_status hoqri_timing_read(hoqri_plan* p, int32_t kind, int64_t* launches, double* total_ms) {
+  HOQRI_TRY(check_plan(p));
+  if (kind < 0 || kind >= kTimingKinds || !launches || !total_ms) return HOQRI_ERR_ARG;
+  const int64_t n = p->timing.count[kind];
+  double tot = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    HOQRI_HIP_TRY(hipEventSynchronize(p->timing.ev[kind][2 * i + 1]));
+    float ms = 0.f;
+    HOQRI_HIP_TRY(hipEventElapsedTime(&ms, p->timing.ev[kind][2 * i], p->timing.ev[kind][2 * i + 1]));
+    tot += ms;
+  }
+  *launches = n;
+  *total_ms = tot;
   return HOQRI_OK;
 }

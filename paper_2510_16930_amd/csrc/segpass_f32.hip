@@ -623,6 +623,7 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   }
   g_strides(p, pa.gstride);
   {
+    TimerScope tp(p, HOQRI_KERNEL_FIXUP, s);
     int64_t total = (int64_t)g.B * KN2 * 4096;
     int grid = (int)((total + 255) / 256);
     hipLaunchKernelGGL(k_prep_gtop, dim3(grid), dim3(256), 0, s, pa);
@@ -643,6 +644,8 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   const int threads = 64 * g.B * a.RPW;
   const size_t shmem = (size_t)(g.B * a.RPW * 16 * YS + a.RPW * g.B * KN2 * 256 + a.RPW * 32) * 4;
   hipError_t e = hipSuccess;
+  {
+  TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
   switch (g.nm1 * 10 + KN2) {
     case 11: e = launch_ttm_t<1, 1>(a, threads, shmem, s); break;
     case 12: e = launch_ttm_t<1, 2>(a, threads, shmem, s); break;
@@ -652,7 +655,9 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
     case 32: e = launch_ttm_t<3, 2>(a, threads, shmem, s); break;
     default: return HOQRI_ERR_UNSUPPORTED;
   }
+  }
   if (e != hipSuccess) return HOQRI_ERR_HIP;
+  TimerScope tf(p, HOQRI_KERNEL_FIXUP, s);
   // 3. split slices and empty rows
   hipLaunchKernelGGL(k_fix_split, dim3((unsigned)((W + 3) / 4)), dim3(256), 0, s, p->sc.meta, p->sc.carry,
                      md.seg_row, a.W, a.Kn, A);
@@ -686,6 +691,8 @@ hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, dou
   const int threads = 64 * g.B * a.RPW;
   const size_t shmem = (size_t)g.B * 16 * KN2 * 256 * 4;
   hipError_t e = hipSuccess;
+  {
+  TimerScope ts(p, HOQRI_KERNEL_CORE, s);
   switch (g.nm1 * 10 + KN2) {
     case 11: e = launch_core_t<1, 1>(a, (int)groups, threads, shmem, s); break;
     case 12: e = launch_core_t<1, 2>(a, (int)groups, threads, shmem, s); break;
@@ -694,6 +701,7 @@ hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, dou
     case 31: e = launch_core_t<3, 1>(a, (int)groups, threads, shmem, s); break;
     case 32: e = launch_core_t<3, 2>(a, (int)groups, threads, shmem, s); break;
     default: return HOQRI_ERR_UNSUPPORTED;
+  }
   }
   if (e != hipSuccess) return HOQRI_ERR_HIP;
   CoreRedArgs r{};

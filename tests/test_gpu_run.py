@@ -41,7 +41,9 @@ def test_c1_trajectory_matches_oracle():
     for n in range(3):
         # canonical QR (positive diagonal): the factors are comparable elementwise
         assert np.abs(U[n] - Uo[n]).max() < 1e-4
-        assert O.subspace_dist(U[n], Uo[n]) < 1e-8
+        # d is a squared Frobenius distance: 1000 entries within 1e-4 give at most 1e-5;
+        # float32 drift over 30 mode steps is observed at ~1e-7
+        assert O.subspace_dist(U[n], Uo[n]) < 1e-6
     assert np.linalg.norm(G - Go) / np.linalg.norm(Go) < 1e-5
     assert st.orth_err_max < 1e-5
     # Theorem 1 on the GPU trajectory (float32 slack)
@@ -90,14 +92,27 @@ def test_matrix_case_top_singular_subspace():
 
 
 def test_rank_one_and_stopping_rule():
+    # K = (1,1,1) with the stop rule |f_t - f_{t-1}| <= tol f_t. Near the threshold
+    # float32 and float64 f may decide differently, so the unique facts are checked:
+    # the GPU stops at the first sweep where its own f sequence meets the rule, the
+    # oracle's stop is within one sweep, and the GPU state equals the oracle's after
+    # the same number of sweeps.
     dims, K = (50, 60, 70), (1, 1, 1)
     idx, vals = synth.coo_uniform(dims, 2000, seed=14)
+    tol = 1e-6
     start = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 5))]
-    U, G, st, fh, Uo, Go, h = run_both(dims, K, idx, vals.astype(np.float32), start, 200, tol=1e-6)
-    assert st.sweeps == len(h["f_sweep"])
-    assert st.f == pytest.approx(h["f_sweep"][-1], rel=1e-5)
+    U, G, st, fh, Uo, Go, h = run_both(dims, K, idx, vals.astype(np.float32), start, 200, tol=tol)
+    T = st.sweeps
+    F = [fh[t * 3] for t in range(T)] + [st.f]          # f before sweep 1, after sweep 1, ..., after T
+    for t in range(1, T):
+        assert abs(F[t] - F[t - 1]) > tol * F[t]
+    assert abs(F[T] - F[T - 1]) <= tol * F[T]
+    assert abs(T - len(h["f_sweep"])) <= 1
+    Uo2, Go2, h2 = O.hoqri(idx, vals.astype(np.float32).astype(np.float64), dims, K,
+                           [u.astype(np.float64) for u in start], sweeps=T)
+    assert st.f == pytest.approx(h2["f_sweep"][-1], rel=1e-5)
     for n in range(3):
-        assert np.abs(U[n] - Uo[n]).max() < 1e-4
+        assert np.abs(U[n] - Uo2[n]).max() < 1e-4
 
 
 def test_order4_run():
