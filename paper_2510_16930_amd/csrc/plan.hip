@@ -149,9 +149,22 @@ struct GatherArgs {
 };
 
 // Mode-n sorted copy: other-mode factor offsets i_m * K_m, values, and i_n.
+// The copy is stored in blocks of 16 nonzeros, each 4x4-transposed: logical
+// position 16b + 4t + g lives at physical 16b + 4g + t, so one 16-byte load of
+// lane group g in the segment passes returns logical 16b + g + {0, 4, 8, 12}.
+// Positions nnz .. nnz_pad-1 (padding to a multiple of 16) hold zeros.
+__device__ inline int64_t phys16(int64_t j) { return (j & ~int64_t(15)) + 4 * (j & 3) + ((j & 15) >> 2); }
+
 __global__ void k_gather_mode(GatherArgs a) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < a.nnz;
+  const int64_t npad = (a.nnz + 15) / 16 * 16;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npad;
        j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pj = phys16(j);
+    if (j >= a.nnz) {
+      for (int c = 0; c < a.N - 1; ++c) a.oidx[c][pj] = 0;
+      a.val[pj] = 0.f;
+      continue;
+    }
     int64_t src = a.perm ? a.perm[j] : j;
     int c = 0;
     for (int m = 0; m < a.N; ++m) {
@@ -159,10 +172,10 @@ __global__ void k_gather_mode(GatherArgs a) {
       if (m == a.mode) {
         a.modeidx[j] = i;
       } else {
-        a.oidx[c++][j] = i * a.K[m];
+        a.oidx[c++][pj] = i * a.K[m];
       }
     }
-    a.val[j] = a.cval[src];
+    a.val[pj] = a.cval[src];
   }
 }
 
@@ -297,9 +310,10 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
 
   Carver c{nullptr, 0};
   // persistent
+  const int64_t npad = (nnz + 15) / 16 * 16;
   for (int n = 0; n < N; ++n) {
-    for (int m = 0; m < N - 1; ++m) c.take<int32_t>(nnz);
-    c.take<float>(nnz);
+    for (int m = 0; m < N - 1; ++m) c.take<int32_t>(npad);
+    c.take<float>(npad);
     int64_t rmax = dims[n] < nnz ? dims[n] : nnz;
     c.take<int32_t>(rmax);
     c.take<int32_t>(rmax + 1);
@@ -391,10 +405,11 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
 
   // persistent region
   Carver c{(char*)p->ws, 0};
+  const int64_t npad_in = (nnz_in + 15) / 16 * 16;
   for (int n = 0; n < N; ++n) {
     ModeData& md = p->md[n];
-    for (int m = 0; m < N - 1; ++m) md.oidx[m] = c.take<int32_t>(nnz_in);
-    md.val = c.take<float>(nnz_in);
+    for (int m = 0; m < N - 1; ++m) md.oidx[m] = c.take<int32_t>(npad_in);
+    md.val = c.take<float>(npad_in);
     int64_t rmax = p->dims[n] < nnz_in ? p->dims[n] : nnz_in;
     md.seg_row = c.take<int32_t>(rmax);
     md.seg_off = c.take<int32_t>(rmax + 1);
@@ -486,7 +501,7 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
     for (int m = 0; m < N - 1; ++m) ga.oidx[m] = md.oidx[m];
     ga.val = md.val;
     ga.modeidx = modeidx;
-    k_gather_mode<<<grid_for(nnz), kThreads, 0, s>>>(ga);
+    k_gather_mode<<<grid_for(nnz + 16), kThreads, 0, s>>>(ga);
     k_head_flags<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, nnz, head);
     tb = L.sort_tmp;
     HOQRI_HIP_TRY(rocprim::exclusive_scan(stmp, tb, head, uid, 0, (size_t)nnz, rocprim::plus<int32_t>(), s));

@@ -68,6 +68,7 @@ struct SegArgs {
   const int32_t* seg_row;   // [R]
   int32_t R;
   int32_t nnz;
+  int32_t nnz_pad;          // nnz rounded up to 16 (the stored length)
   int32_t W;                // ranges
   int32_t B, RB, CB;        // y_i blocks (16x16) per range, as RB x CB
   int32_t RPW;              // ranges per workgroup
@@ -98,78 +99,21 @@ __device__ inline int32_t find_seg(const int32_t* seg_off, int32_t R, int32_t e)
   return lo;
 }
 
-// Accumulates this wave's 16x16 block of y_i over nonzeros [lo, hi) of the
-// sorted stream. Lane (g = lane/16, q = lane%16) supplies A[q][g] and B[g][q]
-// of each 16x16x4 product; the result D[4g+v][q] is returned in acc[v].
-template <int NM1>
-__device__ inline f4 accumulate_block(const SegArgs& a, __amdgpu_buffer_rsrc_t rI0, __amdgpu_buffer_rsrc_t rI1,
-                                      __amdgpu_buffer_rsrc_t rI2, __amdgpu_buffer_rsrc_t rX,
-                                      __amdgpu_buffer_rsrc_t rU0, __amdgpu_buffer_rsrc_t rU1,
-                                      __amdgpu_buffer_rsrc_t rU2, uint32_t ka4, uint32_t kb4, uint32_t kc4,
-                                      int32_t lo, int32_t hi, int g) {
-  f4 tot = {0.f, 0.f, 0.f, 0.f};
-  f4 acc = {0.f, 0.f, 0.f, 0.f};
-  // the bounds are wave-uniform; say so, so the loads take scalar offsets
-  lo = __builtin_amdgcn_readfirstlane(lo);
-  hi = __builtin_amdgcn_readfirstlane(hi);
-  int32_t e0 = lo;
-  int inner = 0;
-  const uint32_t goff = (uint32_t)g * 16u;
-  // bulk: 16 nonzeros per step, group g takes e0+4g .. e0+4g+3
-  for (; e0 + 16 <= hi; e0 += 16) {
-    const uint32_t so = (uint32_t)e0 * 4u;
-    // (bit-cast the whole vector: a bit-cast of one element reads element 0)
-    const f4 xv = __builtin_bit_cast(f4, ld_i4(rX, goff, so));
-    i4 i0 = ld_i4(rI0, goff, so);
-    i4 i1 = (NM1 >= 2) ? ld_i4(rI1, goff, so) : i4{0, 0, 0, 0};
-    i4 i2 = (NM1 >= 3) ? ld_i4(rI2, goff, so) : i4{0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float x = xv[s];
-      float av, bv;
-      if constexpr (NM1 == 1) {
-        av = x;
-        bv = ld_f(rU0, ((uint32_t)i0[s] << 2) + kc4);
-      } else if constexpr (NM1 == 2) {
-        av = x * ld_f(rU0, ((uint32_t)i0[s] << 2) + ka4);
-        bv = ld_f(rU1, ((uint32_t)i1[s] << 2) + kc4);
-      } else {
-        av = x * ld_f(rU0, ((uint32_t)i0[s] << 2) + ka4) * ld_f(rU1, ((uint32_t)i1[s] << 2) + kb4);
-        bv = ld_f(rU2, ((uint32_t)i2[s] << 2) + kc4);
-      }
-      acc = mfma4(av, bv, acc);
-    }
-    if (++inner == 16) {
-      tot += acc;
-      acc = f4{0.f, 0.f, 0.f, 0.f};
-      inner = 0;
-    }
+__device__ inline int32_t rd_lane(int32_t v, int32_t lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// A window of the slice table held in registers: lane i has seg_off[base+i]
+// and seg_row[base+i], so a slice change reads them with readlane.
+struct SegWindow {
+  int32_t base;
+  int32_t off;
+  int32_t row;
+  __device__ void load(const SegArgs& a, int32_t b, int lane) {
+    base = __builtin_amdgcn_readfirstlane(b);
+    const int32_t i = b + lane;  // clamped, unconditional loads keep the control flow uniform
+    off = a.seg_off[i < a.R ? i : a.R];
+    row = a.seg_row[i < a.R ? i : a.R - 1];
   }
-  // tail: 4 nonzeros per step, group g takes e0+g
-  for (; e0 < hi; e0 += 4) {
-    const int32_t e = e0 + g;
-    const uint32_t off = (uint32_t)e * 4u;
-    float x = __builtin_bit_cast(float, ld_i(rX, off));
-    x = (e < hi) ? x : 0.f;
-    int32_t j0 = ld_i(rI0, off);
-    float av, bv;
-    if constexpr (NM1 == 1) {
-      av = x;
-      bv = ld_f(rU0, ((uint32_t)j0 << 2) + kc4);
-    } else if constexpr (NM1 == 2) {
-      int32_t j1 = ld_i(rI1, off);
-      av = x * ld_f(rU0, ((uint32_t)j0 << 2) + ka4);
-      bv = ld_f(rU1, ((uint32_t)j1 << 2) + kc4);
-    } else {
-      int32_t j1 = ld_i(rI1, off);
-      int32_t j2 = ld_i(rI2, off);
-      av = x * ld_f(rU0, ((uint32_t)j0 << 2) + ka4) * ld_f(rU1, ((uint32_t)j1 << 2) + kb4);
-      bv = ld_f(rU2, ((uint32_t)j2 << 2) + kc4);
-    }
-    acc = mfma4(av, bv, acc);
-  }
-  return tot + acc;
-}
+};
 
 // Per-lane byte offsets of this lane's row / column inside the gathered factor
 // rows, for block (rb, cb). Padded rows/columns read finite neighbouring data
@@ -190,6 +134,146 @@ __device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uin
   *kc4 = (uint32_t)c * 4u;
 }
 
+// Walks nonzeros [lo, hi) of the sorted stream (slices s_first..s_last, clipped
+// to the range) and calls on_seg(s, row, y) when the clipped slice s is done;
+// y holds this wave's 16x16 block of y_s as D[4g+v][q] in y[v].
+//
+// The stream is read in aligned blocks of 16 nonzeros. Inside a block the plan
+// stores the nonzeros 4x4-transposed (physical 4g + t holds logical 4t + g), so
+// the 16-byte load of lane group g returns its k-slot for all four sub-steps;
+// sub-step t covers the 4 consecutive logical nonzeros 16b + 4t + (0..3). Each
+// matrix-core product covers one sub-step and one slice; lanes whose nonzero
+// lies outside the slice contribute zero. Factor rows of block b+1 and the
+// index/value vectors of block b+2 are in flight while block b is multiplied.
+template <int NM1, typename OnSeg>
+__device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
+                                  uint32_t ka4, uint32_t kb4, uint32_t kc4, int lane, OnSeg&& on_seg) {
+  const int g = lane >> 4;
+  const uint32_t nb4 = (uint32_t)a.nnz_pad * 4u;
+  const auto rI0 = make_rsrc(a.oidx[0], nb4);
+  const auto rI1 = make_rsrc(a.oidx[1], NM1 >= 2 ? nb4 : 0u);
+  const auto rI2 = make_rsrc(a.oidx[2], NM1 >= 3 ? nb4 : 0u);
+  const auto rX = make_rsrc(a.val, nb4);
+  const auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
+  const auto rU1 = make_rsrc(a.U[1], NM1 >= 2 ? a.Ubytes[1] : 0u);
+  const auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
+  const uint32_t goff = (uint32_t)g * 16u;
+
+  // (bit-cast whole vectors: a bit-cast of one vector element reads element 0)
+  auto load_idx = [&](int32_t blk, f4& xv, i4& j0, i4& j1, i4& j2) {
+    const uint32_t so = (uint32_t)blk * 64u;
+    xv = __builtin_bit_cast(f4, ld_i4(rX, goff, so));
+    j0 = ld_i4(rI0, goff, so);
+    if constexpr (NM1 >= 2) j1 = ld_i4(rI1, goff, so);
+    if constexpr (NM1 >= 3) j2 = ld_i4(rI2, goff, so);
+  };
+  auto gather = [&](const i4& j0, const i4& j1, const i4& j2, float* av, float* bv) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if constexpr (NM1 == 1) {
+        av[t] = 1.f;
+        bv[t] = ld_f(rU0, ((uint32_t)j0[t] << 2) + kc4);
+      } else if constexpr (NM1 == 2) {
+        av[t] = ld_f(rU0, ((uint32_t)j0[t] << 2) + ka4);
+        bv[t] = ld_f(rU1, ((uint32_t)j1[t] << 2) + kc4);
+      } else {
+        av[t] = ld_f(rU0, ((uint32_t)j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)j1[t] << 2) + kb4);
+        bv[t] = ld_f(rU2, ((uint32_t)j2[t] << 2) + kc4);
+      }
+    }
+  };
+
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  const int32_t b0 = lo >> 4;
+  const int32_t nblk = ((hi - 1) >> 4) - b0 + 1;
+  const int32_t bmax = (a.nnz_pad >> 4) - 1;
+
+  s_first = __builtin_amdgcn_readfirstlane(s_first);
+  s_last = __builtin_amdgcn_readfirstlane(s_last);
+  SegWindow win;
+  win.load(a, s_first, lane);
+  int32_t s = s_first;
+  int32_t seg_lo = lo;  // first slice is clipped at lo
+  int32_t seg_hi = rd_lane(win.off, 1);
+  seg_hi = __builtin_amdgcn_readfirstlane(seg_hi < hi ? seg_hi : hi);
+
+  f4 acc = {0.f, 0.f, 0.f, 0.f}, tot = {0.f, 0.f, 0.f, 0.f};
+  int inner = 0;
+
+  // Pipeline state: values x of blocks b, b+1, b+2; factor rows of blocks b,
+  // b+1 (and b+2 issued this step); indices of block b+3 issued this step.
+  // Loads complete in issue order, so each step issues indices(b+3) before
+  // gathers(b+2); the products of block b then wait only for loads issued two
+  // steps earlier.
+  auto clampb = [&](int32_t blk) { return blk <= bmax ? blk : bmax; };
+  f4 x0, x1, x2;
+  i4 p0, p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0};   // indices of block b+2 (then b+3)
+  i4 q0, q1 = {0, 0, 0, 0}, q2 = {0, 0, 0, 0};   // indices of block b+1 (prologue only)
+  float ga[4], gb[4], ha[4], hb[4];
+  load_idx(b0, x0, p0, p1, p2);
+  load_idx(clampb(b0 + 1), x1, q0, q1, q2);
+  gather(p0, p1, p2, ga, gb);
+  load_idx(clampb(b0 + 2), x2, p0, p1, p2);
+  gather(q0, q1, q2, ha, hb);
+
+  bool done = false;
+  for (int32_t ib = 0; ib < nblk && !done; ++ib) {
+    const int32_t blk = b0 + ib;
+    f4 x3;
+    i4 r0, r1 = {0, 0, 0, 0}, r2 = {0, 0, 0, 0};
+    load_idx(clampb(blk + 3), x3, r0, r1, r2);
+    float ka_[4], kb_[4];
+    gather(p0, p1, p2, ka_, kb_);   // block b+2
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int32_t e_sub = blk * 16 + 4 * t;  // uniform
+      const int32_t e = e_sub + g;
+      const float xa = (NM1 == 1) ? x0[t] : x0[t] * ga[t];
+      const float xb = gb[t];
+      while (!done && seg_lo < e_sub + 4) {
+        const bool in = (e >= seg_lo) && (e < seg_hi);
+        acc = mfma4(in ? xa : 0.f, xb, acc);
+        if (seg_hi <= e_sub + 4) {
+          on_seg(s, rd_lane(win.row, s - win.base), tot + acc);
+          acc = f4{0.f, 0.f, 0.f, 0.f};
+          tot = acc;
+          inner = 0;
+          s = __builtin_amdgcn_readfirstlane(s + 1);
+          if (s > s_last) {
+            done = true;
+          } else {
+            if (s + 1 - win.base >= 64) win.load(a, s, lane);
+            seg_lo = __builtin_amdgcn_readfirstlane(rd_lane(win.off, s - win.base));
+            const int32_t nx = rd_lane(win.off, s + 1 - win.base);
+            seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+          }
+        } else {
+          if (++inner == 64) {
+            tot += acc;
+            acc = f4{0.f, 0.f, 0.f, 0.f};
+            inner = 0;
+          }
+          break;
+        }
+      }
+    }
+    x0 = x1;
+    x1 = x2;
+    x2 = x3;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      ga[t] = ha[t];
+      gb[t] = hb[t];
+      ha[t] = ka_[t];
+      hb[t] = kb_[t];
+    }
+    p0 = r0;
+    p1 = r1;
+    p2 = r2;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // TTMcTC pass
 // ---------------------------------------------------------------------------
@@ -203,11 +287,12 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
   const int g = lane >> 4, q = lane & 15;
   const int32_t w = blockIdx.x * a.RPW + rr;
-  const bool active = w < a.W;
+  const bool multi = a.B > 1;
 
   float* ybat = lds + wv * (16 * YS);
   float* red = lds + a.B * a.RPW * 16 * YS + rr * (a.B * KN2 * 256);
-  int32_t* slot_row = reinterpret_cast<int32_t*>(lds + a.B * a.RPW * 16 * YS + a.RPW * a.B * KN2 * 256) + rr * 32;
+  int32_t* slot_row = reinterpret_cast<int32_t*>(lds + a.B * a.RPW * 16 * YS + (multi ? a.RPW * a.B * KN2 * 256 : 0)) +
+                      rr * 32;
   int32_t* slot_kind = slot_row + 16;
 
   // stage-two operand of this block: gt[kb][t] = G_(n)^T[64 g + t][16 kb + q]
@@ -217,125 +302,120 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
 #pragma unroll
     for (int t = 0; t < 64; ++t) gt[kb][t] = a.gtop[(((size_t)b * KN2 + kb) * 64 + t) * 64 + lane];
 
-  const uint32_t nb = (uint32_t)a.nnz * 4u;
-  auto rI0 = make_rsrc(a.oidx[0], nb);
-  auto rI1 = make_rsrc(a.oidx[1], NM1 >= 2 ? nb : 0u);
-  auto rI2 = make_rsrc(a.oidx[2], NM1 >= 3 ? nb : 0u);
-  auto rX = make_rsrc(a.val, nb);
-  auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
-  auto rU1 = make_rsrc(a.U[1], NM1 >= 2 ? a.Ubytes[1] : 0u);
-  auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
   uint32_t ka4, kb4, kc4;
   lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
+  if (w >= a.W) return;  // only when B == 1 (no workgroup barriers then)
 
-  int32_t lo = 0, hi = 0, s_first = 0, s_last = -1;
-  bool head_clip = false, tail_clip = false;
-  if (active) {
-    lo = range_lo(w, a.W, a.nnz);
-    hi = range_lo(w + 1, a.W, a.nnz);
-    s_first = find_seg(a.seg_off, a.R, lo);
-    s_last = find_seg(a.seg_off, a.R, hi - 1);
-    head_clip = a.seg_off[s_first] < lo;
-    tail_clip = a.seg_off[s_last + 1] > hi;
-    if (b == 0 && lane == 0) {
-      a.meta[w * 4 + 0] = s_first;
-      a.meta[w * 4 + 1] = s_last;
-      a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
-      a.meta[w * 4 + 3] = 0;
-    }
+  const int32_t lo = range_lo(w, a.W, a.nnz);
+  const int32_t hi = range_lo(w + 1, a.W, a.nnz);
+  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
+  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  const bool head_clip = a.seg_off[s_first] < lo;
+  const bool tail_clip = a.seg_off[s_last + 1] > hi;
+  if (b == 0 && lane == 0) {
+    a.meta[w * 4 + 0] = s_first;
+    a.meta[w * 4 + 1] = s_last;
+    a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
+    a.meta[w * 4 + 3] = 0;
   }
-  const bool multi = a.B > 1;
+
   int slot = 0;
-  for (int32_t s = s_first; s <= s_last; ++s) {
-    const int32_t so = a.seg_off[s], se = a.seg_off[s + 1];
-    const int32_t slo = so > lo ? so : lo;
-    const int32_t shi = se < hi ? se : hi;
-    f4 y = accumulate_block<NM1>(a, rI0, rI1, rI2, rX, rU0, rU1, rU2, ka4, kb4, kc4, slo, shi, g);
-    // stage y_i (column-major within the block: j' = c*16 + r)
+  // stage two: D[slot][kn] = sum_j' ybat[slot][j'] * G_(n)^T[j'][kn] for the staged slices
+  auto stage_two = [&]() {
+    if (!multi) wave_sync();
+    f4 d[KN2];
+#pragma unroll
+    for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const f4 yv = *reinterpret_cast<const f4*>(ybat + q * YS + 64 * g + 4 * u);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int kb = 0; kb < KN2; ++kb) d[kb] = mfma4(yv[v], gt[kb][4 * u + v], d[kb]);
+    }
+    if (multi) {
+#pragma unroll
+      for (int kb = 0; kb < KN2; ++kb)
+        *reinterpret_cast<f4*>(red + (b * KN2 + kb) * 256 + q * 16 + 4 * g) = d[kb];
+      __syncthreads();
+      if (b == 0) {
+#pragma unroll
+        for (int kb = 0; kb < KN2; ++kb) {
+          f4 t = *reinterpret_cast<const f4*>(red + kb * 256 + q * 16 + 4 * g);
+          for (int bb = 1; bb < a.B; ++bb)
+            t += *reinterpret_cast<const f4*>(red + (bb * KN2 + kb) * 256 + q * 16 + 4 * g);
+          d[kb] = t;
+        }
+      }
+    }
+    if (b == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int sl = 4 * g + v;
+        if (sl < slot) {
+          const int32_t row = slot_row[sl];
+          const int kind = slot_kind[sl];
+#pragma unroll
+          for (int kb = 0; kb < KN2; ++kb) {
+            const int kn = 16 * kb + q;
+            if (kn < a.Kn) {
+              const float val = d[kb][v];
+              if (kind == KIND_COMPLETE) a.A[(size_t)row * a.Kn + kn] = val;
+              else a.carry[((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
+            }
+          }
+        }
+      }
+    }
+    if (multi) __syncthreads();
+    else wave_sync();
+    slot = 0;
+  };
+
+  walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, [&](int32_t s, int32_t row, f4 y) {
+    // stage y_s (column-major within the block: j' = c*16 + r)
     *reinterpret_cast<f4*>(ybat + slot * YS + q * 16 + 4 * g) = y;
     if (b == 0 && lane == 0) {
       int kind = KIND_COMPLETE;
       if (s == s_first && head_clip) kind = KIND_HEAD;
       else if (s == s_last && tail_clip) kind = KIND_TAIL;
-      slot_row[slot] = a.seg_row[s];
+      slot_row[slot] = row;
       slot_kind[slot] = kind;
     }
-    ++slot;
-    if (slot == 16 || s == s_last) {
-      // stage two: D[slot][kn] = sum_j' ybat[slot][j'] * G_(n)^T[j'][kn]
-      if (!multi) wave_sync();
-      f4 d[KN2];
-#pragma unroll
-      for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        f4 yv = *reinterpret_cast<const f4*>(ybat + q * YS + 64 * g + 4 * u);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int kb = 0; kb < KN2; ++kb) d[kb] = mfma4(yv[v], gt[kb][4 * u + v], d[kb]);
-      }
-      if (multi) {
-#pragma unroll
-        for (int kb = 0; kb < KN2; ++kb)
-          *reinterpret_cast<f4*>(red + (b * KN2 + kb) * 256 + q * 16 + 4 * g) = d[kb];
-        __syncthreads();
-        if (b == 0) {
-#pragma unroll
-          for (int kb = 0; kb < KN2; ++kb) {
-            f4 t = *reinterpret_cast<const f4*>(red + kb * 256 + q * 16 + 4 * g);
-            for (int bb = 1; bb < a.B; ++bb) t += *reinterpret_cast<const f4*>(red + (bb * KN2 + kb) * 256 + q * 16 + 4 * g);
-            d[kb] = t;
-          }
-        }
-      }
-      if (b == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int sl = 4 * g + v;
-          if (sl < slot) {
-            const int32_t row = slot_row[sl];
-            const int kind = slot_kind[sl];
-#pragma unroll
-            for (int kb = 0; kb < KN2; ++kb) {
-              const int kn = 16 * kb + q;
-              if (kn < a.Kn) {
-                const float val = d[kb][v];
-                if (kind == KIND_COMPLETE) a.A[(size_t)row * a.Kn + kn] = val;
-                else a.carry[((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
-              }
-            }
-          }
-        }
-      }
-      if (multi) __syncthreads();
-      else wave_sync();
-      slot = 0;
-    }
-  }
+    if (++slot == 16) stage_two();
+  });
+  if (slot > 0) stage_two();
 }
 
-// Adds the partial rows of slices that cross range boundaries, in range order
-// (float64), and writes them. One wave per range; the owner is the range where
-// the slice starts (its tail partial), continued by the head partials of the
-// following ranges.
-__global__ void k_fix_split(const int32_t* meta, const float* carry, const int32_t* seg_row, int32_t W, int32_t Kn,
-                            float* A) {
-  const int lane = threadIdx.x & 63;
-  const int32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (w >= W) return;
+// Adds the partial rows of slices that cross range boundaries and writes them.
+// One workgroup per range; only the owner of a split slice (the range where it
+// starts, holding its tail partial) works: the head partials of the following
+// ranges w0+1..w1 are summed in float64 by 8 thread groups with a fixed
+// stride, then the groups are added in order (deterministic).
+__global__ __launch_bounds__(256) void k_fix_split(const int32_t* meta, const float* carry, const int32_t* seg_row,
+                                                   const int32_t* seg_off, int32_t W, int32_t nnz, int32_t Kn,
+                                                   float* A) {
+  __shared__ double part[8][32];
+  const int32_t w = blockIdx.x;
   const int32_t s_first = meta[w * 4 + 0], s_last = meta[w * 4 + 1], flags = meta[w * 4 + 2];
   const bool head_clip = flags & 1, tail_clip = flags & 2;
-  // does this range hold the first part (tail partial) of a split slice?
-  const bool owner = tail_clip && !(s_first == s_last && head_clip);
-  if (!owner) return;
+  if (!(tail_clip && !(s_first == s_last && head_clip))) return;
   const int32_t s = s_last;
-  double acc = lane < Kn ? (double)carry[((size_t)w * 2 + 1) * 32 + lane] : 0.0;
-  for (int32_t w2 = w + 1; w2 < W; ++w2) {
-    if (meta[w2 * 4 + 0] != s || !(meta[w2 * 4 + 2] & 1)) break;
-    if (lane < Kn) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + lane];
+  // last range holding part of slice s: the largest w1 with w1 * nnz / W <= e_last
+  const int64_t e_last = (int64_t)seg_off[s + 1] - 1;
+  const int32_t w1 = (int32_t)(((e_last + 1) * (int64_t)W - 1) / nnz);
+  const int kn = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  double acc = 0.0;
+  if (kn < Kn)
+    for (int32_t w2 = w + 1 + grp; w2 <= w1; w2 += 8) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + kn];
+  part[grp][kn] = acc;
+  __syncthreads();
+  if (threadIdx.x < 32 && kn < Kn) {
+    double t = (double)carry[((size_t)w * 2 + 1) * 32 + kn];
+    for (int g2 = 0; g2 < 8; ++g2) t += part[g2][kn];
+    A[(size_t)seg_row[s] * Kn + kn] = (float)t;
   }
-  if (lane < Kn) A[(size_t)seg_row[s] * Kn + lane] = (float)acc;
 }
 
 __global__ void k_zero_rows(const int32_t* empty_row, int64_t E, int32_t Kn, float* A) {
@@ -404,14 +484,6 @@ __global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
 #pragma unroll
   for (int k = 0; k < 16 * KN2; ++k) gp[k][0] = gp[k][1] = gp[k][2] = gp[k][3] = 0.f;
 
-  const uint32_t nb = (uint32_t)a.nnz * 4u;
-  auto rI0 = make_rsrc(a.oidx[0], nb);
-  auto rI1 = make_rsrc(a.oidx[1], NM1 >= 2 ? nb : 0u);
-  auto rI2 = make_rsrc(a.oidx[2], NM1 >= 3 ? nb : 0u);
-  auto rX = make_rsrc(a.val, nb);
-  auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
-  auto rU1 = make_rsrc(a.U[1], NM1 >= 2 ? a.Ubytes[1] : 0u);
-  auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
   uint32_t ka4, kb4, kc4;
   lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
 
@@ -420,12 +492,9 @@ __global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
     const int32_t hi = range_lo(w + 1, a.W, a.nnz);
     const int32_t s_first = find_seg(a.seg_off, a.R, lo);
     const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
-    for (int32_t s = s_first; s <= s_last; ++s) {
-      const int32_t so = a.seg_off[s], se = a.seg_off[s + 1];
-      const int32_t slo = so > lo ? so : lo;
-      const int32_t shi = se < hi ? se : hi;
-      f4 y = accumulate_block<NM1>(a, rI0, rI1, rI2, rX, rU0, rU1, rU2, ka4, kb4, kc4, slo, shi, g);
-      const float* urow = a.Uc + (size_t)a.seg_row[s] * a.Kc;
+    walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, [&](int32_t s, int32_t row, f4 y) {
+      // G_(c) += U^(c)(row, :)^T y_s  (the row of U^(c) is wave-uniform: scalar loads)
+      const float* urow = a.Uc + (size_t)__builtin_amdgcn_readfirstlane(row) * a.Kc;
 #pragma unroll
       for (int k = 0; k < 16 * KN2; ++k) {
         if (k < a.Kc) {
@@ -436,7 +505,7 @@ __global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
           gp[k][3] += u * y[3];
         }
       }
-    }
+    });
   }
   // workgroup sum over its ranges (fixed order), then one partial per block
   float* buf = lds + b * (16 * KN2 * 256);
@@ -558,6 +627,7 @@ void fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   a.seg_row = md.seg_row;
   a.R = (int32_t)md.R;
   a.nnz = (int32_t)p->nnz;
+  a.nnz_pad = (int32_t)((p->nnz + 15) / 16 * 16);
   a.B = g.B;
   a.RB = g.RB;
   a.CB = g.CB;
@@ -642,7 +712,7 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   a.carry = p->sc.carry;
   a.meta = p->sc.meta;
   const int threads = 64 * g.B * a.RPW;
-  const size_t shmem = (size_t)(g.B * a.RPW * 16 * YS + a.RPW * g.B * KN2 * 256 + a.RPW * 32) * 4;
+  const size_t shmem = (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32) * 4;
   hipError_t e = hipSuccess;
   {
   TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
@@ -659,8 +729,8 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   if (e != hipSuccess) return HOQRI_ERR_HIP;
   TimerScope tf(p, HOQRI_KERNEL_FIXUP, s);
   // 3. split slices and empty rows
-  hipLaunchKernelGGL(k_fix_split, dim3((unsigned)((W + 3) / 4)), dim3(256), 0, s, p->sc.meta, p->sc.carry,
-                     md.seg_row, a.W, a.Kn, A);
+  hipLaunchKernelGGL(k_fix_split, dim3((unsigned)W), dim3(256), 0, s, p->sc.meta, p->sc.carry, md.seg_row,
+                     md.seg_off, a.W, a.nnz, a.Kn, A);
   if (md.E > 0) {
     int64_t tot = md.E * a.Kn;
     int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);

@@ -67,8 +67,11 @@ def test_planted_tucker_recovered():
     vals32 = block.ravel().astype(np.float32)
     start = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 77))]
     U, G, st, fh, Uo, Go, h = run_both(dims, K, idx, vals32, start, 2)
+    # exact in exact arithmetic; with float32 sums the subspace moves by ~kappa(A) u32 per
+    # update (kappa(A) <= 67 here). A float32 emulation of the same sums in numpy reaches
+    # d = 4.5e-8 .. 1.0e-7, so 1e-7 is the float32 bar.
     for n in range(3):
-        assert O.subspace_dist(U[n], U0t[n]) < 1e-9
+        assert O.subspace_dist(U[n], U0t[n]) < 1e-7
     # squared relative residual (fit loses half the digits near 1)
     assert (st.norm_x2 - st.f) / st.norm_x2 < 1e-5
 
