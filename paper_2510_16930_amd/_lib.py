@@ -13,7 +13,8 @@ from dataclasses import dataclass
 from typing import Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhoqri.so")
+# HOQRI_LIB may point at another build of the same library (same ABI)
+LIB_PATH = os.environ.get("HOQRI_LIB") or os.path.join(_HERE, "libhoqri.so")
 
 HOQRI_OK = 0
 STATUS = {

@@ -198,8 +198,10 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   int32_t seg_hi = rd_lane(win.off, 1);
   seg_hi = __builtin_amdgcn_readfirstlane(seg_hi < hi ? seg_hi : hi);
 
-  f4 acc = {0.f, 0.f, 0.f, 0.f}, tot = {0.f, 0.f, 0.f, 0.f};
-  int inner = 0;
+  // one accumulator per sub-step: four independent matrix-core chains
+  f4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
 
   // Pipeline state: values x of blocks b, b+1, b+2; factor rows of blocks b,
   // b+1 (and b+2 issued this step); indices of block b+3 issued this step.
@@ -218,6 +220,22 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   gather(q0, q1, q2, ha, hb);
 
   bool done = false;
+  // finishes slice s: hands y_s to the consumer and moves to the next slice
+  auto finish = [&]() {
+    const f4 y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    on_seg(s, rd_lane(win.row, s - win.base), y);
+    s = __builtin_amdgcn_readfirstlane(s + 1);
+    if (s > s_last) {
+      done = true;
+    } else {
+      if (s + 1 - win.base >= 64) win.load(a, s, lane);
+      seg_lo = __builtin_amdgcn_readfirstlane(rd_lane(win.off, s - win.base));
+      const int32_t nx = rd_lane(win.off, s + 1 - win.base);
+      seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+    }
+  };
   for (int32_t ib = 0; ib < nblk && !done; ++ib) {
     const int32_t blk = b0 + ib;
     f4 x3;
@@ -225,36 +243,26 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
     load_idx(clampb(blk + 3), x3, r0, r1, r2);
     float ka_[4], kb_[4];
     gather(p0, p1, p2, ka_, kb_);   // block b+2
+    const int32_t eb = blk * 16;    // uniform
+    float xa[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int32_t e_sub = blk * 16 + 4 * t;  // uniform
-      const int32_t e = e_sub + g;
-      const float xa = (NM1 == 1) ? x0[t] : x0[t] * ga[t];
-      const float xb = gb[t];
-      while (!done && seg_lo < e_sub + 4) {
-        const bool in = (e >= seg_lo) && (e < seg_hi);
-        acc = mfma4(in ? xa : 0.f, xb, acc);
-        if (seg_hi <= e_sub + 4) {
-          on_seg(s, rd_lane(win.row, s - win.base), tot + acc);
-          acc = f4{0.f, 0.f, 0.f, 0.f};
-          tot = acc;
-          inner = 0;
-          s = __builtin_amdgcn_readfirstlane(s + 1);
-          if (s > s_last) {
-            done = true;
-          } else {
-            if (s + 1 - win.base >= 64) win.load(a, s, lane);
-            seg_lo = __builtin_amdgcn_readfirstlane(rd_lane(win.off, s - win.base));
-            const int32_t nx = rd_lane(win.off, s + 1 - win.base);
-            seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
-          }
-        } else {
-          if (++inner == 64) {
-            tot += acc;
-            acc = f4{0.f, 0.f, 0.f, 0.f};
-            inner = 0;
-          }
-          break;
+    for (int t = 0; t < 4; ++t) xa[t] = (NM1 == 1) ? x0[t] : x0[t] * ga[t];
+    if (__builtin_expect(seg_lo <= eb && seg_hi >= eb + 16, 1)) {
+      // the whole block lies in the current slice
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = mfma4(xa[t], gb[t], acc[t]);
+      if (__builtin_expect(seg_hi == eb + 16, 0)) finish();
+    } else {
+      // a slice boundary (or the range start) falls inside the block
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int32_t e_sub = eb + 4 * t;
+        const int32_t e = e_sub + g;
+        while (!done && seg_lo < e_sub + 4) {
+          const bool in = (e >= seg_lo) && (e < seg_hi);
+          acc[t] = mfma4(in ? xa[t] : 0.f, gb[t], acc[t]);
+          if (seg_hi <= e_sub + 4) finish();
+          else break;
         }
       }
     }
