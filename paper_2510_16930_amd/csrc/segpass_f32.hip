@@ -101,18 +101,25 @@ __device__ inline int32_t find_seg(const int32_t* seg_off, int32_t R, int32_t e)
 
 __device__ inline int32_t rd_lane(int32_t v, int32_t lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// A window of the slice table held in registers: lane i has seg_off[base+i]
-// and seg_row[base+i], so a slice change reads them with readlane.
+// A window of the slice table in this wave's LDS: entry i holds seg_off[base+i]
+// and seg_row[base+i] (64 entries). Reads use a wave-uniform address; the window
+// lives in LDS so no loop-carried vector registers hold it.
 struct SegWindow {
+  int32_t* off;  // LDS [64]
+  int32_t* row;  // LDS [64]
   int32_t base;
-  int32_t off;
-  int32_t row;
   __device__ void load(const SegArgs& a, int32_t b, int lane) {
     base = __builtin_amdgcn_readfirstlane(b);
-    const int32_t i = b + lane;  // clamped, unconditional loads keep the control flow uniform
-    off = a.seg_off[i < a.R ? i : a.R];
-    row = a.seg_row[i < a.R ? i : a.R - 1];
+    const int32_t i = base + lane;  // clamped, unconditional loads keep the control flow uniform
+    const int32_t o = a.seg_off[i < a.R ? i : a.R];
+    const int32_t r = a.seg_row[i < a.R ? i : a.R - 1];
+    wave_sync();
+    off[lane] = o;
+    row[lane] = r;
+    wave_sync();
   }
+  __device__ int32_t get_off(int32_t s) const { return __builtin_amdgcn_readfirstlane(off[s - base]); }
+  __device__ int32_t get_row(int32_t s) const { return __builtin_amdgcn_readfirstlane(row[s - base]); }
 };
 
 // Per-lane byte offsets of this lane's row / column inside the gathered factor
@@ -141,13 +148,28 @@ __device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uin
 // The stream is read in aligned blocks of 16 nonzeros. Inside a block the plan
 // stores the nonzeros 4x4-transposed (physical 4g + t holds logical 4t + g), so
 // the 16-byte load of lane group g returns its k-slot for all four sub-steps;
-// sub-step t covers the 4 consecutive logical nonzeros 16b + 4t + (0..3). Each
-// matrix-core product covers one sub-step and one slice; lanes whose nonzero
-// lies outside the slice contribute zero. Factor rows of block b+1 and the
-// index/value vectors of block b+2 are in flight while block b is multiplied.
+// sub-step t covers the 4 consecutive logical nonzeros 16b + 4t + (0..3), one
+// matrix-core product each, accumulated in acc[t] (four independent chains).
+// A block inside one slice takes 4 products; a block that a slice boundary cuts
+// takes 4 masked products per slice it touches (lanes outside the slice give 0).
+//
+// Loads form a three-stage pipeline over three register sets rotated by
+// renaming (the block loop is unrolled three times): while block b is
+// multiplied, the factor rows of block b+2 and the index/value vectors of
+// block b+3 are in flight. Loads complete in issue order, so each step issues
+// the indices of b+3 before the rows of b+2 and waits only for loads issued
+// two steps earlier.
+template <int NM1>
+struct PipeSet {
+  f4 x;
+  float ga[4], gb[4];
+  i4 j0, j1, j2;
+};
+
 template <int NM1, typename OnSeg>
 __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
-                                  uint32_t ka4, uint32_t kb4, uint32_t kc4, int lane, OnSeg&& on_seg) {
+                                  uint32_t ka4, uint32_t kb4, uint32_t kc4, int lane, int32_t* wlds,
+                                  OnSeg&& on_seg) {
   const int g = lane >> 4;
   const uint32_t nb4 = (uint32_t)a.nnz_pad * 4u;
   const auto rI0 = make_rsrc(a.oidx[0], nb4);
@@ -159,126 +181,110 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   const auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
   const uint32_t goff = (uint32_t)g * 16u;
 
-  // (bit-cast whole vectors: a bit-cast of one vector element reads element 0)
-  auto load_idx = [&](int32_t blk, f4& xv, i4& j0, i4& j1, i4& j2) {
-    const uint32_t so = (uint32_t)blk * 64u;
-    xv = __builtin_bit_cast(f4, ld_i4(rX, goff, so));
-    j0 = ld_i4(rI0, goff, so);
-    if constexpr (NM1 >= 2) j1 = ld_i4(rI1, goff, so);
-    if constexpr (NM1 >= 3) j2 = ld_i4(rI2, goff, so);
-  };
-  auto gather = [&](const i4& j0, const i4& j1, const i4& j2, float* av, float* bv) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if constexpr (NM1 == 1) {
-        av[t] = 1.f;
-        bv[t] = ld_f(rU0, ((uint32_t)j0[t] << 2) + kc4);
-      } else if constexpr (NM1 == 2) {
-        av[t] = ld_f(rU0, ((uint32_t)j0[t] << 2) + ka4);
-        bv[t] = ld_f(rU1, ((uint32_t)j1[t] << 2) + kc4);
-      } else {
-        av[t] = ld_f(rU0, ((uint32_t)j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)j1[t] << 2) + kb4);
-        bv[t] = ld_f(rU2, ((uint32_t)j2[t] << 2) + kc4);
-      }
-    }
-  };
-
   lo = __builtin_amdgcn_readfirstlane(lo);
   hi = __builtin_amdgcn_readfirstlane(hi);
+  s_first = __builtin_amdgcn_readfirstlane(s_first);
+  s_last = __builtin_amdgcn_readfirstlane(s_last);
   const int32_t b0 = lo >> 4;
   const int32_t nblk = ((hi - 1) >> 4) - b0 + 1;
   const int32_t bmax = (a.nnz_pad >> 4) - 1;
 
-  s_first = __builtin_amdgcn_readfirstlane(s_first);
-  s_last = __builtin_amdgcn_readfirstlane(s_last);
+  // (bit-cast whole vectors: a bit-cast of one vector element reads element 0)
+  auto load_idx = [&](int32_t blk, PipeSet<NM1>& S) {
+    blk = blk <= bmax ? blk : bmax;
+    const uint32_t so = (uint32_t)blk * 64u;
+    S.x = __builtin_bit_cast(f4, ld_i4(rX, goff, so));
+    S.j0 = ld_i4(rI0, goff, so);
+    if constexpr (NM1 >= 2) S.j1 = ld_i4(rI1, goff, so);
+    if constexpr (NM1 >= 3) S.j2 = ld_i4(rI2, goff, so);
+  };
+  auto gather = [&](PipeSet<NM1>& S) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if constexpr (NM1 == 1) {
+        S.ga[t] = 1.f;
+        S.gb[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + kc4);
+      } else if constexpr (NM1 == 2) {
+        S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4);
+        S.gb[t] = ld_f(rU1, ((uint32_t)S.j1[t] << 2) + kc4);
+      } else {
+        S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)S.j1[t] << 2) + kb4);
+        S.gb[t] = ld_f(rU2, ((uint32_t)S.j2[t] << 2) + kc4);
+      }
+    }
+  };
+
   SegWindow win;
+  win.off = wlds;
+  win.row = wlds + 64;
   win.load(a, s_first, lane);
   int32_t s = s_first;
   int32_t seg_lo = lo;  // first slice is clipped at lo
-  int32_t seg_hi = rd_lane(win.off, 1);
+  int32_t seg_hi = win.get_off(s_first + 1);
   seg_hi = __builtin_amdgcn_readfirstlane(seg_hi < hi ? seg_hi : hi);
-
-  // one accumulator per sub-step: four independent matrix-core chains
   f4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-
-  // Pipeline state: values x of blocks b, b+1, b+2; factor rows of blocks b,
-  // b+1 (and b+2 issued this step); indices of block b+3 issued this step.
-  // Loads complete in issue order, so each step issues indices(b+3) before
-  // gathers(b+2); the products of block b then wait only for loads issued two
-  // steps earlier.
-  auto clampb = [&](int32_t blk) { return blk <= bmax ? blk : bmax; };
-  f4 x0, x1, x2;
-  i4 p0, p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0};   // indices of block b+2 (then b+3)
-  i4 q0, q1 = {0, 0, 0, 0}, q2 = {0, 0, 0, 0};   // indices of block b+1 (prologue only)
-  float ga[4], gb[4], ha[4], hb[4];
-  load_idx(b0, x0, p0, p1, p2);
-  load_idx(clampb(b0 + 1), x1, q0, q1, q2);
-  gather(p0, p1, p2, ga, gb);
-  load_idx(clampb(b0 + 2), x2, p0, p1, p2);
-  gather(q0, q1, q2, ha, hb);
-
   bool done = false;
-  // finishes slice s: hands y_s to the consumer and moves to the next slice
-  auto finish = [&]() {
-    const f4 y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+
+  // block `blk` with set C (current), set N2 (block blk+2: gather now);
+  // set C then receives the indices of block blk+3
+  auto step = [&](int32_t blk, PipeSet<NM1>& C, PipeSet<NM1>& N2) {
+    float xa[4], xb[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-    on_seg(s, rd_lane(win.row, s - win.base), y);
-    s = __builtin_amdgcn_readfirstlane(s + 1);
-    if (s > s_last) {
-      done = true;
-    } else {
-      if (s + 1 - win.base >= 64) win.load(a, s, lane);
-      seg_lo = __builtin_amdgcn_readfirstlane(rd_lane(win.off, s - win.base));
-      const int32_t nx = rd_lane(win.off, s + 1 - win.base);
-      seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+    for (int t = 0; t < 4; ++t) {
+      xa[t] = (NM1 == 1) ? C.x[t] : C.x[t] * C.ga[t];
+      xb[t] = C.gb[t];
     }
-  };
-  for (int32_t ib = 0; ib < nblk && !done; ++ib) {
-    const int32_t blk = b0 + ib;
-    f4 x3;
-    i4 r0, r1 = {0, 0, 0, 0}, r2 = {0, 0, 0, 0};
-    load_idx(clampb(blk + 3), x3, r0, r1, r2);
-    float ka_[4], kb_[4];
-    gather(p0, p1, p2, ka_, kb_);   // block b+2
-    const int32_t eb = blk * 16;    // uniform
-    float xa[4];
+    load_idx(blk + 3, C);
+    gather(N2);
+    const int32_t eb = blk * 16;  // uniform
+    if (__builtin_expect(seg_lo <= eb && seg_hi > eb + 16, 1)) {
+      // the slice continues past this block
 #pragma unroll
-    for (int t = 0; t < 4; ++t) xa[t] = (NM1 == 1) ? x0[t] : x0[t] * ga[t];
-    if (__builtin_expect(seg_lo <= eb && seg_hi >= eb + 16, 1)) {
-      // the whole block lies in the current slice
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = mfma4(xa[t], gb[t], acc[t]);
-      if (__builtin_expect(seg_hi == eb + 16, 0)) finish();
+      for (int t = 0; t < 4; ++t) acc[t] = mfma4(xa[t], xb[t], acc[t]);
     } else {
-      // a slice boundary (or the range start) falls inside the block
+      // every slice touching the block: 4 masked products each
+      while (!done && seg_lo < eb + 16) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int32_t e_sub = eb + 4 * t;
-        const int32_t e = e_sub + g;
-        while (!done && seg_lo < e_sub + 4) {
+        for (int t = 0; t < 4; ++t) {
+          const int32_t e = eb + 4 * t + g;
           const bool in = (e >= seg_lo) && (e < seg_hi);
-          acc[t] = mfma4(in ? xa[t] : 0.f, gb[t], acc[t]);
-          if (seg_hi <= e_sub + 4) finish();
-          else break;
+          acc[t] = mfma4(in ? xa[t] : 0.f, xb[t], acc[t]);
+        }
+        if (seg_hi > eb + 16) break;  // continues into the next block
+        // slice s ends in this block
+        const f4 y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+        on_seg(s, win.get_row(s), y);
+        s = __builtin_amdgcn_readfirstlane(s + 1);
+        if (s > s_last) {
+          done = true;
+        } else {
+          if (s + 1 - win.base >= 64) win.load(a, s, lane);
+          seg_lo = win.get_off(s);
+          const int32_t nx = win.get_off(s + 1);
+          seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
         }
       }
     }
-    x0 = x1;
-    x1 = x2;
-    x2 = x3;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      ga[t] = ha[t];
-      gb[t] = hb[t];
-      ha[t] = ka_[t];
-      hb[t] = kb_[t];
-    }
-    p0 = r0;
-    p1 = r1;
-    p2 = r2;
+  };
+
+  PipeSet<NM1> S0, S1, S2;
+  S0.j1 = S0.j2 = S1.j1 = S1.j2 = S2.j1 = S2.j2 = i4{0, 0, 0, 0};
+  load_idx(b0, S0);
+  load_idx(b0 + 1, S1);
+  load_idx(b0 + 2, S2);
+  gather(S0);
+  gather(S1);
+  for (int32_t ib = 0; ib < nblk; ib += 3) {
+    step(b0 + ib, S0, S2);
+    if (done || ib + 1 >= nblk) break;
+    step(b0 + ib + 1, S1, S0);
+    if (done || ib + 2 >= nblk) break;
+    step(b0 + ib + 2, S2, S1);
+    if (done) break;
   }
 }
 
@@ -299,9 +305,10 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
 
   float* ybat = lds + wv * (16 * YS);
   float* red = lds + a.B * a.RPW * 16 * YS + rr * (a.B * KN2 * 256);
-  int32_t* slot_row = reinterpret_cast<int32_t*>(lds + a.B * a.RPW * 16 * YS + (multi ? a.RPW * a.B * KN2 * 256 : 0)) +
-                      rr * 32;
+  int32_t* slot_base = reinterpret_cast<int32_t*>(lds + a.B * a.RPW * 16 * YS + (multi ? a.RPW * a.B * KN2 * 256 : 0));
+  int32_t* slot_row = slot_base + rr * 32;
   int32_t* slot_kind = slot_row + 16;
+  int32_t* wlds = slot_base + a.RPW * 32 + wv * 128;  // slice-table window of this wave
 
   // stage-two operand of this block: gt[kb][t] = G_(n)^T[64 g + t][16 kb + q]
   float gt[KN2][64];
@@ -381,7 +388,7 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
     slot = 0;
   };
 
-  walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, [&](int32_t s, int32_t row, f4 y) {
+  walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
     // stage y_s (column-major within the block: j' = c*16 + r)
     *reinterpret_cast<f4*>(ybat + slot * YS + q * 16 + 4 * g) = y;
     if (b == 0 && lane == 0) {
@@ -487,10 +494,12 @@ __global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
   const int g = lane >> 4, q = lane & 15;
   const int32_t w = blockIdx.x * a.RPW + rr;
-
-  float gp[16 * KN2][4];
-#pragma unroll
-  for (int k = 0; k < 16 * KN2; ++k) gp[k][0] = gp[k][1] = gp[k][2] = gp[k][3] = 0.f;
+  constexpr int KC = 16 * KN2;
+  // this wave's partial G_(c)[kc][j'] for its block, in LDS (no loop-carried
+  // registers): 16*KN2 x 256 floats, this lane owns j' = q*16 + 4g + 0..3
+  float* gw = lds + wv * (KC * 256);
+  int32_t* wlds = reinterpret_cast<int32_t*>(lds + a.RPW * a.B * (KC * 256)) + wv * 128;
+  for (int k = 0; k < KC; ++k) *reinterpret_cast<f4*>(gw + k * 256 + q * 16 + 4 * g) = f4{0.f, 0.f, 0.f, 0.f};
 
   uint32_t ka4, kb4, kc4;
   lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
@@ -500,38 +509,26 @@ __global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
     const int32_t hi = range_lo(w + 1, a.W, a.nnz);
     const int32_t s_first = find_seg(a.seg_off, a.R, lo);
     const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
-    walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, [&](int32_t s, int32_t row, f4 y) {
+    walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
       // G_(c) += U^(c)(row, :)^T y_s  (the row of U^(c) is wave-uniform: scalar loads)
       const float* urow = a.Uc + (size_t)__builtin_amdgcn_readfirstlane(row) * a.Kc;
-#pragma unroll
-      for (int k = 0; k < 16 * KN2; ++k) {
-        if (k < a.Kc) {
-          const float u = urow[k];
-          gp[k][0] += u * y[0];
-          gp[k][1] += u * y[1];
-          gp[k][2] += u * y[2];
-          gp[k][3] += u * y[3];
-        }
+      for (int k = 0; k < a.Kc; ++k) {
+        const float u = urow[k];
+        f4* dst = reinterpret_cast<f4*>(gw + k * 256 + q * 16 + 4 * g);
+        *dst = *dst + u * y;
       }
     });
   }
-  // workgroup sum over its ranges (fixed order), then one partial per block
-  float* buf = lds + b * (16 * KN2 * 256);
-  for (int r2 = 0; r2 < a.RPW; ++r2) {
-    if (rr == r2) {
-#pragma unroll
-      for (int k = 0; k < 16 * KN2; ++k) {
-        f4* dst = reinterpret_cast<f4*>(buf + k * 256 + q * 16 + 4 * g);
-        f4 v = {gp[k][0], gp[k][1], gp[k][2], gp[k][3]};
-        if (r2 == 0) *dst = v;
-        else *dst = *dst + v;
-      }
-    }
-    __syncthreads();
-  }
-  const int total = a.B * 16 * KN2 * 256;
+  __syncthreads();
+  // workgroup sum over its ranges (fixed order) for each block, one partial per block
+  const int total = a.B * KC * 256;
   float* out = a.gpart + (size_t)blockIdx.x * total;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) out[t] = lds[t];
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int bb = t / (KC * 256), rest = t - bb * (KC * 256);
+    float v = 0.f;
+    for (int r2 = 0; r2 < a.RPW; ++r2) v += lds[(r2 * a.B + bb) * (KC * 256) + rest];
+    out[t] = v;
+  }
 }
 
 struct CoreRedArgs {
@@ -720,7 +717,8 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   a.carry = p->sc.carry;
   a.meta = p->sc.meta;
   const int threads = 64 * g.B * a.RPW;
-  const size_t shmem = (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32) * 4;
+  const size_t shmem =
+      (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 + g.B * a.RPW * 128) * 4;
   hipError_t e = hipSuccess;
   {
   TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
@@ -755,7 +753,12 @@ hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, dou
   const int KN2 = (p->K[mode] + 15) / 16;
   SegArgs a{};
   fill_common(a, p, mode, g, U);
-  a.RPW = g.B >= 8 ? 1 : 8 / g.B;
+  // each wave keeps its partial (16*KN2 x 256 floats) in LDS: at most 160 KB per workgroup
+  const int per_wave = 16 * KN2 * 256 * 4 + 128 * 4;
+  int rpw = (160 * 1024) / (per_wave * g.B);
+  if (rpw > 8) rpw = 8;
+  if (rpw < 1) return HOQRI_ERR_UNSUPPORTED;
+  a.RPW = rpw;
   int64_t groups = p->core_groups;
   int64_t W = groups * a.RPW;
   if (W > p->nnz) {
@@ -767,7 +770,7 @@ hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, dou
   a.Kc = p->K[mode];
   a.gpart = p->sc.gpart;
   const int threads = 64 * g.B * a.RPW;
-  const size_t shmem = (size_t)g.B * 16 * KN2 * 256 * 4;
+  const size_t shmem = (size_t)a.RPW * g.B * per_wave;
   hipError_t e = hipSuccess;
   {
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
