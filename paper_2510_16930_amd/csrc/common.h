@@ -37,7 +37,9 @@ struct ModeData {
   float* val;          // values in mode-n sorted order
   int32_t* seg_row;    // [R]   mode-n index of each nonempty slice (ascending)
   int32_t* seg_off;    // [R+1] first nonzero of each slice in sorted order
-  int32_t* empty_row;  // [E]   mode-n indices whose slice is empty
+  int32_t* lab;        // [I_n] new label of original index i (descending slice size)
+  int32_t* inv;        // [I_n] original index of label r
+  int32_t* empty_row;  // [E]   original indices of the empty slices (= inv + R)
   int64_t R;           // number of nonempty slices
   int64_t E;           // number of empty slices (I_n - R)
   int32_t ranges;      // work ranges of the segment passes on this mode
@@ -45,6 +47,7 @@ struct ModeData {
 
 // Scratch regions used by the passes (all inside the caller's workspace).
 struct Scratch {
+  float* Up[kMaxOrder];  // factors with rows in the plan's label order
   float* A;            // max_n I_n * K_n floats: TTMcTC output inside hoqri_run
   float* G;            // prod K floats: the core inside hoqri_run
   float* gpart;        // core partials: core_groups * pad_core floats
@@ -109,8 +112,11 @@ hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, in
 // Segment-pass kernels (segpass_f32.hip).
 hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, double* f_out,
                              hipStream_t s);
+// U: factors in the plan's label order. out_map null: A rows in label order and
+// rows R..I-1 zeroed; otherwise row r is written at out_map[r] (original order)
+// and the empty slices' original rows are zeroed.
 hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, const float* G,
-                               float* A, hipStream_t s);
+                               float* A, const int32_t* out_map, hipStream_t s);
 bool segpass_supported(const hoqri_plan* p, int mode);
 
 // CholeskyQR2 (orth.hip).

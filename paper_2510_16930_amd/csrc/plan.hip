@@ -128,6 +128,16 @@ __global__ void k_sum_final(const double* part, int nparts, double* out) {
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// Keys i_n in the order given by lperm; values are canonical positions.
+__global__ void k_mode_keys_perm(const int32_t* cidx_n, const int32_t* lperm, int64_t nnz, uint32_t* k32,
+                                 int32_t* perm) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = lperm[j];
+    k32[j] = (uint32_t)cidx_n[c];
+    perm[j] = c;
+  }
+}
+
 __global__ void k_mode_keys(const int32_t* cidx_n, int64_t nnz, uint32_t* k32, int32_t* perm) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
        j += (int64_t)gridDim.x * blockDim.x) {
@@ -146,6 +156,7 @@ struct GatherArgs {
   int32_t* oidx[kMaxOrder - 1];
   float* val;
   int32_t* modeidx;
+  const int32_t* lab[kMaxOrder];  // label maps: stored offsets and slice rows use labels
 };
 
 // Mode-n sorted copy: other-mode factor offsets i_m * K_m, values, and i_n.
@@ -168,11 +179,11 @@ __global__ void k_gather_mode(GatherArgs a) {
     int64_t src = a.perm ? a.perm[j] : j;
     int c = 0;
     for (int m = 0; m < a.N; ++m) {
-      int32_t i = a.cidx[(int64_t)m * a.stride + src];
+      const int32_t i = a.cidx[(int64_t)m * a.stride + src];
       if (m == a.mode) {
-        a.modeidx[j] = i;
+        a.modeidx[j] = i;  // original index: slice boundaries
       } else {
-        a.oidx[c++][pj] = i * a.K[m];
+        a.oidx[c++][pj] = a.lab[m][i] * a.K[m];
       }
     }
     a.val[pj] = a.cval[src];
@@ -180,11 +191,11 @@ __global__ void k_gather_mode(GatherArgs a) {
 }
 
 __global__ void k_segments(const int32_t* modeidx, const int32_t* head, const int32_t* sid, int64_t nnz,
-                           int32_t* seg_row, int32_t* seg_off, int64_t* R_out) {
+                           const int32_t* lab, int32_t* seg_row, int32_t* seg_off, int64_t* R_out) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz;
        j += (int64_t)gridDim.x * blockDim.x) {
     if (head[j]) {
-      seg_row[sid[j]] = modeidx[j];
+      seg_row[sid[j]] = lab[modeidx[j]];
       seg_off[sid[j]] = (int32_t)j;
     }
     if (j == nnz - 1) {
@@ -195,23 +206,49 @@ __global__ void k_segments(const int32_t* modeidx, const int32_t* head, const in
   }
 }
 
+// Slice sizes (degrees) of every mode-n index; integer atomics, exact.
+__global__ void k_degree(const int32_t* cidx_n, int64_t nnz, int32_t* deg) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&deg[cidx_n[j]], 1);
+}
+
+// Sort keys for the relabelling: larger degree first; the stable sort keeps
+// equal degrees in index order.
+__global__ void k_degree_keys(const int32_t* deg, int64_t In, uint32_t* key, int32_t* idx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < In; i += (int64_t)gridDim.x * blockDim.x) {
+    key[i] = 0x7FFFFFFFu - (uint32_t)deg[i];
+    idx[i] = (int32_t)i;
+  }
+}
+
+struct LabKeyArgs {
+  const int32_t* cidx;  // [N][stride]
+  int64_t stride, nnz;
+  int32_t N;
+  const int32_t* lab[kMaxOrder];
+  uint64_t lstride[kMaxOrder];
+};
+
+// C-order linear key of each nonzero's label coordinates; position as value.
+__global__ void k_label_keys(LabKeyArgs a, uint64_t* keys, int32_t* pos) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < a.nnz; j += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t k = 0;
+    for (int m = 0; m < a.N; ++m) k += (uint64_t)a.lab[m][a.cidx[(int64_t)m * a.stride + j]] * a.lstride[m];
+    keys[j] = k;
+    pos[j] = (int32_t)j;
+  }
+}
+
+// lab[inv[r]] = r
+__global__ void k_invert(const int32_t* inv, int64_t In, int32_t* lab) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < In; r += (int64_t)gridDim.x * blockDim.x)
+    lab[inv[r]] = (int32_t)r;
+}
+
 __global__ void k_fill_i32(int32_t* x, int64_t n, int32_t v) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x)
     x[j] = v;
-}
-
-__global__ void k_mark_rows(const int32_t* seg_row, const int64_t* R_dev, int32_t* notempty_inv) {
-  int64_t R = *R_dev;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < R;
-       s += (int64_t)gridDim.x * blockDim.x)
-    notempty_inv[seg_row[s]] = 0;  // array starts at 1 (= empty)
-}
-
-__global__ void k_empty_rows(const int32_t* is_empty, const int32_t* pos, int64_t In, int32_t* empty_row) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < In;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (is_empty[i]) empty_row[pos[i]] = (int32_t)i;
 }
 
 // Workspace carving ---------------------------------------------------------
@@ -232,7 +269,7 @@ size_t sort_tmp_bytes(int64_t nnz, int64_t Imax, hipError_t* err) {
                                    (int32_t*)nullptr, (size_t)nnz, 0, 64, (hipStream_t)0);
   if (*err != hipSuccess) return 0;
   *err = rocprim::radix_sort_pairs(nullptr, b32, (uint32_t*)nullptr, (uint32_t*)nullptr, (int32_t*)nullptr,
-                                   (int32_t*)nullptr, (size_t)nnz, 0, 32, (hipStream_t)0);
+                                   (int32_t*)nullptr, (size_t)(nnz > Imax ? nnz : Imax), 0, 32, (hipStream_t)0);
   if (*err != hipSuccess) return 0;
   *err = rocprim::exclusive_scan(nullptr, bs, (int32_t*)nullptr, (int32_t*)nullptr, 0, (size_t)nnz,
                                  rocprim::plus<int32_t>(), (hipStream_t)0);
@@ -317,7 +354,8 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     int64_t rmax = dims[n] < nnz ? dims[n] : nnz;
     c.take<int32_t>(rmax);
     c.take<int32_t>(rmax + 1);
-    c.take<int32_t>(dims[n]);
+    c.take<int32_t>(dims[n]);  // lab
+    c.take<int32_t>(dims[n]);  // inv
   }
   size_t persistent = c.off;
   // build temporaries
@@ -334,6 +372,8 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   b.take<int32_t>(nnz);
   b.take<int32_t>(Imax);
   b.take<int32_t>(Imax);
+  b.take<uint32_t>(Imax);
+  b.take<uint32_t>(Imax);
   b.take<double>(65536);
   b.take<int64_t>(64);
   b.take<char>(stmp);
@@ -360,7 +400,10 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     if (L->ranges[n] > rmax) rmax = L->ranges[n];
   }
   L->core_groups = groups;
+  int64_t IKsum = 0;
+  for (int n = 0; n < N; ++n) IKsum += dims[n] * K[n];
   Carver r{nullptr, 0};
+  for (int n = 0; n < N; ++n) r.take<float>(dims[n] * K[n]);  // row-relabelled factors
   r.take<float>(IKmax);                 // A
   r.take<float>(PK);                    // G
   r.take<float>((size_t)groups * gpart);// core partials
@@ -413,7 +456,8 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
     int64_t rmax = p->dims[n] < nnz_in ? p->dims[n] : nnz_in;
     md.seg_row = c.take<int32_t>(rmax);
     md.seg_off = c.take<int32_t>(rmax + 1);
-    md.empty_row = c.take<int32_t>(p->dims[n]);
+    md.lab = c.take<int32_t>(p->dims[n]);
+    md.inv = c.take<int32_t>(p->dims[n]);
   }
   // build temporaries (after the persistent region)
   Carver b{(char*)p->ws + L.persistent, 0};
@@ -429,6 +473,8 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   int32_t* modeidx = b.take<int32_t>(nnz_in);
   int32_t* flag_i = b.take<int32_t>(Imax);
   int32_t* scan_i = b.take<int32_t>(Imax);
+  uint32_t* lkey = b.take<uint32_t>(Imax);
+  uint32_t* lkey_s = b.take<uint32_t>(Imax);
   double* dpart = b.take<double>(65536);
   int64_t* small = b.take<int64_t>(64);
   void* stmp = b.take<char>(L.sort_tmp);
@@ -476,23 +522,61 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   p->nnz = nnz;
   p->normx2 = nx2;
 
-  // 3. per mode: stable sort by i_n, sorted copy, slice table, empty rows
+  // 3. label every mode's indices by descending slice size (ties by index):
+  //    factor rows are kept in label order inside the passes, so hot rows are
+  //    contiguous in memory and empty slices take the last labels; the sorted
+  //    streams below keep the original index order, so heavy and light slices
+  //    stay mixed along each stream
+  for (int n = 0; n < N; ++n) {
+    ModeData& md = p->md[n];
+    const int64_t In = p->dims[n];
+    const int32_t* cn = cidx + (int64_t)n * nnz_in;
+    k_fill_i32<<<grid_for(In), kThreads, 0, s>>>(flag_i, In, 0);
+    k_degree<<<grid_for(nnz), kThreads, 0, s>>>(cn, nnz, flag_i);
+    k_degree_keys<<<grid_for(In), kThreads, 0, s>>>(flag_i, In, lkey, scan_i);
+    tb = L.sort_tmp;
+    HOQRI_HIP_TRY(rocprim::radix_sort_pairs(stmp, tb, lkey, lkey_s, scan_i, md.inv, (size_t)In, 0, 31, s));
+    k_invert<<<grid_for(In), kThreads, 0, s>>>(md.inv, In, md.lab);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+
+  // 4. order the merged nonzeros by their label coordinates (C order): inside
+  //    every slice of every mode the nonzeros then come hot rows first, grouped
+  //    by row, which is what the gathers of the segment passes want
+  int32_t* lperm = reinterpret_cast<int32_t*>(vsq);  // the squares are summed already: reuse their storage
+  {
+    LabKeyArgs la{};
+    la.cidx = cidx;
+    la.stride = nnz_in;
+    la.nnz = nnz;
+    la.N = N;
+    uint64_t st = 1;
+    for (int m = N - 1; m >= 0; --m) {
+      la.lab[m] = p->md[m].lab;
+      la.lstride[m] = st;
+      st *= (uint64_t)p->dims[m];
+    }
+    k_label_keys<<<grid_for(nnz), kThreads, 0, s>>>(la, keys, pos);
+    tb = L.sort_tmp;
+    HOQRI_HIP_TRY(rocprim::radix_sort_pairs(stmp, tb, keys, keys_s, pos, lperm, (size_t)nnz, 0, bits_for(st), s));
+  }
+
+  // 5. per mode: stable sort of that order by the original i_n (slice order
+  //    stays the original index order), sorted copy (labels), slice table
   uint32_t* k32 = reinterpret_cast<uint32_t*>(keys);
   uint32_t* k32s = reinterpret_cast<uint32_t*>(keys_s);
   for (int n = 0; n < N; ++n) {
     ModeData& md = p->md[n];
-    const int32_t* perm = nullptr;
-    if (n > 0) {  // canonical order is already sorted by mode 0
-      k_mode_keys<<<grid_for(nnz), kThreads, 0, s>>>(cidx + (int64_t)n * nnz_in, nnz, k32, pos);
-      tb = L.sort_tmp;
-      HOQRI_HIP_TRY(rocprim::radix_sort_pairs(stmp, tb, k32, k32s, pos, pos_s, (size_t)nnz, 0,
-                                              bits_for((uint64_t)p->dims[n]), s));
-      perm = pos_s;
-    }
+    k_mode_keys_perm<<<grid_for(nnz), kThreads, 0, s>>>(cidx + (int64_t)n * nnz_in, lperm, nnz, k32, pos);
+    tb = L.sort_tmp;
+    HOQRI_HIP_TRY(rocprim::radix_sort_pairs(stmp, tb, k32, k32s, pos, pos_s, (size_t)nnz, 0,
+                                            bits_for((uint64_t)p->dims[n]), s));
+    const int32_t* perm = pos_s;
     GatherArgs ga{};
     ga.cidx = cidx;
     ga.cval = cval;
     ga.perm = perm;
+    for (int m = 0; m < N; ++m) ga.lab[m] = p->md[m].lab;
     ga.stride = nnz_in;
     ga.nnz = nnz;
     ga.N = N;
@@ -505,14 +589,8 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
     k_head_flags<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, nnz, head);
     tb = L.sort_tmp;
     HOQRI_HIP_TRY(rocprim::exclusive_scan(stmp, tb, head, uid, 0, (size_t)nnz, rocprim::plus<int32_t>(), s));
-    k_segments<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, head, uid, nnz, md.seg_row, md.seg_off,
+    k_segments<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, head, uid, nnz, md.lab, md.seg_row, md.seg_off,
                                                     small + 2 + n);
-    k_fill_i32<<<grid_for(p->dims[n]), kThreads, 0, s>>>(flag_i, p->dims[n], 1);
-    k_mark_rows<<<grid_for(nnz), kThreads, 0, s>>>(md.seg_row, small + 2 + n, flag_i);
-    tb = L.sort_tmp;
-    HOQRI_HIP_TRY(rocprim::exclusive_scan(stmp, tb, flag_i, scan_i, 0, (size_t)p->dims[n],
-                                          rocprim::plus<int32_t>(), s));
-    k_empty_rows<<<grid_for(p->dims[n]), kThreads, 0, s>>>(flag_i, scan_i, p->dims[n], md.empty_row);
     HOQRI_HIP_TRY(hipGetLastError());
   }
   int64_t Rh[kMaxOrder];
@@ -523,6 +601,7 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   for (int n = 0; n < N; ++n) {
     p->md[n].R = Rh[n];
     p->md[n].E = p->dims[n] - Rh[n];
+    p->md[n].empty_row = p->md[n].inv + Rh[n];  // original indices of the empty slices
     p->md[n].ranges = L.ranges[n];
     // core pass cost on mode n ~ nnz / K_n + R_n (per unit prod K)
     double cost = (double)nnz / p->K[n] + (double)Rh[n];
@@ -554,6 +633,7 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
   for (int n = 0; n < p->N; ++n)
     if (L.ranges[n] > rmax) rmax = L.ranges[n];
   Carver r{(char*)p->ws + L.persistent, 0};
+  for (int n = 0; n < p->N; ++n) p->sc.Up[n] = r.take<float>(p->dims[n] * p->K[n]);
   p->sc.A = r.take<float>(IKmax);
   p->sc.G = r.take<float>(PK);
   p->sc.gpart = r.take<float>((size_t)L.core_groups * gpart);

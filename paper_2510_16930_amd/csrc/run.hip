@@ -33,6 +33,44 @@ hoqri_status check_plan(const hoqri_plan* p) {
   return HOQRI_OK;
 }
 
+// Up[r, :] = U[inv[r], :] (rows into the plan's label order)
+__global__ void k_rows_to_labels(const float* U, const int32_t* inv, int64_t I, int32_t K, float* Up) {
+  const int64_t total = I * K;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / K;
+    Up[t] = U[(size_t)inv[r] * K + (t - r * K)];
+  }
+}
+
+// U[inv[r], :] = Up[r, :] (rows back to the caller's order)
+__global__ void k_rows_from_labels(const float* Up, const int32_t* inv, int64_t I, int32_t K, float* U) {
+  const int64_t total = I * K;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / K;
+    U[(size_t)inv[r] * K + (t - r * K)] = Up[t];
+  }
+}
+
+__global__ void k_fill_f32(float* x, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+int grid_of(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
+}
+
+hoqri_status to_labels(hoqri_plan* p, const float* const* U, hipStream_t s) {
+  for (int n = 0; n < p->N; ++n) {
+    const int64_t I = p->dims[n];
+    hipLaunchKernelGGL(k_rows_to_labels, dim3(grid_of(I * p->K[n])), dim3(256), 0, s, U[n], p->md[n].inv, I, p->K[n],
+                       p->sc.Up[n]);
+  }
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
 hoqri_status check_prec(hoqri_prec prec) {
   if (prec == HOQRI_FP32) return HOQRI_OK;
   if (prec == HOQRI_BF16 || prec == HOQRI_FP16) return HOQRI_ERR_UNSUPPORTED;
@@ -51,7 +89,8 @@ extern "C" hoqri_status hoqri_core(hoqri_plan* p, const float* const* d_U, float
   for (int n = 0; n < p->N; ++n)
     if (!d_U[n]) return HOQRI_ERR_ARG;
   HOQRI_TRY(check_prec(prec));
-  return launch_core_f32(p, d_U, d_G, d_f, stream);
+  HOQRI_TRY(to_labels(p, d_U, stream));
+  return launch_core_f32(p, p->sc.Up, d_G, d_f, stream);
 }
 
 extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* const* d_U, const float* d_G,
@@ -61,7 +100,8 @@ extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* c
   for (int n = 0; n < p->N; ++n)
     if (!d_U[n]) return HOQRI_ERR_ARG;
   HOQRI_TRY(check_prec(prec));
-  return launch_ttmctc_f32(p, mode, d_U, d_G, d_A, stream);
+  HOQRI_TRY(to_labels(p, d_U, stream));
+  return launch_ttmctc_f32(p, mode, p->sc.Up, d_G, d_A, p->md[mode].inv, stream);
 }
 
 extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
@@ -77,7 +117,6 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
 
   const int N = p->N;
-  const float* const* U = d_U_inout;
   int32_t* status = p->sc.status;
   double* fsw = p->sc.fsweep;
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, status, 4, 0);
@@ -88,8 +127,13 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       HOQRI_TRY(launch_orth(p->dims[n], p->K[n], d_U_inout[n], d_U_inout[n], nullptr, status, p->sc.orth_ws,
                             p->sc.orth_ws_bytes, stream, true));
   }
+  // the loop works on row-relabelled copies of the factors (label order)
+  for (int n = 0; n < N; ++n)
+    if (p->md[n].R < p->K[n]) return HOQRI_ERR_BREAKDOWN;  // fewer nonempty slices than K_n
+  HOQRI_TRY(to_labels(p, d_U_inout, stream));
+  float* const* Up = p->sc.Up;
   // core of the starting factors
-  HOQRI_TRY(launch_core_f32(p, U, d_G_out, fsw + 0, stream));
+  HOQRI_TRY(launch_core_f32(p, Up, d_G_out, fsw + 0, stream));
 
   int T = 0;
   double f_last = 0.0, f_prev = 0.0, rel = 0.0;
@@ -98,14 +142,21 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     for (int n = 0; n < N; ++n) {
       if (n > 0) {
         double* fdst = d_f_hist ? d_f_hist + (size_t)t * N + n : p->sc.f_dev;
-        HOQRI_TRY(launch_core_f32(p, U, d_G_out, fdst, stream));
+        HOQRI_TRY(launch_core_f32(p, Up, d_G_out, fdst, stream));
       }
-      HOQRI_TRY(launch_ttmctc_f32(p, n, U, d_G_out, p->sc.A, stream));
+      HOQRI_TRY(launch_ttmctc_f32(p, n, Up, d_G_out, p->sc.A, nullptr, stream));
+      // rows R_n.. of A are zero (empty slices): orthonormalise the first R_n rows
+      // and keep the remaining rows of the factor at zero
+      const int64_t Rn = p->md[n].R;
       TimerScope to(p, HOQRI_KERNEL_ORTH, stream);
-      HOQRI_TRY(launch_orth(p->dims[n], p->K[n], p->sc.A, d_U_inout[n], nullptr, status, p->sc.orth_ws,
-                            p->sc.orth_ws_bytes, stream, true));
+      HOQRI_TRY(launch_orth(Rn, p->K[n], p->sc.A, Up[n], nullptr, status, p->sc.orth_ws, p->sc.orth_ws_bytes,
+                            stream, true));
+      if (p->dims[n] > Rn) {
+        const int64_t ne = (p->dims[n] - Rn) * p->K[n];
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(ne)), dim3(256), 0, stream, Up[n] + Rn * p->K[n], ne, 0.f);
+      }
     }
-    HOQRI_TRY(launch_core_f32(p, U, d_G_out, fsw + t + 1, stream));
+    HOQRI_TRY(launch_core_f32(p, Up, d_G_out, fsw + t + 1, stream));
     T = t + 1;
     if (T % opts->check_every == 0 || T == opts->max_sweeps) {
       double fv[2];
@@ -125,7 +176,12 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     hipLaunchKernelGGL(k_hist_first, dim3(1), dim3(256), 0, stream, fsw, T, N, d_f_hist);
     HOQRI_HIP_TRY(hipGetLastError());
   }
-  // final statistics
+  // factors back to the caller's row order, then final statistics
+  if (T > 0)
+    for (int n = 0; n < N; ++n)
+      hipLaunchKernelGGL(k_rows_from_labels, dim3(grid_of(p->dims[n] * p->K[n])), dim3(256), 0, stream, Up[n],
+                         p->md[n].inv, p->dims[n], p->K[n], d_U_inout[n]);
+  HOQRI_HIP_TRY(hipGetLastError());
   double errs[kMaxOrder] = {0, 0, 0, 0};
   for (int n = 0; n < N; ++n)
     HOQRI_TRY(launch_orth_err(p->dims[n], p->K[n], d_U_inout[n], p->sc.f_dev + 8 + n, p->sc.orth_ws,

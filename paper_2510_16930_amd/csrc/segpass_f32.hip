@@ -81,6 +81,7 @@ struct SegArgs {
   int32_t Kn;
   float* carry;             // [W][2][32]
   int32_t* meta;            // [W][4]
+  const int32_t* out_map;   // null: A rows in label order; else row r goes to out_map[r]
   // core
   const float* Uc;          // factor of the pass mode
   int32_t Kc;
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
       int kind = KIND_COMPLETE;
       if (s == s_first && head_clip) kind = KIND_HEAD;
       else if (s == s_last && tail_clip) kind = KIND_TAIL;
-      slot_row[slot] = row;
+      slot_row[slot] = a.out_map ? a.out_map[row] : row;
       slot_kind[slot] = kind;
     }
     if (++slot == 16) stage_two();
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
 // stride, then the groups are added in order (deterministic).
 __global__ __launch_bounds__(256) void k_fix_split(const int32_t* meta, const float* carry, const int32_t* seg_row,
                                                    const int32_t* seg_off, int32_t W, int32_t nnz, int32_t Kn,
-                                                   float* A) {
+                                                   const int32_t* out_map, float* A) {
   __shared__ double part[8][32];
   const int32_t w = blockIdx.x;
   const int32_t s_first = meta[w * 4 + 0], s_last = meta[w * 4 + 1], flags = meta[w * 4 + 2];
@@ -429,15 +430,19 @@ __global__ __launch_bounds__(256) void k_fix_split(const int32_t* meta, const fl
   if (threadIdx.x < 32 && kn < Kn) {
     double t = (double)carry[((size_t)w * 2 + 1) * 32 + kn];
     for (int g2 = 0; g2 < 8; ++g2) t += part[g2][kn];
-    A[(size_t)seg_row[s] * Kn + kn] = (float)t;
+    const int32_t row = out_map ? out_map[seg_row[s]] : seg_row[s];
+    A[(size_t)row * Kn + kn] = (float)t;
   }
 }
 
-__global__ void k_zero_rows(const int32_t* empty_row, int64_t E, int32_t Kn, float* A) {
+// Zeroes the rows of empty slices: empty_row[r] (original order) or, with a
+// null list, the contiguous label-order rows row0 .. row0+E-1.
+__global__ void k_zero_rows(const int32_t* empty_row, int64_t row0, int64_t E, int32_t Kn, float* A) {
   const int64_t total = E * Kn;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = t / Kn;
-    A[(size_t)empty_row[r] * Kn + (t - r * Kn)] = 0.f;
+    const int64_t row = empty_row ? empty_row[r] : row0 + r;
+    A[(size_t)row * Kn + (t - r * Kn)] = 0.f;
   }
 }
 
@@ -674,7 +679,7 @@ bool segpass_supported(const hoqri_plan* p, int mode) {
 }
 
 hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, const float* G, float* A,
-                               hipStream_t s) {
+                               const int32_t* out_map, hipStream_t s) {
   if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
@@ -716,6 +721,7 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   a.Kn = p->K[mode];
   a.carry = p->sc.carry;
   a.meta = p->sc.meta;
+  a.out_map = out_map;
   const int threads = 64 * g.B * a.RPW;
   const size_t shmem =
       (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 + g.B * a.RPW * 128) * 4;
@@ -736,11 +742,12 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   TimerScope tf(p, HOQRI_KERNEL_FIXUP, s);
   // 3. split slices and empty rows
   hipLaunchKernelGGL(k_fix_split, dim3((unsigned)W), dim3(256), 0, s, p->sc.meta, p->sc.carry, md.seg_row,
-                     md.seg_off, a.W, a.nnz, a.Kn, A);
+                     md.seg_off, a.W, a.nnz, a.Kn, out_map, A);
   if (md.E > 0) {
     int64_t tot = md.E * a.Kn;
     int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
-    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, md.empty_row, md.E, a.Kn, A);
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, out_map ? md.empty_row : (const int32_t*)nullptr,
+                       md.R, md.E, a.Kn, A);
   }
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
