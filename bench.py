@@ -38,6 +38,14 @@ CONFIGS = {
     "c3f32": dict(dims=(1_000_000, 500_000, 20_000), ranks=(32, 32, 32), nnz=50_000_000, dist="zipf", alpha=1.2,
                   values="lognormal", seed=12, init_seed=113, prec="fp32",
                   desc="c2 tensor at ranks 32^3, FP32 form"),
+    "c3": dict(dims=(1_000_000, 500_000, 20_000), ranks=(32, 32, 32), nnz=50_000_000, dist="zipf", alpha=1.2,
+               values="lognormal", seed=12, init_seed=113, prec="bf16",
+               desc="c2 tensor at ranks 32^3, Kronecker x core products in BF16 on MFMA, FP32 accumulation, "
+                    "FP64 CholeskyQR2"),
+    "c4": dict(dims=(200_000, 200_000, 5_000, 1_000), ranks=(10, 10, 10, 10), nnz=100_000_000, dist="zipf",
+               alpha=1.1, values="uniform", seed=14, init_seed=114, prec="fp16",
+               desc="4-way 2e5 x 2e5 x 5e3 x 1e3, nnz 100M, Zipf(1.1), uniform(0,1) values, ranks 10^4, "
+                    "FP16 MFMA form (power-of-two scaled), FP32 accumulation"),
     "c4f32": dict(dims=(200_000, 200_000, 5_000, 1_000), ranks=(10, 10, 10, 10), nnz=100_000_000, dist="zipf",
                   alpha=1.1, values="uniform", seed=14, init_seed=114, prec="fp32",
                   desc="4-way 2e5 x 2e5 x 5e3 x 1e3, nnz 100M, Zipf(1.1), uniform(0,1) values, ranks 10^4, FP32 form"),
@@ -168,7 +176,7 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved_flops / PEAK[prec], 4),
         "traffic": None,
-        "kernel": "k_ttm_f32 (TTMcTC segment pass)",
+        "kernel": f"k_ttm<{prec}> (TTMcTC segment pass)",
         "launches": ttm_launch,
         "avg_launch_ms": round(ttm_ms / max(ttm_launch, 1), 4),
         "algorithmic_flops_per_launch": int(ttm_flops / max(ttm_launch, 1)),

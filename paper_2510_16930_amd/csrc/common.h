@@ -48,6 +48,7 @@ struct ModeData {
 // Scratch regions used by the passes (all inside the caller's workspace).
 struct Scratch {
   float* Up[kMaxOrder];  // factors with rows in the plan's label order
+  uint16_t* Uh[kMaxOrder];  // 16-bit copies of Up (bfloat16, or float16 scaled by 2^15)
   float* A;            // max_n I_n * K_n floats: TTMcTC output inside hoqri_run
   float* G;            // prod K floats: the core inside hoqri_run
   float* gpart;        // core partials: core_groups * pad_core floats
@@ -82,6 +83,7 @@ struct hoqri_plan {
   int64_t nnz_in;      // coordinates given
   int64_t nnz;         // distinct coordinates after merging duplicates
   double normx2;       // ||X||^2 (float64)
+  double maxabs_x;     // max |x| over the merged nonzeros
   int32_t core_mode;   // mode whose sorted copy the core pass reads (fewest slices)
   int32_t core_groups; // workgroups of the core pass (partials to reduce)
   hoqri::ModeData md[hoqri::kMaxOrder];
@@ -109,15 +111,27 @@ struct Layout {
 hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L);
 hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz);
 
-// Segment-pass kernels (segpass_f32.hip).
-hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, double* f_out,
-                             hipStream_t s);
-// U: factors in the plan's label order. out_map null: A rows in label order and
-// rows R..I-1 zeroed; otherwise row r is written at out_map[r] (original order)
-// and the empty slices' original rows are zeroed.
-hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, const float* G,
-                               float* A, const int32_t* out_map, hipStream_t s);
+// Segment-pass kernels (segpass.hip). Factors are in the plan's label order:
+// U32 float32 (always; the core pass multiplies by its pass mode's factor in
+// float32), U16 the 16-bit copies read by the BF16 / FP16 forms.
+enum OperandPrec { OP_FP32 = 0, OP_BF16 = 1, OP_FP16 = 2 };
+struct Operands {
+  int prec;  // OperandPrec
+  const float* const* U32;
+  const uint16_t* const* U16;
+};
+hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, hipStream_t s);
+// out_map null: A rows in label order and rows R..I-1 zeroed; otherwise row r is
+// written at out_map[r] (original order) and the empty slices' original rows
+// are zeroed.
+hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
+                           const int32_t* out_map, hipStream_t s);
 bool segpass_supported(const hoqri_plan* p, int mode);
+// Power-of-two scales of the FP16 form for this plan (false: the values' range
+// does not allow them; use another precision).
+bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale);
+// Rounds rows [0, rows) of a float32 factor (K columns) to the 16-bit copy.
+hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s);
 
 // CholeskyQR2 (orth.hip).
 size_t orth_ws_bytes(int64_t rows, int32_t cols);

@@ -4,6 +4,7 @@
 //
 // Integer and sort dominated; runs once per tensor. Sorting uses rocPRIM's
 // stable radix sort; every other step is a small kernel of this file.
+#include <cmath>
 #include <cstring>
 #include <cstdlib>
 #include <new>
@@ -123,6 +124,36 @@ __global__ void k_sum_final(const double* part, int nparts, double* out) {
   __syncthreads();
   for (int s = kThreads / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Per-block maxima of x (non-negative values, e.g. squares), then the maximum.
+__global__ void k_max_partial(const double* x, const int64_t* n_dev, double* part) {
+  __shared__ double sh[kThreads];
+  int64_t n = *n_dev;
+  double m = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, x[e]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_max_final(const double* part, int nparts, double* out) {
+  __shared__ double sh[kThreads];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, part[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];
@@ -404,6 +435,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   for (int n = 0; n < N; ++n) IKsum += dims[n] * K[n];
   Carver r{nullptr, 0};
   for (int n = 0; n < N; ++n) r.take<float>(dims[n] * K[n]);  // row-relabelled factors
+  for (int n = 0; n < N; ++n) r.take<uint16_t>(dims[n] * K[n]);  // their 16-bit copies
   r.take<float>(IKmax);                 // A
   r.take<float>(PK);                    // G
   r.take<float>((size_t)groups * gpart);// core partials
@@ -512,15 +544,19 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   int np = grid_for(nnz_in, kThreads, 1024);
   k_sum_partial<<<np, kThreads, 0, s>>>(vsq, small, dpart);
   k_sum_final<<<1, kThreads, 0, s>>>(dpart, np, (double*)(small + 1));
+  k_max_partial<<<np, kThreads, 0, s>>>(vsq, small, dpart);
+  k_max_final<<<1, kThreads, 0, s>>>(dpart, np, (double*)(small + 16));
   HOQRI_HIP_TRY(hipGetLastError());
-  int64_t hsmall[2];
-  HOQRI_HIP_TRY(hipMemcpyAsync(hsmall, small, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  int64_t hsmall[17];
+  HOQRI_HIP_TRY(hipMemcpyAsync(hsmall, small, 17 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HOQRI_HIP_TRY(hipStreamSynchronize(s));
   const int64_t nnz = hsmall[0];
-  double nx2;
+  double nx2, mx2;
   std::memcpy(&nx2, &hsmall[1], sizeof(double));
+  std::memcpy(&mx2, &hsmall[16], sizeof(double));
   p->nnz = nnz;
   p->normx2 = nx2;
+  p->maxabs_x = std::sqrt(mx2);
 
   // 3. label every mode's indices by descending slice size (ties by index):
   //    factor rows are kept in label order inside the passes, so hot rows are
@@ -634,6 +670,7 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
     if (L.ranges[n] > rmax) rmax = L.ranges[n];
   Carver r{(char*)p->ws + L.persistent, 0};
   for (int n = 0; n < p->N; ++n) p->sc.Up[n] = r.take<float>(p->dims[n] * p->K[n]);
+  for (int n = 0; n < p->N; ++n) p->sc.Uh[n] = r.take<uint16_t>(p->dims[n] * p->K[n]);
   p->sc.A = r.take<float>(IKmax);
   p->sc.G = r.take<float>(PK);
   p->sc.gpart = r.take<float>((size_t)L.core_groups * gpart);

@@ -71,10 +71,28 @@ hoqri_status to_labels(hoqri_plan* p, const float* const* U, hipStream_t s) {
   return HOQRI_OK;
 }
 
-hoqri_status check_prec(hoqri_prec prec) {
-  if (prec == HOQRI_FP32) return HOQRI_OK;
-  if (prec == HOQRI_BF16 || prec == HOQRI_FP16) return HOQRI_ERR_UNSUPPORTED;
-  return HOQRI_ERR_ARG;
+hoqri_status check_prec(hoqri_prec prec, int* op) {
+  if (prec == HOQRI_FP32) *op = OP_FP32;
+  else if (prec == HOQRI_BF16) *op = OP_BF16;
+  else if (prec == HOQRI_FP16) *op = OP_FP16;
+  else return HOQRI_ERR_ARG;
+  return HOQRI_OK;
+}
+
+// Operands of the segment passes: the plan's label-order factors and, for the
+// 16-bit forms, their copies refreshed from rows [0, R_m) (only rows of
+// nonempty slices are ever gathered).
+Operands plan_operands(hoqri_plan* p, int op) {
+  Operands o;
+  o.prec = op;
+  o.U32 = p->sc.Up;
+  o.U16 = p->sc.Uh;
+  return o;
+}
+
+hoqri_status refresh16(hoqri_plan* p, int op, int mode, hipStream_t s) {
+  if (op == OP_FP32) return HOQRI_OK;
+  return launch_cast16(p->sc.Up[mode], p->md[mode].R, p->K[mode], p->sc.Uh[mode], op, s);
 }
 
 }  // namespace
@@ -88,9 +106,11 @@ extern "C" hoqri_status hoqri_core(hoqri_plan* p, const float* const* d_U, float
   if (!d_U || !d_G) return HOQRI_ERR_ARG;
   for (int n = 0; n < p->N; ++n)
     if (!d_U[n]) return HOQRI_ERR_ARG;
-  HOQRI_TRY(check_prec(prec));
+  int op = 0;
+  HOQRI_TRY(check_prec(prec, &op));
   HOQRI_TRY(to_labels(p, d_U, stream));
-  return launch_core_f32(p, p->sc.Up, d_G, d_f, stream);
+  for (int n = 0; n < p->N; ++n) HOQRI_TRY(refresh16(p, op, n, stream));
+  return launch_core(p, plan_operands(p, op), d_G, d_f, stream);
 }
 
 extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* const* d_U, const float* d_G,
@@ -99,9 +119,12 @@ extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* c
   if (mode < 0 || mode >= p->N || !d_U || !d_G || !d_A) return HOQRI_ERR_ARG;
   for (int n = 0; n < p->N; ++n)
     if (!d_U[n]) return HOQRI_ERR_ARG;
-  HOQRI_TRY(check_prec(prec));
+  int op = 0;
+  HOQRI_TRY(check_prec(prec, &op));
   HOQRI_TRY(to_labels(p, d_U, stream));
-  return launch_ttmctc_f32(p, mode, p->sc.Up, d_G, d_A, p->md[mode].inv, stream);
+  for (int n = 0; n < p->N; ++n)
+    if (n != mode) HOQRI_TRY(refresh16(p, op, n, stream));
+  return launch_ttmctc(p, mode, plan_operands(p, op), d_G, d_A, p->md[mode].inv, stream);
 }
 
 extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
@@ -112,9 +135,14 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     if (!d_U_inout[n]) return HOQRI_ERR_ARG;
   if (opts->max_sweeps < 0 || opts->max_sweeps > kMaxSweeps || opts->check_every < 1 || !(opts->tol >= 0.0))
     return HOQRI_ERR_ARG;
-  HOQRI_TRY(check_prec(opts->prec));
+  int op = 0;
+  HOQRI_TRY(check_prec(opts->prec, &op));
   for (int n = 0; n < p->N; ++n)
     if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
+  if (op == OP_FP16) {
+    float as, ys;
+    if (!fp16_scales(p, p->N - 1, &as, &ys)) return HOQRI_ERR_UNSUPPORTED;
+  }
 
   const int N = p->N;
   int32_t* status = p->sc.status;
@@ -132,8 +160,10 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     if (p->md[n].R < p->K[n]) return HOQRI_ERR_BREAKDOWN;  // fewer nonempty slices than K_n
   HOQRI_TRY(to_labels(p, d_U_inout, stream));
   float* const* Up = p->sc.Up;
+  const Operands ops = plan_operands(p, op);
+  for (int n = 0; n < N; ++n) HOQRI_TRY(refresh16(p, op, n, stream));
   // core of the starting factors
-  HOQRI_TRY(launch_core_f32(p, Up, d_G_out, fsw + 0, stream));
+  HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + 0, stream));
 
   int T = 0;
   double f_last = 0.0, f_prev = 0.0, rel = 0.0;
@@ -142,9 +172,9 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     for (int n = 0; n < N; ++n) {
       if (n > 0) {
         double* fdst = d_f_hist ? d_f_hist + (size_t)t * N + n : p->sc.f_dev;
-        HOQRI_TRY(launch_core_f32(p, Up, d_G_out, fdst, stream));
+        HOQRI_TRY(launch_core(p, ops, d_G_out, fdst, stream));
       }
-      HOQRI_TRY(launch_ttmctc_f32(p, n, Up, d_G_out, p->sc.A, nullptr, stream));
+      HOQRI_TRY(launch_ttmctc(p, n, ops, d_G_out, p->sc.A, nullptr, stream));
       // rows R_n.. of A are zero (empty slices): orthonormalise the first R_n rows
       // and keep the remaining rows of the factor at zero
       const int64_t Rn = p->md[n].R;
@@ -155,8 +185,9 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
         const int64_t ne = (p->dims[n] - Rn) * p->K[n];
         hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(ne)), dim3(256), 0, stream, Up[n] + Rn * p->K[n], ne, 0.f);
       }
+      HOQRI_TRY(refresh16(p, op, n, stream));
     }
-    HOQRI_TRY(launch_core_f32(p, Up, d_G_out, fsw + t + 1, stream));
+    HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + t + 1, stream));
     T = t + 1;
     if (T % opts->check_every == 0 || T == opts->max_sweeps) {
       double fv[2];
@@ -172,6 +203,9 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       if (opts->tol > 0.0 && std::fabs(f_last - f_prev) <= opts->tol * f_last) break;
     }
   }
+  // the returned core and f are those of the final factors with float32
+  // operands, whatever form the sweeps used
+  if (op != OP_FP32) HOQRI_TRY(launch_core(p, plan_operands(p, OP_FP32), d_G_out, fsw + T, stream));
   if (d_f_hist && T > 0) {
     hipLaunchKernelGGL(k_hist_first, dim3(1), dim3(256), 0, stream, fsw, T, N, d_f_hist);
     HOQRI_HIP_TRY(hipGetLastError());

@@ -1,5 +1,12 @@
-// Segment passes for TTMcTC and the core, float32 operands on the gfx950
-// float32 matrix cores (v_mfma_f32_16x16x4f32), float32 accumulation.
+// Segment passes for TTMcTC and the core on the gfx950 matrix cores, float32
+// accumulation, in three operand precisions for the Kronecker products:
+//   FP32: float32 factor rows, v_mfma_f32_16x16x4f32 (4 nonzeros per product);
+//   BF16: bfloat16 factor copies, v_mfma_f32_16x16x16_bf16 (16 nonzeros);
+//   FP16: float16 factor copies scaled by 2^15 (entries of a factor with
+//         orthonormal columns are at most 1), v_mfma_f32_16x16x16_f16; the
+//         value-times-row operand is scaled by a power of two chosen from
+//         max|x| so it cannot overflow, and y is unscaled exactly afterwards.
+// The product of y_i with the core (stage two) is float32 in all three.
 //
 // Both passes walk a copy of the nonzeros sorted by one mode n and, for every
 // nonempty slice i (the index set I^(n)_i of Table 1), form
@@ -25,6 +32,8 @@
 // (rows > 16 or columns > 16); then each block is handled by its own wave of
 // the workgroup and the TTMcTC partial products are added in LDS.
 #include "common.h"
+
+#include <cmath>
 
 namespace hoqri {
 namespace {
@@ -61,6 +70,35 @@ __device__ inline f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+
+constexpr int P_FP32 = 0, P_BF16 = 1, P_FP16 = 2;
+
+__device__ inline uint32_t ld_u16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+// 16-bit factor entry (raw bits) to float32
+template <int PREC>
+__device__ inline float f16bits_to_f32(uint32_t b) {
+  if constexpr (PREC == P_BF16) return __builtin_bit_cast(float, b << 16);
+  else return (float)__builtin_bit_cast(_Float16, (unsigned short)b);
+}
+// one 16x16x16 product: a[t] (float32, rounded to nearest even here) against
+// b[t] (16-bit raw bits), k-slot 4g + t of lane group g
+template <int PREC>
+__device__ inline f4 mfma16(const float* a, const uint32_t* b, f4 c) {
+  const s4 bv = {(short)b[0], (short)b[1], (short)b[2], (short)b[3]};
+  if constexpr (PREC == P_BF16) {
+    const b4 av = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, av), bv, c, 0, 0, 0);
+  } else {
+    const h4 av = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, __builtin_bit_cast(h4, bv), c, 0, 0, 0);
+  }
+}
+
 struct SegArgs {
   const int32_t* oidx[3];   // other-mode element offsets (i_m * K_m), mode-sorted
   const float* val;
@@ -72,8 +110,10 @@ struct SegArgs {
   int32_t W;                // ranges
   int32_t B, RB, CB;        // y_i blocks (16x16) per range, as RB x CB
   int32_t RPW;              // ranges per workgroup
-  const float* U[3];        // factors of the other modes, ascending
+  const void* U[3];         // factors of the other modes (float32 or 16-bit copies), ascending
   uint32_t Ubytes[3];
+  float ascale;             // FP16: power of two applied to x * (row factors) before rounding
+  float yscale;             // 16-bit forms: exact unscale of y
   int32_t K1;               // rank of the second other mode (row split for N = 4)
   // TTMcTC
   const float* gtop;        // stage-two operand [B][KN2][64][64]
@@ -127,19 +167,20 @@ struct SegWindow {
 // rows, for block (rb, cb). Padded rows/columns read finite neighbouring data
 // (or 0 beyond the buffer); their products land in padded entries of y_i that
 // the stage-two operand zeroes and the core pass never stores.
-template <int NM1>
+template <int NM1, int PREC>
 __device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uint32_t* ka4, uint32_t* kb4,
                                     uint32_t* kc4) {
+  const uint32_t es = PREC == P_FP32 ? 4u : 2u;  // bytes per factor entry
   const int r = 16 * rb + q;
   const int c = 16 * cb + q;
   if constexpr (NM1 == 3) {
-    *ka4 = (uint32_t)(r / a.K1) * 4u;
-    *kb4 = (uint32_t)(r % a.K1) * 4u;
+    *ka4 = (uint32_t)(r / a.K1) * es;
+    *kb4 = (uint32_t)(r % a.K1) * es;
   } else {
-    *ka4 = (uint32_t)r * 4u;
+    *ka4 = (uint32_t)r * es;
     *kb4 = 0;
   }
-  *kc4 = (uint32_t)c * 4u;
+  *kc4 = (uint32_t)c * es;
 }
 
 // Walks nonzeros [lo, hi) of the sorted stream (slices s_first..s_last, clipped
@@ -163,11 +204,12 @@ __device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uin
 template <int NM1>
 struct PipeSet {
   f4 x;
-  float ga[4], gb[4];
+  float ga[4];     // row-factor part of the A operand (float32)
+  uint32_t gb[4];  // column-factor entry: float32 bits, or 16-bit raw bits
   i4 j0, j1, j2;
 };
 
-template <int NM1, typename OnSeg>
+template <int NM1, int PREC, typename OnSeg>
 __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
                                   uint32_t ka4, uint32_t kb4, uint32_t kc4, int lane, int32_t* wlds,
                                   OnSeg&& on_seg) {
@@ -199,18 +241,33 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
     if constexpr (NM1 >= 2) S.j1 = ld_i4(rI1, goff, so);
     if constexpr (NM1 >= 3) S.j2 = ld_i4(rI2, goff, so);
   };
+  // element offset j + k of a factor row: byte offset (j + k) * esize
   auto gather = [&](PipeSet<NM1>& S) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      if constexpr (NM1 == 1) {
-        S.ga[t] = 1.f;
-        S.gb[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + kc4);
-      } else if constexpr (NM1 == 2) {
-        S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4);
-        S.gb[t] = ld_f(rU1, ((uint32_t)S.j1[t] << 2) + kc4);
-      } else {
-        S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)S.j1[t] << 2) + kb4);
-        S.gb[t] = ld_f(rU2, ((uint32_t)S.j2[t] << 2) + kc4);
+      if constexpr (PREC == P_FP32) {
+        if constexpr (NM1 == 1) {
+          S.ga[t] = 1.f;
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU0, ((uint32_t)S.j0[t] << 2) + kc4, 0, 0);
+        } else if constexpr (NM1 == 2) {
+          S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU1, ((uint32_t)S.j1[t] << 2) + kc4, 0, 0);
+        } else {
+          S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)S.j1[t] << 2) + kb4);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU2, ((uint32_t)S.j2[t] << 2) + kc4, 0, 0);
+        }
+      } else {  // 16-bit copies: offsets in 2-byte units (ka4 etc. hold 2 * k here)
+        if constexpr (NM1 == 1) {
+          S.ga[t] = 1.f;
+          S.gb[t] = ld_u16(rU0, ((uint32_t)S.j0[t] << 1) + kc4);
+        } else if constexpr (NM1 == 2) {
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)S.j0[t] << 1) + ka4));
+          S.gb[t] = ld_u16(rU1, ((uint32_t)S.j1[t] << 1) + kc4);
+        } else {
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)S.j0[t] << 1) + ka4)) *
+                    f16bits_to_f32<PREC>(ld_u16(rU1, ((uint32_t)S.j1[t] << 1) + kb4));
+          S.gb[t] = ld_u16(rU2, ((uint32_t)S.j2[t] << 1) + kc4);
+        }
       }
     }
   };
@@ -229,33 +286,47 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   bool done = false;
 
   // block `blk` with set C (current), set N2 (block blk+2: gather now);
-  // set C then receives the indices of block blk+3
-  auto step = [&](int32_t blk, PipeSet<NM1>& C, PipeSet<NM1>& N2) {
-    float xa[4], xb[4];
+  // set C then receives the indices of block blk+3. FP32: four products per
+  // block (sub-steps t, chains acc[t]); 16-bit: one product per block, chain
+  // acc[ci] (ci = position in the three-step unroll).
+  auto step = [&](int32_t blk, PipeSet<NM1>& C, PipeSet<NM1>& N2, const int ci) {
+    float xa[4];
+    uint32_t xb[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      xa[t] = (NM1 == 1) ? C.x[t] : C.x[t] * C.ga[t];
+      // FP16: the scale goes first, so no intermediate can exceed the bound
+      const float xv = (PREC == P_FP16) ? C.x[t] * a.ascale : C.x[t];
+      xa[t] = (NM1 == 1) ? xv : xv * C.ga[t];
       xb[t] = C.gb[t];
     }
     load_idx(blk + 3, C);
     gather(N2);
     const int32_t eb = blk * 16;  // uniform
+    auto product = [&](const float* av) {
+      if constexpr (PREC == P_FP32) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = mfma4(av[t], __builtin_bit_cast(float, xb[t]), acc[t]);
+      } else {
+        acc[ci] = mfma16<PREC>(av, xb, acc[ci]);
+      }
+    };
     if (__builtin_expect(seg_lo <= eb && seg_hi > eb + 16, 1)) {
       // the slice continues past this block
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = mfma4(xa[t], xb[t], acc[t]);
+      product(xa);
     } else {
-      // every slice touching the block: 4 masked products each
+      // every slice touching the block: masked products (lanes outside give 0)
       while (!done && seg_lo < eb + 16) {
+        float am[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int32_t e = eb + 4 * t + g;
-          const bool in = (e >= seg_lo) && (e < seg_hi);
-          acc[t] = mfma4(in ? xa[t] : 0.f, xb[t], acc[t]);
+          am[t] = (e >= seg_lo && e < seg_hi) ? xa[t] : 0.f;
         }
+        product(am);
         if (seg_hi > eb + 16) break;  // continues into the next block
         // slice s ends in this block
-        const f4 y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        f4 y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        if constexpr (PREC != P_FP32) y *= a.yscale;
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
         on_seg(s, win.get_row(s), y);
@@ -280,11 +351,11 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   gather(S0);
   gather(S1);
   for (int32_t ib = 0; ib < nblk; ib += 3) {
-    step(b0 + ib, S0, S2);
+    step(b0 + ib, S0, S2, 0);
     if (done || ib + 1 >= nblk) break;
-    step(b0 + ib + 1, S1, S0);
+    step(b0 + ib + 1, S1, S0, 1);
     if (done || ib + 2 >= nblk) break;
-    step(b0 + ib + 2, S2, S1);
+    step(b0 + ib + 2, S2, S1, 2);
     if (done) break;
   }
 }
@@ -292,8 +363,8 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
 // ---------------------------------------------------------------------------
 // TTMcTC pass
 // ---------------------------------------------------------------------------
-template <int NM1, int KN2>
-__global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -319,7 +390,7 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
     for (int t = 0; t < 64; ++t) gt[kb][t] = a.gtop[(((size_t)b * KN2 + kb) * 64 + t) * 64 + lane];
 
   uint32_t ka4, kb4, kc4;
-  lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
+  lane_offsets<NM1, PREC>(a, rb, cb, q, &ka4, &kb4, &kc4);
   if (w >= a.W) return;  // only when B == 1 (no workgroup barriers then)
 
   const int32_t lo = range_lo(w, a.W, a.nnz);
@@ -389,7 +460,7 @@ __global__ __launch_bounds__(512) void k_ttm_f32(SegArgs a) {
     slot = 0;
   };
 
-  walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
+  walk_range<NM1, PREC>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
     // stage y_s (column-major within the block: j' = c*16 + r)
     *reinterpret_cast<f4*>(ybat + slot * YS + q * 16 + 4 * g) = y;
     if (b == 0 && lane == 0) {
@@ -489,8 +560,8 @@ __global__ void k_prep_gtop(PrepArgs p) {
 // ---------------------------------------------------------------------------
 // Core pass
 // ---------------------------------------------------------------------------
-template <int NM1, int KN2>
-__global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_core(SegArgs a) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -507,14 +578,14 @@ __global__ __launch_bounds__(512) void k_core_f32(SegArgs a) {
   for (int k = 0; k < KC; ++k) *reinterpret_cast<f4*>(gw + k * 256 + q * 16 + 4 * g) = f4{0.f, 0.f, 0.f, 0.f};
 
   uint32_t ka4, kb4, kc4;
-  lane_offsets<NM1>(a, rb, cb, q, &ka4, &kb4, &kc4);
+  lane_offsets<NM1, PREC>(a, rb, cb, q, &ka4, &kb4, &kc4);
 
   if (w < a.W) {
     const int32_t lo = range_lo(w, a.W, a.nnz);
     const int32_t hi = range_lo(w + 1, a.W, a.nnz);
     const int32_t s_first = find_seg(a.seg_off, a.R, lo);
     const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
-    walk_range<NM1>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
+    walk_range<NM1, PREC>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
       // G_(c) += U^(c)(row, :)^T y_s  (the row of U^(c) is wave-uniform: scalar loads)
       const float* urow = a.Uc + (size_t)__builtin_amdgcn_readfirstlane(row) * a.Kc;
       for (int k = 0; k < a.Kc; ++k) {
@@ -624,14 +695,18 @@ PassGeom geom(const hoqri_plan* p, int mode) {
   return g;
 }
 
-void fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, const float* const* U) {
+bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, const Operands& op) {
   const ModeData& md = p->md[mode];
+  const int es = op.prec == OP_FP32 ? 4 : 2;
   for (int c = 0; c < 3; ++c) {
     a.oidx[c] = c < g.nm1 ? md.oidx[c] : md.oidx[0];
     const int m = c < g.nm1 ? g.om[c] : g.om[0];
-    a.U[c] = U[m];
-    a.Ubytes[c] = (uint32_t)(p->dims[m] * p->K[m] * 4);
+    a.U[c] = op.prec == OP_FP32 ? (const void*)op.U32[m] : (const void*)op.U16[m];
+    a.Ubytes[c] = (uint32_t)(p->dims[m] * p->K[m] * es);
   }
+  a.ascale = 1.f;
+  a.yscale = 1.f;
+  if (op.prec == OP_FP16 && !fp16_scales(p, g.nm1, &a.ascale, &a.yscale)) return false;
   a.val = md.val;
   a.seg_off = md.seg_off;
   a.seg_row = md.seg_row;
@@ -642,11 +717,12 @@ void fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   a.RB = g.RB;
   a.CB = g.CB;
   a.K1 = g.nm1 >= 2 ? g.Ko[1] : 1;
+  return true;
 }
 
-template <int NM1, int KN2>
+template <int NM1, int KN2, int PREC>
 hipError_t launch_ttm_t(const SegArgs& a, int threads, size_t shmem, hipStream_t s) {
-  auto k = k_ttm_f32<NM1, KN2>;
+  auto k = k_ttm<NM1, KN2, PREC>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   const int grid = (a.W + a.RPW - 1) / a.RPW;
@@ -654,13 +730,52 @@ hipError_t launch_ttm_t(const SegArgs& a, int threads, size_t shmem, hipStream_t
   return hipGetLastError();
 }
 
-template <int NM1, int KN2>
+template <int NM1, int KN2, int PREC>
 hipError_t launch_core_t(const SegArgs& a, int grid, int threads, size_t shmem, hipStream_t s) {
-  auto k = k_core_f32<NM1, KN2>;
+  auto k = k_core<NM1, KN2, PREC>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid), dim3(threads), shmem, s, a);
   return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t dispatch_ttm(int sel, const SegArgs& a, int threads, size_t shmem, hipStream_t s) {
+  switch (sel) {
+    case 11: return launch_ttm_t<1, 1, PREC>(a, threads, shmem, s);
+    case 12: return launch_ttm_t<1, 2, PREC>(a, threads, shmem, s);
+    case 21: return launch_ttm_t<2, 1, PREC>(a, threads, shmem, s);
+    case 22: return launch_ttm_t<2, 2, PREC>(a, threads, shmem, s);
+    case 31: return launch_ttm_t<3, 1, PREC>(a, threads, shmem, s);
+    case 32: return launch_ttm_t<3, 2, PREC>(a, threads, shmem, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int PREC>
+hipError_t dispatch_core(int sel, const SegArgs& a, int grid, int threads, size_t shmem, hipStream_t s) {
+  switch (sel) {
+    case 11: return launch_core_t<1, 1, PREC>(a, grid, threads, shmem, s);
+    case 12: return launch_core_t<1, 2, PREC>(a, grid, threads, shmem, s);
+    case 21: return launch_core_t<2, 1, PREC>(a, grid, threads, shmem, s);
+    case 22: return launch_core_t<2, 2, PREC>(a, grid, threads, shmem, s);
+    case 31: return launch_core_t<3, 1, PREC>(a, grid, threads, shmem, s);
+    case 32: return launch_core_t<3, 2, PREC>(a, grid, threads, shmem, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Rounds to the 16-bit copy: bfloat16 (nearest even), or float16 of u * 2^15
+// (nearest even). |u| <= 1 for a factor with orthonormal columns, so the
+// float16 copy stays below 2^15 < 65504.
+__global__ void k_cast16(const float* __restrict__ U, int64_t n, uint16_t* __restrict__ Uh, int prec) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float u = U[i];
+    uint16_t b;
+    if (prec == OP_BF16) b = __builtin_bit_cast(uint16_t, (__bf16)u);
+    else b = __builtin_bit_cast(uint16_t, (_Float16)(u * 32768.f));
+    Uh[i] = b;
+  }
 }
 
 void g_strides(const hoqri_plan* p, int64_t* st) {
@@ -678,8 +793,32 @@ bool segpass_supported(const hoqri_plan* p, int mode) {
   return g.B <= 8 && p->K[mode] <= 32;
 }
 
-hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, const float* G, float* A,
-                               const int32_t* out_map, hipStream_t s) {
+bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale) {
+  // A operand of the FP16 form: x * ascale * (nm1 - 1 float16 copies, each
+  // below 2^15 in magnitude) must stay below 60000; the product then carries
+  // the factor ascale * 2^(15 nm1), removed exactly by yscale.
+  const double mx = p->maxabs_x > 0 ? p->maxabs_x : 1.0;
+  const int e = (int)std::floor(std::log2(60000.0 / mx) - 15.0 * (nm1 - 1));
+  const int ec = e > 60 ? 60 : e;
+  const int ey = -(15 * nm1 + ec);
+  if (ec < -126 || ey < -126 || ey > 127) return false;
+  *ascale = std::ldexp(1.0f, ec);
+  *yscale = std::ldexp(1.0f, ey);
+  return true;
+}
+
+hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s) {
+  const int64_t n = rows * K;
+  if (n <= 0) return HOQRI_OK;
+  int64_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_cast16, dim3((unsigned)grid), dim3(256), 0, s, U, n, Uh, prec);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
+                           const int32_t* out_map, hipStream_t s) {
   if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
@@ -711,7 +850,7 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   }
   // 2. main pass
   SegArgs a{};
-  fill_common(a, p, mode, g, U);
+  if (!fill_common(a, p, mode, g, op)) return HOQRI_ERR_UNSUPPORTED;
   int64_t W = md.ranges;
   if (W > p->nnz) W = p->nnz;
   a.W = (int32_t)W;
@@ -728,15 +867,10 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   hipError_t e = hipSuccess;
   {
   TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
-  switch (g.nm1 * 10 + KN2) {
-    case 11: e = launch_ttm_t<1, 1>(a, threads, shmem, s); break;
-    case 12: e = launch_ttm_t<1, 2>(a, threads, shmem, s); break;
-    case 21: e = launch_ttm_t<2, 1>(a, threads, shmem, s); break;
-    case 22: e = launch_ttm_t<2, 2>(a, threads, shmem, s); break;
-    case 31: e = launch_ttm_t<3, 1>(a, threads, shmem, s); break;
-    case 32: e = launch_ttm_t<3, 2>(a, threads, shmem, s); break;
-    default: return HOQRI_ERR_UNSUPPORTED;
-  }
+  const int sel = g.nm1 * 10 + KN2;
+  if (op.prec == OP_FP32) e = dispatch_ttm<P_FP32>(sel, a, threads, shmem, s);
+  else if (op.prec == OP_BF16) e = dispatch_ttm<P_BF16>(sel, a, threads, shmem, s);
+  else e = dispatch_ttm<P_FP16>(sel, a, threads, shmem, s);
   }
   if (e != hipSuccess) return HOQRI_ERR_HIP;
   TimerScope tf(p, HOQRI_KERNEL_FIXUP, s);
@@ -753,13 +887,13 @@ hoqri_status launch_ttmctc_f32(hoqri_plan* p, int mode, const float* const* U, c
   return HOQRI_OK;
 }
 
-hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, double* f_out, hipStream_t s) {
+hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, hipStream_t s) {
   const int mode = p->core_mode;
   if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
   SegArgs a{};
-  fill_common(a, p, mode, g, U);
+  if (!fill_common(a, p, mode, g, op)) return HOQRI_ERR_UNSUPPORTED;
   // each wave keeps its partial (16*KN2 x 256 floats) in LDS: at most 160 KB per workgroup
   const int per_wave = 16 * KN2 * 256 * 4 + 128 * 4;
   int rpw = (160 * 1024) / (per_wave * g.B);
@@ -773,7 +907,7 @@ hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, dou
     groups = (W + a.RPW - 1) / a.RPW;
   }
   a.W = (int32_t)W;
-  a.Uc = U[mode];
+  a.Uc = op.U32[mode];
   a.Kc = p->K[mode];
   a.gpart = p->sc.gpart;
   const int threads = 64 * g.B * a.RPW;
@@ -781,15 +915,10 @@ hoqri_status launch_core_f32(hoqri_plan* p, const float* const* U, float* G, dou
   hipError_t e = hipSuccess;
   {
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
-  switch (g.nm1 * 10 + KN2) {
-    case 11: e = launch_core_t<1, 1>(a, (int)groups, threads, shmem, s); break;
-    case 12: e = launch_core_t<1, 2>(a, (int)groups, threads, shmem, s); break;
-    case 21: e = launch_core_t<2, 1>(a, (int)groups, threads, shmem, s); break;
-    case 22: e = launch_core_t<2, 2>(a, (int)groups, threads, shmem, s); break;
-    case 31: e = launch_core_t<3, 1>(a, (int)groups, threads, shmem, s); break;
-    case 32: e = launch_core_t<3, 2>(a, (int)groups, threads, shmem, s); break;
-    default: return HOQRI_ERR_UNSUPPORTED;
-  }
+  const int sel = g.nm1 * 10 + KN2;
+  if (op.prec == OP_FP32) e = dispatch_core<P_FP32>(sel, a, (int)groups, threads, shmem, s);
+  else if (op.prec == OP_BF16) e = dispatch_core<P_BF16>(sel, a, (int)groups, threads, shmem, s);
+  else e = dispatch_core<P_FP16>(sel, a, (int)groups, threads, shmem, s);
   }
   if (e != hipSuccess) return HOQRI_ERR_HIP;
   CoreRedArgs r{};
