@@ -52,20 +52,49 @@ CONFIGS = {
 }
 
 
-def pass_work(dims, ranks, nnz, R):
+def pass_work(dims, ranks, nnz, R, su=4):
     """Algorithmic flops and HBM bytes of one TTMcTC pass per mode (segment-first
     count: 2 nnz prod K_{-n} + 2 R_n prod K flops; indices + values streamed once,
-    each needed factor row read once, the output written once)."""
+    each needed factor row read once (su bytes per entry: 4 for float32, 2 for
+    the 16-bit copies), the output written once)."""
     N = len(dims)
     PK = math.prod(ranks)
     out = []
     for n in range(N):
         P = PK // ranks[n]
         flops = 2 * nnz * P + 2 * R[n] * PK
-        byts = nnz * (4 * (N - 1) + 4) + 8 * R[n] + sum(R[m] * ranks[m] * 4 for m in range(N) if m != n) \
+        byts = nnz * (4 * (N - 1) + 4) + 8 * R[n] + sum(R[m] * ranks[m] * su for m in range(N) if m != n) \
             + 4 * dims[n] * ranks[n]
         out.append((flops, byts))
     return out
+
+
+TRAFFIC_PROFILES = {("c2", "fp32"): "profiles/ttmctc_fp32_c2_traffic.txt"}
+KERNEL_SOURCES = ("paper_2510_16930_amd/csrc/segpass.hip", "paper_2510_16930_amd/csrc/common.h")
+
+
+def measured_traffic(config, prec):
+    """HBM bytes per TTMcTC launch from the stored FETCH_SIZE / WRITE_SIZE
+    counter summary of this workload, or None when there is none or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = TRAFFIC_PROFILES.get((config, prec))
+    if path is None or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    fields = {}
+    with open(os.path.join(ROOT, path)) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def make_input(cfg, dev):
@@ -109,6 +138,20 @@ def cpu_baseline(idx_cpu, vals_cpu, dims, ranks, U0_cpu, nnz_full, budget_s=20.0
                       f"{nnz_full} nonzeros: passes {t_pass:.2f} s scaled x{nnz_full / S:.1f}, QR {t_qr:.2f} s"}
 
 
+def copy_calibration():
+    """One device copy of exactly 1 GiB (read 1 GiB, write 1 GiB): what the
+    FETCH_SIZE / WRITE_SIZE counters report for it gives their scale."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,7 +159,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy and exit (scale for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; the multi-GPU design is documented, not run",
                           "n_gpus": args.gpus}))
@@ -160,7 +207,7 @@ def main():
     kt = {k: H.hoqri_timing_read(plan, k) for k in ("ttmctc", "core", "orth", "fixup")}
     H.hoqri_timing_enable(plan, False)
 
-    work = pass_work(dims, ranks, nnz, R)
+    work = pass_work(dims, ranks, nnz, R, 4 if cfg["prec"] == "fp32" else 2)
     sweeps = st.sweeps
     ttm_launch, ttm_ms = kt["ttmctc"]
     ttm_flops = sweeps * sum(w[0] for w in work)
@@ -169,13 +216,18 @@ def main():
     achieved_flops = ttm_flops / ttm_s
     achieved_bytes = ttm_bytes / ttm_s
     prec = cfg["prec"]
+    # the binding roof is the one whose peak needs more time for the algorithmic work
+    mfma_bound = ttm_flops / PEAK[prec] >= ttm_bytes / HBM_PEAK
+    if mfma_bound:
+        rl = dict(bound="mfma", achieved=round(achieved_flops / 1e12, 3), peak=PEAK[prec] / 1e12, unit="TFLOP/s",
+                  frac=round(achieved_flops / PEAK[prec], 4))
+    else:
+        rl = dict(bound="hbm", achieved=round(achieved_bytes / 1e9, 1), peak=HBM_PEAK / 1e9, unit="GB/s",
+                  frac=round(achieved_bytes / HBM_PEAK, 4))
     roofline = {
-        "bound": "mfma",
-        "achieved": round(achieved_flops / 1e12, 3),
-        "peak": PEAK[prec] / 1e12,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_flops / PEAK[prec], 4),
-        "traffic": None,
+        **rl,
+        "traffic": measured_traffic(args.config, prec),
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
         "kernel": f"k_ttm<{prec}> (TTMcTC segment pass)",
         "launches": ttm_launch,
         "avg_launch_ms": round(ttm_ms / max(ttm_launch, 1), 4),
@@ -183,6 +235,7 @@ def main():
         "algorithmic_bytes_per_launch": int(ttm_bytes / max(ttm_launch, 1)),
         "hbm_GBps_algorithmic": round(achieved_bytes / 1e9, 1),
         "hbm_frac_algorithmic": round(achieved_bytes / HBM_PEAK, 4),
+        "mfma_frac_algorithmic": round(achieved_flops / PEAK[prec], 4),
     }
     line = {
         "metric": "HOQRI iters/s & TTMcTC GFLOP/s, BF16 vs FP32 at equal fit; serve p50/p99",
