@@ -46,6 +46,11 @@ CONFIGS = {
                alpha=1.1, values="uniform", seed=14, init_seed=114, prec="fp16",
                desc="4-way 2e5 x 2e5 x 5e3 x 1e3, nnz 100M, Zipf(1.1), uniform(0,1) values, ranks 10^4, "
                     "FP16 MFMA form (power-of-two scaled), FP32 accumulation"),
+    "c5": dict(serve=True, n_requests=2000, seed=15, arena_gib=8.0, max_slots=64, max_sweeps=30, tol=1e-6,
+               load=0.8,
+               desc="stream of 2000 3-way requests, dims log-uniform [1e3, 2e5], nnz log-uniform [1e4, 2e6], "
+                    "uniform coordinates, N(0,1) values, ranks {4,8,16}, stop at rel. change 1e-6 or 30 sweeps, "
+                    "Poisson arrivals at 0.8x the saturated rate, FP32"),
     "c4f32": dict(dims=(200_000, 200_000, 5_000, 1_000), ranks=(10, 10, 10, 10), nnz=100_000_000, dist="zipf",
                   alpha=1.1, values="uniform", seed=14, init_seed=114, prec="fp32",
                   desc="4-way 2e5 x 2e5 x 5e3 x 1e3, nnz 100M, Zipf(1.1), uniform(0,1) values, ranks 10^4, FP32 form"),
@@ -152,6 +157,84 @@ def copy_calibration():
     return 0
 
 
+def bench_serve(args, cfg):
+    """Request stream through the server: saturated throughput first (every
+    request queued at time 0), then Poisson arrivals at `load` times that rate;
+    latency = result time - arrival time."""
+    import numpy as np
+    import torch
+    from paper_2510_16930_amd import _lib as H
+    from paper_2510_16930_amd import synth
+    from paper_2510_16930_amd.serving import run_stream
+
+    dev = "cuda:0"
+    n = cfg["n_requests"] if args.requests is None else args.requests
+    params = synth.serve_stream_params(n, cfg["seed"])
+    print(f"[bench] generating {n} requests", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    reqs = []
+    for i, p in enumerate(params):
+        idx, vals = synth.coo_uniform_torch(p["dims"], p["nnz"], p["data_seed"], device=dev)
+        U0 = [H.hoqri_orth(r)[0] for r in synth.gaussian_start_torch(p["dims"], p["ranks"], p["init_seed"], device=dev)]
+        reqs.append(dict(idx=idx, vals=vals, dims=p["dims"], ranks=p["ranks"], U0=U0))
+        if (i + 1) % 250 == 0:
+            print(f"[bench] {i + 1} requests ready", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    arena = int(cfg["arena_gib"] * (1 << 30))
+
+    def one_pass(arrivals, label):
+        for q in reqs:
+            q["U"] = [u.clone() for u in q["U0"]]
+            q["G"] = torch.empty(q["ranks"], dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        srv = H.Server(arena, max_slots=cfg["max_slots"], max_sweeps=cfg["max_sweeps"], tol=cfg["tol"])
+        print(f"[bench] {label}", file=sys.stderr, flush=True)
+        res, lat, wall, steps = run_stream(srv, reqs, arrivals)
+        srv.close()
+        bad = [r for r in res.values() if r.status != 0]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed, first status {bad[0].status}")
+        return res, lat, wall, steps
+
+    res0, lat0, wall0, steps0 = one_pass(np.zeros(n), "saturated pass (all requests at t=0)")
+    mu = n / wall0
+    rate = cfg["load"] * mu
+    arrivals = synth.poisson_arrivals(n, rate, cfg["seed"] + 1)
+    res, lat, wall, steps = one_pass(arrivals, f"Poisson pass at {rate:.1f} requests/s")
+    L = np.array([lat[i] for i in range(n)]) * 1e3
+    sweeps = np.array([res[i].sweeps for i in range(n)])
+    line = {
+        "metric": "HOQRI iters/s & TTMcTC GFLOP/s, BF16 vs FP32 at equal fit; serve p50/p99",
+        "value": round(n / wall, 3),
+        "unit": "tensors/s",
+        "n_gpus": 1,
+        "steps": int(steps),
+        "warmup": 0,
+        "ms_per_step": round(1e3 * wall / max(steps, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "requests": n, "max_slots": cfg["max_slots"],
+                   "arena_bytes": arena, "max_sweeps": cfg["max_sweeps"], "tol": cfg["tol"]},
+        "p50_ms": round(float(np.percentile(L, 50)), 3),
+        "p99_ms": round(float(np.percentile(L, 99)), 3),
+        "arrival_rate_per_s": round(rate, 3),
+        "saturated_tensors_per_s": round(mu, 3),
+        "saturated_p50_ms": round(float(np.percentile(np.array(list(lat0.values())) * 1e3, 50)), 3),
+        "sweeps_mean": round(float(sweeps.mean()), 2),
+        "sweeps_total": int(sweeps.sum()),
+        "skipped_updates_total": int(sum(res[i].skipped_updates for i in range(n))),
+        "requests_with_skipped_updates": int(sum(1 for i in range(n) if res[i].skipped_updates > 0)),
+        "hoqri_iters_per_s": round(float(sweeps.sum()) / wall0, 1),
+        "input_gen_s": round(t_gen, 1),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +242,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=None, help="serving configs: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device-to-device copy and exit (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -174,6 +258,8 @@ def main():
     from paper_2510_16930_amd import _lib as H
 
     cfg = CONFIGS[args.config]
+    if cfg.get("serve"):
+        return bench_serve(args, cfg)
     dev = torch.device("cuda:0")
     dims, ranks, N = cfg["dims"], cfg["ranks"], len(cfg["dims"])
     print(f"[bench] config={args.config} generating input", file=sys.stderr, flush=True)

@@ -125,6 +125,8 @@ typedef struct {
   hoqri_prec prec;      /* operand precision of the segment passes */
   int32_t check_every;  /* read f back every this many sweeps (>= 1) */
   int32_t orthonormalize_input; /* nonzero: first replace each U^(n) by its orthonormal basis */
+  int32_t keep_on_breakdown;  /* nonzero: a rank-deficient A^(n) leaves U^(n) unchanged for that
+                                 step (counted in skipped_updates) instead of ending the run */
 } hoqri_run_opts;
 
 typedef struct {
@@ -134,6 +136,7 @@ typedef struct {
   double fit;           /* 1 - sqrt(max(||X||^2 - f, 0)) / ||X|| */
   double rel_change;    /* |f_t - f_{t-1}| / f_t at the last sweep */
   double orth_err_max;  /* max_n ||U^(n)T U^(n) - I||_F of the returned factors */
+  int32_t skipped_updates; /* mode updates skipped for rank deficiency (keep_on_breakdown) */
 } hoqri_run_stats;
 
 /* HOQRI (Alg. 2): for each sweep, for n = 1..N: G from the current factors,
@@ -144,7 +147,8 @@ typedef struct {
  * Alg. 2). d_f_hist (optional, device, max_sweeps * N doubles) receives f
  * before every mode update. stats (host) is filled at the end. Synchronises
  * `stream` every check_every sweeps and at the end. Returns
- * HOQRI_ERR_BREAKDOWN if some A^(n) is rank deficient. */
+ * HOQRI_ERR_BREAKDOWN if some A^(n) is rank deficient (unless keep_on_breakdown),
+ * or before any sweep if some mode has fewer nonempty slices than K_n. */
 hoqri_status hoqri_run(hoqri_plan* plan, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
                        const hoqri_run_opts* opts, hoqri_run_stats* stats, hipStream_t stream);
 
@@ -161,6 +165,88 @@ hoqri_status hoqri_run(hoqri_plan* plan, float* const* d_U_inout, float* d_G_out
 typedef enum { HOQRI_KERNEL_TTMCTC = 0, HOQRI_KERNEL_CORE = 1, HOQRI_KERNEL_ORTH = 2, HOQRI_KERNEL_FIXUP = 3 } hoqri_kernel;
 hoqri_status hoqri_timing_enable(hoqri_plan* plan, int32_t enable);
 hoqri_status hoqri_timing_read(hoqri_plan* plan, int32_t kind, int64_t* launches, double* total_ms);
+
+/* ------------------------------------------------------------------------
+ * Device memory arena (host-side bookkeeping only; no HIP calls).
+ * First-fit allocator over [0, bytes) in 256-byte granules with coalescing of
+ * neighbouring free blocks. Offsets are relative to whatever device buffer the
+ * caller associates with the arena. Used by the request server for admission
+ * by footprint; exported for callers that pack several plans in one buffer.
+ * ------------------------------------------------------------------------ */
+typedef struct hoqri_arena hoqri_arena;
+hoqri_status hoqri_arena_create(size_t bytes, hoqri_arena** arena);
+/* HOQRI_ERR_NOMEM when no free block is large enough (nothing changes). */
+hoqri_status hoqri_arena_alloc(hoqri_arena* arena, size_t bytes, size_t* offset);
+/* HOQRI_ERR_ARG for an offset that is not the start of a live block. */
+hoqri_status hoqri_arena_free(hoqri_arena* arena, size_t offset);
+hoqri_status hoqri_arena_stats(const hoqri_arena* arena, size_t* used, size_t* largest_free, int32_t* live_blocks);
+void hoqri_arena_destroy(hoqri_arena* arena);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of many HOQRI runs (Alg. 2) on one GPU.
+ *
+ * Requests are admitted first-come first-served when a slot is free and the
+ * plan's workspace (hoqri_plan_workspace_size) fits in the server's arena;
+ * a request that does not fit waits (later requests do not overtake it). Each
+ * hoqri_server_step advances every admitted request by one mode update (core,
+ * TTMcTC, orthonormalisation), with one launch per kernel kind covering all
+ * admitted requests (blocks are split among requests by a table), so requests
+ * admitted at different times overlap on the device. A request's launches use
+ * the same work split as hoqri_run, so its results are bitwise those of
+ * hoqri_run with the same options (float32 operands, check_every = 1).
+ * Requests finish when the stop rule of hoqri_run holds or after max_sweeps.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  void* d_arena;            /* device memory owned by the caller, kept until destroy */
+  size_t arena_bytes;       /* plans are admitted while their workspaces fit in here */
+  int32_t max_slots;        /* requests in flight at once (1 .. 1024) */
+  int32_t max_sweeps;       /* per request (>= 1) */
+  double tol;               /* stop rule |f_t - f_{t-1}| <= tol * f_t (0 disables) */
+  int32_t max_admit_per_step; /* plan builds per step (0: no limit) */
+  int32_t report_orth_err;  /* nonzero: compute ||U^T U - I||_F of finished requests */
+  int32_t keep_on_breakdown; /* as in hoqri_run_opts */
+} hoqri_server_opts;
+
+typedef struct {
+  int64_t id;               /* caller's tag, returned in the result */
+  int32_t order;
+  const int64_t* dims;      /* host [order], copied at submit */
+  const int32_t* ranks;     /* host [order], copied at submit */
+  int64_t nnz;
+  const int32_t* d_idx;     /* device [order][nnz]; read when the request is admitted */
+  const float* d_vals;      /* device [nnz]; read when the request is admitted */
+  float* const* d_U;        /* host array of order device pointers (copied at submit): orthonormal
+                               start factors, overwritten with the result when the request finishes */
+  float* d_G;               /* device, prod K floats: receives the core of the result */
+} hoqri_request;
+
+typedef struct {
+  int64_t id;
+  hoqri_status status;      /* HOQRI_OK, or the error that ended the request */
+  int32_t sweeps;
+  double norm_x2, f, fit, rel_change, orth_err_max;
+  int64_t admitted_step, finished_step;
+  int32_t skipped_updates;
+} hoqri_result;
+
+typedef struct hoqri_server hoqri_server;
+/* Allocates pinned host memory for the per-step launch tables; takes the first
+ * part of the arena for their device copy. Needs a visible device. */
+hoqri_status hoqri_server_create(const hoqri_server_opts* opts, hoqri_server** server);
+/* Queues a request (host only; no device work). The caller keeps d_idx,
+ * d_vals, the factors and d_G allocated until the request's result is returned. */
+hoqri_status hoqri_server_submit(hoqri_server* server, const hoqri_request* request);
+/* Admits queued requests, advances all admitted requests by one mode update on
+ * `stream`, and writes the results of requests that finished during this step
+ * (at most `cap`; the rest are returned by later calls) to `results`. Results
+ * are complete (factors and core written) when the call returns. Synchronises
+ * `stream` once per step, plus once per admitted request (plan build). */
+hoqri_status hoqri_server_step(hoqri_server* server, hipStream_t stream, hoqri_result* results, int32_t cap,
+                               int32_t* n_results);
+/* Requests queued, requests in flight, bytes of the arena in use. */
+hoqri_status hoqri_server_info(const hoqri_server* server, int32_t* queued, int32_t* active, size_t* arena_used);
+/* Frees the server's host memory; nothing the caller owns. In-flight requests are dropped. */
+void hoqri_server_destroy(hoqri_server* server);
 
 /* Human-readable name of a status code (static string). */
 const char* hoqri_status_string(hoqri_status status);

@@ -29,7 +29,8 @@ Readings where the paper is silent (all also listed in the design doc):
   (§2.2); fit = 1 - sqrt(max(||X||^2 - ||G||^2, 0)) / ||X||.
 * Duplicate coordinates are summed (TTMcTC and the core are linear in X).
 * Rank deficiency: a QR pivot with R_kk^2 <= 1e-13 * ||A||_F^2 is a breakdown
-  (the paper does not discuss it).
+  (the paper does not discuss it); it either ends the run or, on request,
+  leaves that mode's factor unchanged for that step.
 * Unfolding column order: C order (last remaining mode fastest), which matches
   the ascending-mode Kronecker chain of the TTMc formula in §2.1.
 
@@ -341,7 +342,7 @@ def fit_from(normx2: float, f: float) -> float:
 
 
 def hoqri(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: float | None = None,
-          stop: str = "rel_f", impl: str = "segment", record_A: bool = False):
+          stop: str = "rel_f", impl: str = "segment", record_A: bool = False, on_breakdown: str = "raise"):
     """Alg. 2 (HOQRI). Sweeps over n = 1..N in order (Gauss-Seidel: the update of
     mode n sees the already-updated factors of modes < n, as in the single-mode
     update rule of §5). Per mode: G from the current factors (first line of
@@ -351,9 +352,17 @@ def hoqri(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: fl
     stop == "rel_f" and |f_t - f_{t-1}| <= tol * f_t, or stop == "err" and the
     relative approximation error changes by less than tol (§6.1's rule).
 
+    A numerically rank-deficient A^(n) (the QR pivot test of qr_positive) raises
+    RankDeficient, or with on_breakdown == "keep" leaves U^(n) as it was for that
+    step (the paper does not treat this case; keeping the factor skips one
+    single-mode update, so f still does not decrease) and counts it in
+    history["skipped"].
+
     Returns (U, G, history) where history has per-mode-step f (before the update),
     per-sweep f, fit, and optionally every A^(n).
     """
+    if on_breakdown not in ("raise", "keep"):
+        raise ValueError(on_breakdown)
     validate(idx, dims, ranks)
     idx, vals = coalesce(idx, vals, dims)
     nx2 = norm_x2(vals)
@@ -361,7 +370,7 @@ def hoqri(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: fl
     U = [np.array(u, dtype=np.float64, copy=True) for u in U0]
     core = core_segment if impl == "segment" else (lambda i, v, Us: core_elementwise(i, v, Us))
     tt = ttmctc_segment if impl == "segment" else (lambda i, v, Us, n, G: ttmctc_elementwise(i, v, Us, n, G))
-    hist = {"f_step": [], "f_sweep": [], "fit": [], "A": [], "G_step": [], "normx2": nx2}
+    hist = {"f_step": [], "f_sweep": [], "fit": [], "A": [], "G_step": [], "normx2": nx2, "skipped": 0}
     f_prev = float(np.sum(core(idx, vals, U) ** 2))
     err_prev = math.sqrt(max(nx2 - f_prev, 0.0) / nx2)
     for t in range(sweeps):
@@ -372,7 +381,12 @@ def hoqri(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: fl
             if record_A:
                 hist["A"].append(A)
                 hist["G_step"].append(G)
-            U[n] = qr_positive(A)[0]
+            try:
+                U[n] = qr_positive(A)[0]
+            except RankDeficient:
+                if on_breakdown == "raise":
+                    raise
+                hist["skipped"] += 1
         G = core(idx, vals, U)
         f = float(np.sum(G * G))
         hist["f_sweep"].append(f)

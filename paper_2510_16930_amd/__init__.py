@@ -4,7 +4,10 @@ The computation runs in libhoqri.so (HIP kernels behind the C ABI of
 include/hoqri.h); this package is its thin Python binding.
 """
 from ._lib import (  # noqa: F401
+    Arena,
     HoqriError,
+    ServeResult,
+    Server,
     Plan,
     Stats,
     hoqri_core,

@@ -28,6 +28,8 @@ EXPORTS = (
     "hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_plan_destroy",
     "hoqri_core", "hoqri_ttmctc", "hoqri_orth_workspace_size", "hoqri_orth", "hoqri_run",
     "hoqri_status_string", "hoqri_timing_enable", "hoqri_timing_read",
+    "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats", "hoqri_arena_destroy",
+    "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info", "hoqri_server_destroy",
 )
 KERNEL = {"ttmctc": 0, "core": 1, "orth": 2, "fixup": 3}
 
@@ -40,12 +42,34 @@ class HoqriError(RuntimeError):
 
 class RunOpts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("prec", ctypes.c_int),
-                ("check_every", ctypes.c_int32), ("orthonormalize_input", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("orthonormalize_input", ctypes.c_int32),
+                ("keep_on_breakdown", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("norm_x2", ctypes.c_double), ("f", ctypes.c_double),
-                ("fit", ctypes.c_double), ("rel_change", ctypes.c_double), ("orth_err_max", ctypes.c_double)]
+                ("fit", ctypes.c_double), ("rel_change", ctypes.c_double), ("orth_err_max", ctypes.c_double),
+                ("skipped_updates", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("max_admit_per_step", ctypes.c_int32),
+                ("report_orth_err", ctypes.c_int32), ("keep_on_breakdown", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("order", ctypes.c_int32), ("dims", ctypes.POINTER(ctypes.c_int64)),
+                ("ranks", ctypes.POINTER(ctypes.c_int32)), ("nnz", ctypes.c_int64), ("d_idx", ctypes.c_void_p),
+                ("d_vals", ctypes.c_void_p), ("d_U", ctypes.POINTER(ctypes.c_void_p)), ("d_G", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int), ("sweeps", ctypes.c_int32),
+                ("norm_x2", ctypes.c_double), ("f", ctypes.c_double), ("fit", ctypes.c_double),
+                ("rel_change", ctypes.c_double), ("orth_err_max", ctypes.c_double),
+                ("admitted_step", ctypes.c_int64), ("finished_step", ctypes.c_int64),
+                ("skipped_updates", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,8 +100,22 @@ def load() -> ctypes.CDLL:
     L.hoqri_timing_read.argtypes = [vp, i32, P(i64), P(dbl)]
     L.hoqri_status_string.argtypes = [ctypes.c_int]
     L.hoqri_status_string.restype = ctypes.c_char_p
+    L.hoqri_arena_create.argtypes = [sz, P(vp)]
+    L.hoqri_arena_alloc.argtypes = [vp, sz, P(sz)]
+    L.hoqri_arena_free.argtypes = [vp, sz]
+    L.hoqri_arena_stats.argtypes = [vp, P(sz), P(sz), P(i32)]
+    L.hoqri_arena_destroy.argtypes = [vp]
+    L.hoqri_arena_destroy.restype = None
+    L.hoqri_server_create.argtypes = [P(ServerOpts), P(vp)]
+    L.hoqri_server_submit.argtypes = [vp, P(Request)]
+    L.hoqri_server_step.argtypes = [vp, vp, P(Result), i32, P(i32)]
+    L.hoqri_server_info.argtypes = [vp, P(i32), P(i32), P(sz)]
+    L.hoqri_server_destroy.argtypes = [vp]
+    L.hoqri_server_destroy.restype = None
     for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
-                 "hoqri_ttmctc", "hoqri_orth", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read"):
+                 "hoqri_ttmctc", "hoqri_orth", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
+                 "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats",
+                 "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -241,10 +279,11 @@ class Stats:
     fit: float
     rel_change: float
     orth_err_max: float
+    skipped_updates: int = 0
 
 
 def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp32", check_every: int = 1,
-              orthonormalize_input: bool = False, G=None, f_hist=None, stream=None):
+              orthonormalize_input: bool = False, G=None, f_hist=None, stream=None, keep_on_breakdown: bool = False):
     """Runs HOQRI in place on Us. Returns (G, Stats)."""
     import torch
     L = load()
@@ -252,11 +291,12 @@ def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp
         _need_cuda(U, torch.float32, "U")
     if G is None:
         G = torch.empty(plan.ranks, dtype=torch.float32, device=Us[0].device)
-    opts = RunOpts(int(max_sweeps), float(tol), PREC[prec], int(check_every), int(bool(orthonormalize_input)))
+    opts = RunOpts(int(max_sweeps), float(tol), PREC[prec], int(check_every), int(bool(orthonormalize_input)),
+                   int(bool(keep_on_breakdown)))
     st = RunStats()
     _check(L.hoqri_run(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f_hist) if f_hist is not None else None,
                        ctypes.byref(opts), ctypes.byref(st), _stream(stream)), "hoqri_run")
-    return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max)
+    return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max, st.skipped_updates)
 
 
 def hoqri_timing_enable(plan: Plan, enable: bool = True):
@@ -271,3 +311,132 @@ def hoqri_timing_read(plan: Plan, kind: str):
     _check(load().hoqri_timing_read(plan.handle, KERNEL[kind], ctypes.byref(n), ctypes.byref(ms)),
            "hoqri_timing_read")
     return int(n.value), float(ms.value)
+
+
+class Arena:
+    """Host-side first-fit allocator over [0, size) (hoqri_arena_*)."""
+
+    def __init__(self, size: int):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.hoqri_arena_create(int(size), ctypes.byref(h)), "hoqri_arena_create")
+        self._h = h
+
+    def alloc(self, nbytes: int):
+        """Offset of a new block, or None when nothing fits."""
+        off = ctypes.c_size_t(0)
+        st = load().hoqri_arena_alloc(self._h, int(nbytes), ctypes.byref(off))
+        if st == -5:
+            return None
+        _check(st, "hoqri_arena_alloc")
+        return int(off.value)
+
+    def free(self, offset: int):
+        _check(load().hoqri_arena_free(self._h, int(offset)), "hoqri_arena_free")
+
+    def stats(self):
+        used, largest, live = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_int32(0)
+        _check(load().hoqri_arena_stats(self._h, ctypes.byref(used), ctypes.byref(largest), ctypes.byref(live)),
+               "hoqri_arena_stats")
+        return int(used.value), int(largest.value), int(live.value)
+
+    def close(self):
+        if self._h:
+            load().hoqri_arena_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class ServeResult:
+    id: int
+    status: int
+    sweeps: int
+    norm_x2: float
+    f: float
+    fit: float
+    rel_change: float
+    orth_err_max: float
+    admitted_step: int
+    finished_step: int
+    skipped_updates: int
+
+
+class Server:
+    """Request server (hoqri_server_*): continuous batching of HOQRI runs.
+
+    The arena is a torch uint8 tensor of `arena_bytes` on the current device.
+    Tensors handed to submit() are kept referenced until their result is
+    returned by step().
+    """
+
+    def __init__(self, arena_bytes: int, max_slots: int = 64, max_sweeps: int = 30, tol: float = 1e-6,
+                 max_admit_per_step: int = 0, report_orth_err: bool = False, keep_on_breakdown: bool = True,
+                 device=None):
+        import torch
+        L = load()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device or "cuda")
+        opts = ServerOpts(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(max_slots), int(max_sweeps),
+                          float(tol), int(max_admit_per_step), int(bool(report_orth_err)),
+                          int(bool(keep_on_breakdown)))
+        h = ctypes.c_void_p()
+        _check(L.hoqri_server_create(ctypes.byref(opts), ctypes.byref(h)), "hoqri_server_create")
+        self._h = h
+        self._keep = {}
+        self._cap = 1024
+        self._res = (Result * self._cap)()
+
+    def submit(self, rid: int, idx, vals, dims, ranks, Us, G):
+        """Queues request `rid`: coordinates idx [N, nnz] int32 and values float32 on
+        the device, orthonormal start factors Us (overwritten with the result) and
+        the core output G."""
+        import torch
+        _need_cuda(idx, torch.int32, "idx")
+        _need_cuda(vals, torch.float32, "vals")
+        for U in Us:
+            _need_cuda(U, torch.float32, "U")
+        _need_cuda(G, torch.float32, "G")
+        N = len(dims)
+        d = (ctypes.c_int64 * N)(*[int(x) for x in dims])
+        r = (ctypes.c_int32 * N)(*[int(x) for x in ranks])
+        u = _ptr_array(Us)
+        req = Request(int(rid), N, d, r, int(vals.numel()), ctypes.c_void_p(idx.data_ptr()),
+                      ctypes.c_void_p(vals.data_ptr()), u, ctypes.c_void_p(G.data_ptr()))
+        _check(load().hoqri_server_submit(self._h, ctypes.byref(req)), "hoqri_server_submit")
+        self._keep[int(rid)] = (idx, vals, Us, G)
+
+    def step(self, stream=None):
+        """One engine step; returns the results of requests that finished."""
+        n = ctypes.c_int32(0)
+        _check(load().hoqri_server_step(self._h, _stream(stream), self._res, self._cap, ctypes.byref(n)),
+               "hoqri_server_step")
+        out = []
+        for i in range(n.value):
+            r = self._res[i]
+            out.append(ServeResult(int(r.id), int(r.status), int(r.sweeps), r.norm_x2, r.f, r.fit, r.rel_change,
+                                   r.orth_err_max, int(r.admitted_step), int(r.finished_step),
+                                   int(r.skipped_updates)))
+            self._keep.pop(int(r.id), None)
+        return out
+
+    def info(self):
+        q, a, used = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_size_t(0)
+        _check(load().hoqri_server_info(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(used)),
+               "hoqri_server_info")
+        return int(q.value), int(a.value), int(used.value)
+
+    def close(self):
+        if self._h:
+            load().hoqri_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

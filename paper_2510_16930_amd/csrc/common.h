@@ -133,10 +133,18 @@ bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale);
 // Rounds rows [0, rows) of a float32 factor (K columns) to the 16-bit copy.
 hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s);
 
+// Factor rows between the caller's order and the plan's label order (run.hip).
+hoqri_status to_labels(hoqri_plan* p, const float* const* U, hipStream_t s);
+hoqri_status from_labels(hoqri_plan* p, float* const* U, hipStream_t s);
+// Zeroes the label-order rows of mode n's empty slices (rows R_n .. I_n-1).
+hoqri_status zero_empty_rows(hoqri_plan* p, int n, hipStream_t s);
+hoqri_status fill_i32(int32_t* x, int n, int32_t v, hipStream_t s);
+
 // CholeskyQR2 (orth.hip).
 size_t orth_ws_bytes(int64_t rows, int32_t cols);
 hoqri_status launch_orth(int64_t rows, int32_t cols, const float* A, float* U, double* R,
-                         int32_t* status, void* ws, size_t ws_bytes, hipStream_t s, bool sticky);
+                         int32_t* status, void* ws, size_t ws_bytes, hipStream_t s, bool sticky,
+                         int32_t* skipped = nullptr, int64_t zero_to = 0);
 hoqri_status launch_orth_err(int64_t rows, int32_t cols, const float* U, double* err_out, void* ws,
                              size_t ws_bytes, hipStream_t s);
 

@@ -1,0 +1,238 @@
+// Launch descriptors of the segment-pass and CholeskyQR2 kernels.
+//
+// Every kernel of a mode step (core pass, TTMcTC pass, QR) is written as a
+// device body that takes its descriptor and a block index. The single-plan
+// entry points launch each body once per plan; the request server launches
+// each body once per engine step for all active requests together: the
+// launch's blocks are split among the requests by a prefix table, and every
+// block reads its request's descriptor from a per-step table in device memory.
+// A request gets the same blocks, ranges and summation order either way, so
+// its results do not depend on what else is in the batch.
+#pragma once
+
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace hoqri {
+
+struct SegArgs {
+  const int32_t* oidx[3];   // other-mode element offsets (i_m * K_m), mode-sorted
+  const float* val;
+  const int32_t* seg_off;   // [R+1]
+  const int32_t* seg_row;   // [R]
+  int32_t R;
+  int32_t nnz;
+  int32_t nnz_pad;          // nnz rounded up to 16 (the stored length)
+  int32_t W;                // ranges
+  int32_t B, RB, CB;        // y_i blocks (16x16) per range, as RB x CB
+  int32_t RPW;              // ranges per workgroup
+  const void* U[3];         // factors of the other modes (float32 or 16-bit copies), ascending
+  uint32_t Ubytes[3];
+  float ascale;             // FP16: power of two applied to x * (row factors) before rounding
+  float yscale;             // 16-bit forms: exact unscale of y
+  int32_t K1;               // rank of the second other mode (row split for N = 4)
+  // TTMcTC
+  const float* gtop;        // stage-two operand [B][KN2][64][64]
+  float* A;
+  int32_t Kn;
+  float* carry;             // [W][2][32]
+  int32_t* meta;            // [W][4]
+  const int32_t* out_map;   // null: A rows in label order; else row r goes to out_map[r]
+  // core
+  const float* Uc;          // factor of the pass mode
+  int32_t Kc;
+  float* gpart;             // [groups][B][16*KN2][256]
+};
+
+struct PrepArgs {
+  const float* G;
+  float* gtop;
+  int32_t B, CB, KN2, krow, kcol, Kn, mode, N, nm1;
+  int32_t om[3];          // other modes ascending
+  int32_t Ko[3];          // their ranks
+  int64_t gstride[4];     // C-order strides of G
+  int32_t nblk;           // blocks of this launch (grid-stride loop)
+};
+
+struct FixArgs {
+  const int32_t* meta;
+  const float* carry;
+  const int32_t* seg_row;
+  const int32_t* seg_off;
+  int32_t W, nnz, Kn;
+  const int32_t* out_map;
+  float* A;
+};
+
+struct CoreRedArgs {
+  const float* gpart;
+  int32_t groups, B, CB, KN2, krow, kcol, Kc, mode, nm1;
+  int32_t om[3], Ko[3];
+  int64_t gstride[4];
+  float* G;
+  double* fpart;
+};
+
+struct SumArgs {
+  const double* part;
+  int32_t n;
+  double* out;
+};
+
+// Kernel instance of a segment pass: tensor order, rank blocks, precision.
+inline int seg_key(int nm1, int kn2, int prec) { return nm1 * 100 + kn2 * 10 + prec; }
+
+struct TtmJob {
+  int key, threads;
+  size_t shmem;
+  PrepArgs prep;
+  int prep_blocks;
+  SegArgs seg;
+  int seg_blocks;
+  FixArgs fix;
+  int fix_blocks;
+};
+
+struct CoreJob {
+  int key, threads;
+  size_t shmem;
+  SegArgs seg;
+  int seg_blocks;
+  CoreRedArgs red;
+  int red_blocks;
+  SumArgs sum;
+};
+
+// Fills a job for one plan (no device work). G: the core the TTMcTC pass
+// multiplies by; A: its output (rows in label order when out_map is null).
+hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
+                         const int32_t* out_map, TtmJob* job);
+hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, CoreJob* job);
+
+struct GramArgs {
+  const float* A;
+  int64_t rows;
+  int32_t K;
+  const double* M;  // null: Gram of A; else Gram of A M (M upper triangular)
+  double* part;     // [K*K][nb]
+  int32_t nb;
+};
+struct GRedArgs {
+  const double* part;
+  int32_t nb;
+  double* W;
+};
+struct CholArgs {
+  const double* W;
+  int32_t K;
+  const double* Mprev;
+  const double* Rprev;
+  double* Mout;
+  double* Rout;
+  int32_t* flag;
+  int32_t* status;
+  int32_t sticky;
+  int32_t* skipped;  // null: breakdown sets *status; else counts kept factors
+};
+struct ApplyArgs {
+  const float* A;
+  int64_t rows;
+  int32_t K;
+  const double* M;
+  float* U;
+  const int32_t* flag;
+  int32_t nblk;
+  int64_t zero_to;  // rows [rows, zero_to) of U are zeroed with the update
+};
+struct OrthJob {
+  GramArgs g1, g2;
+  GRedArgs r1, r2;
+  CholArgs c1, c2;
+  ApplyArgs ap;
+  int gram_blocks, red_blocks, apply_blocks;
+};
+hoqri_status prepare_orth(int64_t rows, int32_t K, const float* A, float* U, double* R, int32_t* status, void* ws,
+                          size_t ws_bytes, bool sticky, OrthJob* job, int32_t* skipped = nullptr,
+                          int64_t zero_to = 0);
+
+// ---------------------------------------------------------------------------
+// Per-step descriptor tables: written on the host into pinned memory, copied
+// to device memory with one asynchronous copy, read by the batched kernels.
+// ---------------------------------------------------------------------------
+struct Staging {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  size_t mark = 0;
+  void bind(char* h, char* d, size_t c) {
+    host = h;
+    dev = d;
+    cap = c;
+    off = mark = 0;
+  }
+  // Copies n items into the table; returns their device address (null: full).
+  template <class T>
+  const T* put(const T* items, size_t n) {
+    const size_t start = align_up(off, 64);
+    const size_t bytes = n * sizeof(T);
+    if (start + bytes > cap) return nullptr;
+    std::memcpy(host + start, items, bytes);
+    off = start + bytes;
+    return reinterpret_cast<const T*>(dev + start);
+  }
+  hipError_t upload(hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (off > mark) e = hipMemcpyAsync(dev + mark, host + mark, off - mark, hipMemcpyHostToDevice, s);
+    mark = off;
+    return e;
+  }
+};
+
+// A batched launch: `count` items, item r owns blocks [first[r], first[r+1]).
+struct BatchTable {
+  const void* descs;
+  const int32_t* first;
+  int32_t count;
+  int32_t blocks;
+};
+
+// Stages descs[0..n) with their block counts; false when the table is full.
+template <class T>
+bool stage_table(Staging& st, const T* descs, const int32_t* nblocks, int n, BatchTable* out) {
+  if (n < 1 || n > 1024) return false;
+  std::vector<int32_t> first((size_t)n + 1);
+  first[0] = 0;
+  for (int i = 0; i < n; ++i) first[i + 1] = first[i] + nblocks[i];
+  out->descs = st.put(descs, (size_t)n);
+  out->first = st.put(first.data(), (size_t)n + 1);
+  out->count = n;
+  out->blocks = first[n];
+  return out->descs && out->first;
+}
+
+struct TtmGroup {
+  int key, threads;
+  size_t shmem;
+  BatchTable prep, seg, fix;
+};
+struct CoreGroup {
+  int key, threads;
+  size_t shmem;
+  BatchTable seg, red, sum;
+};
+struct OrthGroup {
+  BatchTable g1, r1, c1, g2, r2, c2, ap;
+};
+
+// Jobs of one group must share key, threads and shmem.
+bool stage_ttm_group(const TtmJob* const* jobs, int n, Staging& st, TtmGroup* g);
+bool stage_core_group(const CoreJob* const* jobs, int n, Staging& st, CoreGroup* g);
+bool stage_orth_group(const OrthJob* const* jobs, int n, Staging& st, OrthGroup* g);
+hoqri_status launch_ttm_group(const TtmGroup& g, hipStream_t s);
+hoqri_status launch_core_group(const CoreGroup& g, hipStream_t s);
+hoqri_status launch_orth_group(const OrthGroup& g, hipStream_t s);
+
+}  // namespace hoqri

@@ -61,15 +61,6 @@ int grid_of(int64_t n) {
   return (int)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
 }
 
-hoqri_status to_labels(hoqri_plan* p, const float* const* U, hipStream_t s) {
-  for (int n = 0; n < p->N; ++n) {
-    const int64_t I = p->dims[n];
-    hipLaunchKernelGGL(k_rows_to_labels, dim3(grid_of(I * p->K[n])), dim3(256), 0, s, U[n], p->md[n].inv, I, p->K[n],
-                       p->sc.Up[n]);
-  }
-  HOQRI_HIP_TRY(hipGetLastError());
-  return HOQRI_OK;
-}
 
 hoqri_status check_prec(hoqri_prec prec, int* op) {
   if (prec == HOQRI_FP32) *op = OP_FP32;
@@ -96,6 +87,41 @@ hoqri_status refresh16(hoqri_plan* p, int op, int mode, hipStream_t s) {
 }
 
 }  // namespace
+
+hoqri_status to_labels(hoqri_plan* p, const float* const* U, hipStream_t s) {
+  for (int n = 0; n < p->N; ++n) {
+    const int64_t I = p->dims[n];
+    hipLaunchKernelGGL(k_rows_to_labels, dim3(grid_of(I * p->K[n])), dim3(256), 0, s, U[n], p->md[n].inv, I, p->K[n],
+                       p->sc.Up[n]);
+  }
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status from_labels(hoqri_plan* p, float* const* U, hipStream_t s) {
+  for (int n = 0; n < p->N; ++n)
+    hipLaunchKernelGGL(k_rows_from_labels, dim3(grid_of(p->dims[n] * p->K[n])), dim3(256), 0, s, p->sc.Up[n],
+                       p->md[n].inv, p->dims[n], p->K[n], U[n]);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status zero_empty_rows(hoqri_plan* p, int n, hipStream_t s) {
+  const int64_t Rn = p->md[n].R;
+  if (p->dims[n] > Rn) {
+    const int64_t ne = (p->dims[n] - Rn) * p->K[n];
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(ne)), dim3(256), 0, s, p->sc.Up[n] + Rn * p->K[n], ne, 0.f);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+  return HOQRI_OK;
+}
+
+hoqri_status fill_i32(int32_t* x, int n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, x, n, v);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
 }  // namespace hoqri
 
 using namespace hoqri;
@@ -179,12 +205,9 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       // and keep the remaining rows of the factor at zero
       const int64_t Rn = p->md[n].R;
       TimerScope to(p, HOQRI_KERNEL_ORTH, stream);
+      // rows R_n.. (empty slices) of the new factor are zeroed by the same launch
       HOQRI_TRY(launch_orth(Rn, p->K[n], p->sc.A, Up[n], nullptr, status, p->sc.orth_ws, p->sc.orth_ws_bytes,
-                            stream, true));
-      if (p->dims[n] > Rn) {
-        const int64_t ne = (p->dims[n] - Rn) * p->K[n];
-        hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(ne)), dim3(256), 0, stream, Up[n] + Rn * p->K[n], ne, 0.f);
-      }
+                            stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n]));
       HOQRI_TRY(refresh16(p, op, n, stream));
     }
     HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + t + 1, stream));
@@ -211,23 +234,21 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     HOQRI_HIP_TRY(hipGetLastError());
   }
   // factors back to the caller's row order, then final statistics
-  if (T > 0)
-    for (int n = 0; n < N; ++n)
-      hipLaunchKernelGGL(k_rows_from_labels, dim3(grid_of(p->dims[n] * p->K[n])), dim3(256), 0, stream, Up[n],
-                         p->md[n].inv, p->dims[n], p->K[n], d_U_inout[n]);
-  HOQRI_HIP_TRY(hipGetLastError());
+  if (T > 0) HOQRI_TRY(from_labels(p, d_U_inout, stream));
   double errs[kMaxOrder] = {0, 0, 0, 0};
   for (int n = 0; n < N; ++n)
     HOQRI_TRY(launch_orth_err(p->dims[n], p->K[n], d_U_inout[n], p->sc.f_dev + 8 + n, p->sc.orth_ws,
                               p->sc.orth_ws_bytes, stream));
   double fend = 0.0;
-  int32_t st = 0;
+  int32_t st = 0, skips = 0;
   HOQRI_HIP_TRY(hipMemcpyAsync(errs, p->sc.f_dev + 8, N * sizeof(double), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipMemcpyAsync(&fend, fsw + T, sizeof(double), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HOQRI_HIP_TRY(hipMemcpyAsync(&skips, status + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipStreamSynchronize(stream));
   if (st != 0) return HOQRI_ERR_BREAKDOWN;
   (void)have_prev;
+  stats->skipped_updates = skips;
   stats->sweeps = T;
   stats->norm_x2 = p->normx2;
   stats->f = fend;

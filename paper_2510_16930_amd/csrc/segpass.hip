@@ -31,9 +31,10 @@
 // so results are bitwise reproducible. Y_i may span several 16x16 blocks
 // (rows > 16 or columns > 16); then each block is handled by its own wave of
 // the workgroup and the TTMcTC partial products are added in LDS.
-#include "common.h"
+#include "passes.h"
 
 #include <cmath>
+#include <vector>
 
 namespace hoqri {
 namespace {
@@ -64,6 +65,16 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Item of a batched launch that owns block b: first[r] <= b < first[r+1].
+__device__ inline int batch_item(const int32_t* first, int count, int b) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
 __device__ inline f4 mfma4(float a, float b, f4 c) {
@@ -99,34 +110,6 @@ __device__ inline f4 mfma16(const float* a, const uint32_t* b, f4 c) {
   }
 }
 
-struct SegArgs {
-  const int32_t* oidx[3];   // other-mode element offsets (i_m * K_m), mode-sorted
-  const float* val;
-  const int32_t* seg_off;   // [R+1]
-  const int32_t* seg_row;   // [R]
-  int32_t R;
-  int32_t nnz;
-  int32_t nnz_pad;          // nnz rounded up to 16 (the stored length)
-  int32_t W;                // ranges
-  int32_t B, RB, CB;        // y_i blocks (16x16) per range, as RB x CB
-  int32_t RPW;              // ranges per workgroup
-  const void* U[3];         // factors of the other modes (float32 or 16-bit copies), ascending
-  uint32_t Ubytes[3];
-  float ascale;             // FP16: power of two applied to x * (row factors) before rounding
-  float yscale;             // 16-bit forms: exact unscale of y
-  int32_t K1;               // rank of the second other mode (row split for N = 4)
-  // TTMcTC
-  const float* gtop;        // stage-two operand [B][KN2][64][64]
-  float* A;
-  int32_t Kn;
-  float* carry;             // [W][2][32]
-  int32_t* meta;            // [W][4]
-  const int32_t* out_map;   // null: A rows in label order; else row r goes to out_map[r]
-  // core
-  const float* Uc;          // factor of the pass mode
-  int32_t Kc;
-  float* gpart;             // [groups][B][16*KN2][256]
-};
 
 __device__ inline int32_t range_lo(int64_t w, int64_t W, int64_t nnz) { return (int32_t)((w * nnz) / W); }
 
@@ -364,7 +347,7 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
 // TTMcTC pass
 // ---------------------------------------------------------------------------
 template <int NM1, int KN2, int PREC>
-__global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
+__device__ inline void ttm_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -372,7 +355,7 @@ __global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
   const int b = wv - rr * a.B;
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
   const int g = lane >> 4, q = lane & 15;
-  const int32_t w = blockIdx.x * a.RPW + rr;
+  const int32_t w = wg * a.RPW + rr;
   const bool multi = a.B > 1;
 
   float* ybat = lds + wv * (16 * YS);
@@ -475,16 +458,31 @@ __global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
   if (slot > 0) stage_two();
 }
 
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
+  ttm_body<NM1, KN2, PREC>(a, blockIdx.x);
+}
+
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_ttm_b(const SegArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  ttm_body<NM1, KN2, PREC>(d[r], blockIdx.x - first[r]);
+}
+
 // Adds the partial rows of slices that cross range boundaries and writes them.
 // One workgroup per range; only the owner of a split slice (the range where it
 // starts, holding its tail partial) works: the head partials of the following
 // ranges w0+1..w1 are summed in float64 by 8 thread groups with a fixed
 // stride, then the groups are added in order (deterministic).
-__global__ __launch_bounds__(256) void k_fix_split(const int32_t* meta, const float* carry, const int32_t* seg_row,
-                                                   const int32_t* seg_off, int32_t W, int32_t nnz, int32_t Kn,
-                                                   const int32_t* out_map, float* A) {
+__device__ inline void fix_body(const FixArgs& f, const int32_t w) {
   __shared__ double part[8][32];
-  const int32_t w = blockIdx.x;
+  const int32_t* meta = f.meta;
+  const float* carry = f.carry;
+  const int32_t* seg_row = f.seg_row;
+  const int32_t* seg_off = f.seg_off;
+  const int32_t W = f.W, nnz = f.nnz, Kn = f.Kn;
+  const int32_t* out_map = f.out_map;
+  float* A = f.A;
   const int32_t s_first = meta[w * 4 + 0], s_last = meta[w * 4 + 1], flags = meta[w * 4 + 2];
   const bool head_clip = flags & 1, tail_clip = flags & 2;
   if (!(tail_clip && !(s_first == s_last && head_clip))) return;
@@ -506,6 +504,13 @@ __global__ __launch_bounds__(256) void k_fix_split(const int32_t* meta, const fl
   }
 }
 
+__global__ __launch_bounds__(256) void k_fix_split(FixArgs f) { fix_body(f, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_fix_split_b(const FixArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  fix_body(d[r], blockIdx.x - first[r]);
+}
+
 // Zeroes the rows of empty slices: empty_row[r] (original order) or, with a
 // null list, the contiguous label-order rows row0 .. row0+E-1.
 __global__ void k_zero_rows(const int32_t* empty_row, int64_t row0, int64_t E, int32_t Kn, float* A) {
@@ -517,21 +522,13 @@ __global__ void k_zero_rows(const int32_t* empty_row, int64_t row0, int64_t E, i
   }
 }
 
-struct PrepArgs {
-  const float* G;
-  float* gtop;
-  int32_t B, CB, KN2, krow, kcol, Kn, mode, N, nm1;
-  int32_t om[3];          // other modes ascending
-  int32_t Ko[3];          // their ranks
-  int64_t gstride[4];     // C-order strides of G
-};
 
 // gtop[b][kb][t][lane] = G_(n)^T[j'][kn] with j' = 64 (lane/16) + t inside block b
 // (j' = c*16 + r), kn = 16 kb + lane%16; zero in padding.
-__global__ void k_prep_gtop(PrepArgs p) {
+__device__ inline void prep_body(const PrepArgs& p, const int blk) {
   const int64_t total = (int64_t)p.B * p.KN2 * 4096;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t idx = blk * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)p.nblk * blockDim.x) {
     const int lane = (int)(idx & 63);
     const int t = (int)((idx >> 6) & 63);
     const int64_t rest = idx >> 12;
@@ -557,11 +554,18 @@ __global__ void k_prep_gtop(PrepArgs p) {
   }
 }
 
+__global__ void k_prep_gtop(PrepArgs p) { prep_body(p, blockIdx.x); }
+
+__global__ void k_prep_gtop_b(const PrepArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  prep_body(d[r], blockIdx.x - first[r]);
+}
+
 // ---------------------------------------------------------------------------
 // Core pass
 // ---------------------------------------------------------------------------
 template <int NM1, int KN2, int PREC>
-__global__ __launch_bounds__(512) void k_core(SegArgs a) {
+__device__ inline void core_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -569,7 +573,7 @@ __global__ __launch_bounds__(512) void k_core(SegArgs a) {
   const int b = wv - rr * a.B;
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
   const int g = lane >> 4, q = lane & 15;
-  const int32_t w = blockIdx.x * a.RPW + rr;
+  const int32_t w = wg * a.RPW + rr;
   constexpr int KC = 16 * KN2;
   // this wave's partial G_(c)[kc][j'] for its block, in LDS (no loop-carried
   // registers): 16*KN2 x 256 floats, this lane owns j' = q*16 + 4g + 0..3
@@ -598,7 +602,7 @@ __global__ __launch_bounds__(512) void k_core(SegArgs a) {
   __syncthreads();
   // workgroup sum over its ranges (fixed order) for each block, one partial per block
   const int total = a.B * KC * 256;
-  float* out = a.gpart + (size_t)blockIdx.x * total;
+  float* out = a.gpart + (size_t)wg * total;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int bb = t / (KC * 256), rest = t - bb * (KC * 256);
     float v = 0.f;
@@ -607,21 +611,24 @@ __global__ __launch_bounds__(512) void k_core(SegArgs a) {
   }
 }
 
-struct CoreRedArgs {
-  const float* gpart;
-  int32_t groups, B, CB, KN2, krow, kcol, Kc, mode, nm1;
-  int32_t om[3], Ko[3];
-  int64_t gstride[4];
-  float* G;
-  double* fpart;
-};
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_core(SegArgs a) {
+  core_body<NM1, KN2, PREC>(a, blockIdx.x);
+}
+
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_core_b(const SegArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  core_body<NM1, KN2, PREC>(d[r], blockIdx.x - first[r]);
+}
+
 
 // Sums the workgroup partials in order (float64), scatters into G (C order),
 // and leaves per-block partial sums of squares for ||G||^2.
-__global__ void k_core_reduce(CoreRedArgs p) {
+__device__ inline void red_body(const CoreRedArgs& p, const int blk) {
   __shared__ double sh[256];
   const int total = p.B * 16 * p.KN2 * 256;
-  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int e = blk * 64 + (threadIdx.x & 63);
   const int sp = threadIdx.x >> 6;
   double acc = 0.0;
   if (e < total)
@@ -659,13 +666,22 @@ __global__ void k_core_reduce(CoreRedArgs p) {
     if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) p.fpart[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) p.fpart[blk] = sh[0];
 }
 
-__global__ void k_sum_f(const double* part, int n, double* out) {
+__global__ void k_core_reduce(CoreRedArgs p) { red_body(p, blockIdx.x); }
+
+__global__ void k_core_reduce_b(const CoreRedArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  red_body(d[r], blockIdx.x - first[r]);
+}
+
+__device__ inline void sum_body(const SumArgs& a) {
   __shared__ double sh[256];
+  const double* part = a.part;
+  double* out = a.out;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  for (int i = threadIdx.x; i < a.n; i += blockDim.x) acc += part[i];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
@@ -673,6 +689,12 @@ __global__ void k_sum_f(const double* part, int n, double* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ void k_sum_f(SumArgs a) { sum_body(a); }
+
+__global__ void k_sum_f_b(const SumArgs* d, const int32_t* first, int count) {
+  sum_body(d[batch_item(first, count, blockIdx.x)]);
 }
 
 struct PassGeom {
@@ -720,49 +742,44 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   return true;
 }
 
-template <int NM1, int KN2, int PREC>
-hipError_t launch_ttm_t(const SegArgs& a, int threads, size_t shmem, hipStream_t s) {
-  auto k = k_ttm<NM1, KN2, PREC>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  const int grid = (a.W + a.RPW - 1) / a.RPW;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), shmem, s, a);
-  return hipGetLastError();
-}
+// Kernel instances: one single-plan and one batched launch per
+// (order, rank blocks, precision).
+struct SegKernels {
+  const void* ttm;
+  const void* ttm_b;
+  const void* core;
+  const void* core_b;
+};
 
 template <int NM1, int KN2, int PREC>
-hipError_t launch_core_t(const SegArgs& a, int grid, int threads, size_t shmem, hipStream_t s) {
-  auto k = k_core<NM1, KN2, PREC>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), shmem, s, a);
-  return hipGetLastError();
+SegKernels seg_kernels_t() {
+  return SegKernels{(const void*)k_ttm<NM1, KN2, PREC>, (const void*)k_ttm_b<NM1, KN2, PREC>,
+                    (const void*)k_core<NM1, KN2, PREC>, (const void*)k_core_b<NM1, KN2, PREC>};
 }
 
 template <int PREC>
-hipError_t dispatch_ttm(int sel, const SegArgs& a, int threads, size_t shmem, hipStream_t s) {
-  switch (sel) {
-    case 11: return launch_ttm_t<1, 1, PREC>(a, threads, shmem, s);
-    case 12: return launch_ttm_t<1, 2, PREC>(a, threads, shmem, s);
-    case 21: return launch_ttm_t<2, 1, PREC>(a, threads, shmem, s);
-    case 22: return launch_ttm_t<2, 2, PREC>(a, threads, shmem, s);
-    case 31: return launch_ttm_t<3, 1, PREC>(a, threads, shmem, s);
-    case 32: return launch_ttm_t<3, 2, PREC>(a, threads, shmem, s);
-    default: return hipErrorInvalidValue;
+bool seg_kernels_p(int nm1, int kn2, SegKernels* k) {
+  switch (nm1 * 10 + kn2) {
+    case 11: *k = seg_kernels_t<1, 1, PREC>(); return true;
+    case 12: *k = seg_kernels_t<1, 2, PREC>(); return true;
+    case 21: *k = seg_kernels_t<2, 1, PREC>(); return true;
+    case 22: *k = seg_kernels_t<2, 2, PREC>(); return true;
+    case 31: *k = seg_kernels_t<3, 1, PREC>(); return true;
+    case 32: *k = seg_kernels_t<3, 2, PREC>(); return true;
+    default: return false;
   }
 }
 
-template <int PREC>
-hipError_t dispatch_core(int sel, const SegArgs& a, int grid, int threads, size_t shmem, hipStream_t s) {
-  switch (sel) {
-    case 11: return launch_core_t<1, 1, PREC>(a, grid, threads, shmem, s);
-    case 12: return launch_core_t<1, 2, PREC>(a, grid, threads, shmem, s);
-    case 21: return launch_core_t<2, 1, PREC>(a, grid, threads, shmem, s);
-    case 22: return launch_core_t<2, 2, PREC>(a, grid, threads, shmem, s);
-    case 31: return launch_core_t<3, 1, PREC>(a, grid, threads, shmem, s);
-    case 32: return launch_core_t<3, 2, PREC>(a, grid, threads, shmem, s);
-    default: return hipErrorInvalidValue;
-  }
+bool seg_kernels(int key, SegKernels* k) {
+  const int nm1 = key / 100, kn2 = (key / 10) % 10, prec = key % 10;
+  if (prec == P_FP32) return seg_kernels_p<P_FP32>(nm1, kn2, k);
+  if (prec == P_BF16) return seg_kernels_p<P_BF16>(nm1, kn2, k);
+  if (prec == P_FP16) return seg_kernels_p<P_FP16>(nm1, kn2, k);
+  return false;
+}
+
+hipError_t set_shmem(const void* k, size_t shmem) {
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
 }
 
 // Rounds to the 16-bit copy: bfloat16 (nearest even), or float16 of u * 2^15
@@ -817,14 +834,16 @@ hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh
   return HOQRI_OK;
 }
 
-hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
-                           const int32_t* out_map, hipStream_t s) {
+hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
+                         const int32_t* out_map, TtmJob* job) {
   if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
   const ModeData& md = p->md[mode];
-  // 1. stage-two operand
-  PrepArgs pa{};
+  *job = TtmJob{};
+  job->key = seg_key(g.nm1, KN2, op.prec);
+  // stage-two operand
+  PrepArgs& pa = job->prep;
   pa.G = G;
   pa.gtop = p->sc.gtop;
   pa.B = g.B;
@@ -841,15 +860,11 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
     pa.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
   }
   g_strides(p, pa.gstride);
-  {
-    TimerScope tp(p, HOQRI_KERNEL_FIXUP, s);
-    int64_t total = (int64_t)g.B * KN2 * 4096;
-    int grid = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_prep_gtop, dim3(grid), dim3(256), 0, s, pa);
-    HOQRI_HIP_TRY(hipGetLastError());
-  }
-  // 2. main pass
-  SegArgs a{};
+  const int64_t total = (int64_t)g.B * KN2 * 4096;
+  pa.nblk = (int)((total + 255) / 256);
+  job->prep_blocks = pa.nblk;
+  // main pass
+  SegArgs& a = job->seg;
   if (!fill_common(a, p, mode, g, op)) return HOQRI_ERR_UNSUPPORTED;
   int64_t W = md.ranges;
   if (W > p->nnz) W = p->nnz;
@@ -861,38 +876,35 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
   a.carry = p->sc.carry;
   a.meta = p->sc.meta;
   a.out_map = out_map;
-  const int threads = 64 * g.B * a.RPW;
-  const size_t shmem =
-      (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 + g.B * a.RPW * 128) * 4;
-  hipError_t e = hipSuccess;
-  {
-  TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
-  const int sel = g.nm1 * 10 + KN2;
-  if (op.prec == OP_FP32) e = dispatch_ttm<P_FP32>(sel, a, threads, shmem, s);
-  else if (op.prec == OP_BF16) e = dispatch_ttm<P_BF16>(sel, a, threads, shmem, s);
-  else e = dispatch_ttm<P_FP16>(sel, a, threads, shmem, s);
-  }
-  if (e != hipSuccess) return HOQRI_ERR_HIP;
-  TimerScope tf(p, HOQRI_KERNEL_FIXUP, s);
-  // 3. split slices and empty rows
-  hipLaunchKernelGGL(k_fix_split, dim3((unsigned)W), dim3(256), 0, s, p->sc.meta, p->sc.carry, md.seg_row,
-                     md.seg_off, a.W, a.nnz, a.Kn, out_map, A);
-  if (md.E > 0) {
-    int64_t tot = md.E * a.Kn;
-    int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
-    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, out_map ? md.empty_row : (const int32_t*)nullptr,
-                       md.R, md.E, a.Kn, A);
-  }
-  HOQRI_HIP_TRY(hipGetLastError());
+  job->threads = 64 * g.B * a.RPW;
+  job->shmem = (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 +
+                        g.B * a.RPW * 128) * 4;
+  job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
+  // split slices
+  FixArgs& f = job->fix;
+  f.meta = p->sc.meta;
+  f.carry = p->sc.carry;
+  f.seg_row = md.seg_row;
+  f.seg_off = md.seg_off;
+  f.W = a.W;
+  f.nnz = a.nnz;
+  f.Kn = a.Kn;
+  f.out_map = out_map;
+  f.A = A;
+  job->fix_blocks = a.W;
+  SegKernels k;
+  if (!seg_kernels(job->key, &k)) return HOQRI_ERR_UNSUPPORTED;
   return HOQRI_OK;
 }
 
-hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, hipStream_t s) {
+hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, CoreJob* job) {
   const int mode = p->core_mode;
   if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
-  SegArgs a{};
+  *job = CoreJob{};
+  job->key = seg_key(g.nm1, KN2, op.prec);
+  SegArgs& a = job->seg;
   if (!fill_common(a, p, mode, g, op)) return HOQRI_ERR_UNSUPPORTED;
   // each wave keeps its partial (16*KN2 x 256 floats) in LDS: at most 160 KB per workgroup
   const int per_wave = 16 * KN2 * 256 * 4 + 128 * 4;
@@ -910,18 +922,10 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
   a.Uc = op.U32[mode];
   a.Kc = p->K[mode];
   a.gpart = p->sc.gpart;
-  const int threads = 64 * g.B * a.RPW;
-  const size_t shmem = (size_t)a.RPW * g.B * per_wave;
-  hipError_t e = hipSuccess;
-  {
-  TimerScope ts(p, HOQRI_KERNEL_CORE, s);
-  const int sel = g.nm1 * 10 + KN2;
-  if (op.prec == OP_FP32) e = dispatch_core<P_FP32>(sel, a, (int)groups, threads, shmem, s);
-  else if (op.prec == OP_BF16) e = dispatch_core<P_BF16>(sel, a, (int)groups, threads, shmem, s);
-  else e = dispatch_core<P_FP16>(sel, a, (int)groups, threads, shmem, s);
-  }
-  if (e != hipSuccess) return HOQRI_ERR_HIP;
-  CoreRedArgs r{};
+  job->threads = 64 * g.B * a.RPW;
+  job->shmem = (size_t)a.RPW * g.B * per_wave;
+  job->seg_blocks = (int)groups;
+  CoreRedArgs& r = job->red;
   r.gpart = p->sc.gpart;
   r.groups = (int32_t)groups;
   r.B = g.B;
@@ -940,9 +944,137 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
   r.G = G;
   r.fpart = p->sc.fpart;
   const int total = g.B * 16 * KN2 * 256;
-  const int nblk = (total + 63) / 64;
-  hipLaunchKernelGGL(k_core_reduce, dim3(nblk), dim3(256), 0, s, r);
-  hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, p->sc.fpart, nblk, f_out ? f_out : p->sc.f_dev);
+  job->red_blocks = (total + 63) / 64;
+  job->sum.part = p->sc.fpart;
+  job->sum.n = job->red_blocks;
+  job->sum.out = f_out ? f_out : p->sc.f_dev;
+  SegKernels k;
+  if (!seg_kernels(job->key, &k)) return HOQRI_ERR_UNSUPPORTED;
+  return HOQRI_OK;
+}
+
+hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
+                           const int32_t* out_map, hipStream_t s) {
+  TtmJob job;
+  HOQRI_TRY(prepare_ttm(p, mode, op, G, A, out_map, &job));
+  SegKernels k;
+  seg_kernels(job.key, &k);
+  {
+    TimerScope tp(p, HOQRI_KERNEL_FIXUP, s);
+    hipLaunchKernelGGL(k_prep_gtop, dim3(job.prep_blocks), dim3(256), 0, s, job.prep);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+  {
+    TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
+    HOQRI_HIP_TRY(set_shmem(k.ttm, job.shmem));
+    void* args[] = {(void*)&job.seg};
+    HOQRI_HIP_TRY(hipLaunchKernel(k.ttm, dim3(job.seg_blocks), dim3(job.threads), args, job.shmem, s));
+  }
+  TimerScope tf(p, HOQRI_KERNEL_FIXUP, s);
+  hipLaunchKernelGGL(k_fix_split, dim3(job.fix_blocks), dim3(256), 0, s, job.fix);
+  const ModeData& md = p->md[mode];
+  if (md.E > 0) {
+    int64_t tot = md.E * p->K[mode];
+    int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, out_map ? md.empty_row : (const int32_t*)nullptr,
+                       md.R, md.E, p->K[mode], A);
+  }
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, hipStream_t s) {
+  CoreJob job;
+  HOQRI_TRY(prepare_core(p, op, G, f_out, &job));
+  SegKernels k;
+  seg_kernels(job.key, &k);
+  {
+    TimerScope ts(p, HOQRI_KERNEL_CORE, s);
+    HOQRI_HIP_TRY(set_shmem(k.core, job.shmem));
+    void* args[] = {(void*)&job.seg};
+    HOQRI_HIP_TRY(hipLaunchKernel(k.core, dim3(job.seg_blocks), dim3(job.threads), args, job.shmem, s));
+  }
+  hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(256), 0, s, job.red);
+  hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches (request server)
+// ---------------------------------------------------------------------------
+bool stage_ttm_group(const TtmJob* const* jobs, int n, Staging& st, TtmGroup* g) {
+  if (n < 1 || n > 1024) return false;
+  std::vector<PrepArgs> prep(n);
+  std::vector<SegArgs> seg(n);
+  std::vector<FixArgs> fix(n);
+  std::vector<int32_t> nb_prep(n), nb_seg(n), nb_fix(n);
+  for (int i = 0; i < n; ++i) {
+    prep[i] = jobs[i]->prep;
+    seg[i] = jobs[i]->seg;
+    fix[i] = jobs[i]->fix;
+    nb_prep[i] = jobs[i]->prep_blocks;
+    nb_seg[i] = jobs[i]->seg_blocks;
+    nb_fix[i] = jobs[i]->fix_blocks;
+  }
+  g->key = jobs[0]->key;
+  g->threads = jobs[0]->threads;
+  g->shmem = jobs[0]->shmem;
+  return stage_table(st, prep.data(), nb_prep.data(), n, &g->prep) &&
+         stage_table(st, seg.data(), nb_seg.data(), n, &g->seg) && stage_table(st, fix.data(), nb_fix.data(), n, &g->fix);
+}
+
+bool stage_core_group(const CoreJob* const* jobs, int n, Staging& st, CoreGroup* g) {
+  if (n < 1 || n > 1024) return false;
+  std::vector<SegArgs> seg(n);
+  std::vector<CoreRedArgs> red(n);
+  std::vector<SumArgs> sum(n);
+  std::vector<int32_t> nb_seg(n), nb_red(n), ones(n);
+  for (int i = 0; i < n; ++i) {
+    seg[i] = jobs[i]->seg;
+    red[i] = jobs[i]->red;
+    sum[i] = jobs[i]->sum;
+    nb_seg[i] = jobs[i]->seg_blocks;
+    nb_red[i] = jobs[i]->red_blocks;
+    ones[i] = 1;
+  }
+  g->key = jobs[0]->key;
+  g->threads = jobs[0]->threads;
+  g->shmem = jobs[0]->shmem;
+  return stage_table(st, seg.data(), nb_seg.data(), n, &g->seg) &&
+         stage_table(st, red.data(), nb_red.data(), n, &g->red) && stage_table(st, sum.data(), ones.data(), n, &g->sum);
+}
+
+hoqri_status launch_ttm_group(const TtmGroup& g, hipStream_t s) {
+  SegKernels k;
+  if (!seg_kernels(g.key, &k)) return HOQRI_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_prep_gtop_b, dim3(g.prep.blocks), dim3(256), 0, s, (const PrepArgs*)g.prep.descs,
+                     g.prep.first, g.prep.count);
+  HOQRI_HIP_TRY(set_shmem(k.ttm_b, g.shmem));
+  const SegArgs* d = (const SegArgs*)g.seg.descs;
+  const int32_t* first = g.seg.first;
+  int count = g.seg.count;
+  void* args[] = {(void*)&d, (void*)&first, (void*)&count};
+  HOQRI_HIP_TRY(hipLaunchKernel(k.ttm_b, dim3(g.seg.blocks), dim3(g.threads), args, g.shmem, s));
+  hipLaunchKernelGGL(k_fix_split_b, dim3(g.fix.blocks), dim3(256), 0, s, (const FixArgs*)g.fix.descs, g.fix.first,
+                     g.fix.count);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status launch_core_group(const CoreGroup& g, hipStream_t s) {
+  SegKernels k;
+  if (!seg_kernels(g.key, &k)) return HOQRI_ERR_UNSUPPORTED;
+  HOQRI_HIP_TRY(set_shmem(k.core_b, g.shmem));
+  const SegArgs* d = (const SegArgs*)g.seg.descs;
+  const int32_t* first = g.seg.first;
+  int count = g.seg.count;
+  void* args[] = {(void*)&d, (void*)&first, (void*)&count};
+  HOQRI_HIP_TRY(hipLaunchKernel(k.core_b, dim3(g.seg.blocks), dim3(g.threads), args, g.shmem, s));
+  hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(256), 0, s, (const CoreRedArgs*)g.red.descs,
+                     g.red.first, g.red.count);
+  hipLaunchKernelGGL(k_sum_f_b, dim3(g.sum.blocks), dim3(256), 0, s, (const SumArgs*)g.sum.descs, g.sum.first,
+                     g.sum.count);
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
 }

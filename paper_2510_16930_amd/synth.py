@@ -28,6 +28,8 @@ __all__ = [
     "coo_zipf_torch",
     "coo_uniform_torch",
     "gaussian_start_torch",
+    "serve_stream_params",
+    "poisson_arrivals",
 ]
 
 
@@ -215,3 +217,26 @@ def gaussian_start_torch(dims: Sequence[int], ranks: Sequence[int], seed: int, d
         g.manual_seed(int(seed) + n)
         out.append(torch.randn((int(d), int(k)), generator=g, device=device, dtype=torch.float32))
     return out
+
+
+def serve_stream_params(n_requests: int, seed: int, dim_range=(1_000, 200_000), nnz_range=(10_000, 2_000_000),
+                        ranks=(4, 8, 16)):
+    """Parameters of a stream of 3-way requests: each mode's size and the nnz are
+    log-uniform on their ranges (independently), one rank from `ranks` for all
+    three modes; each request also gets a data seed and a start seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_requests):
+        dims = tuple(int(round(math.exp(rng.uniform(math.log(dim_range[0]), math.log(dim_range[1])))))
+                     for _ in range(3))
+        nnz = int(round(math.exp(rng.uniform(math.log(nnz_range[0]), math.log(nnz_range[1])))))
+        r = int(ranks[int(rng.integers(len(ranks)))])
+        out.append(dict(dims=dims, nnz=nnz, ranks=(r, r, r), data_seed=int(seed) * 100_000 + i,
+                        init_seed=int(seed) * 100_000 + 50_000 + i))
+    return out
+
+
+def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process with the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))

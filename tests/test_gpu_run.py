@@ -151,3 +151,30 @@ def test_orthonormalize_input_from_raw_gaussian():
     U0 = O.orthonormal_start([r.astype(np.float32).astype(np.float64) for r in raw])
     Uo, Go, h = O.hoqri(idx, vals.astype(np.float32).astype(np.float64), dims, K, U0, sweeps=3)
     assert st.f == pytest.approx(h["f_sweep"][-1], rel=1e-5)
+
+
+def test_rank_deficient_mode_kept_like_oracle():
+    # sum of two rank-one terms on a 20x25x30 block inside 60x70x80: the mode-0
+    # unfolding has rank 2 < K_0 = 3, so every mode-0 update is rank deficient
+    rng = np.random.default_rng(22)
+    dims, K = (60, 70, 80), (3, 2, 2)
+    rows = [np.sort(rng.choice(d, size=s, replace=False)) for d, s in zip(dims, (20, 25, 30))]
+    block = sum(np.einsum("i,j,k->ijk", rng.standard_normal(20), rng.standard_normal(25), rng.standard_normal(30))
+                for _ in range(2))
+    grids = np.meshgrid(*rows, indexing="ij")
+    idx = np.stack([g.ravel() for g in grids]).astype(np.int32)
+    vals32 = block.ravel().astype(np.float32)
+    start = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 9))]
+    plan = H.hoqri_plan_create(dev(idx), dev(vals32), dims, K)
+    with pytest.raises(H.HoqriError) as e:
+        H.hoqri_run(plan, [dev(u) for u in start], max_sweeps=2)
+    assert e.value.status == -4
+    Us = [dev(u) for u in start]
+    G, st = H.hoqri_run(plan, Us, max_sweeps=3, keep_on_breakdown=True)
+    Uo, Go, h = O.hoqri(idx, vals32.astype(np.float64), dims, K, [u.astype(np.float64) for u in start], sweeps=3,
+                        on_breakdown="keep")
+    assert st.skipped_updates == h["skipped"] == 3
+    assert torch.equal(Us[0].cpu(), torch.from_numpy(start[0]))
+    for n in (1, 2):
+        assert np.abs(Us[n].cpu().numpy() - Uo[n]).max() < 1e-4
+    assert st.f == pytest.approx(h["f_sweep"][-1], rel=1e-5)

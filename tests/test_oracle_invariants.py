@@ -178,3 +178,24 @@ def test_stopping_rules():
     assert len(f) < 200 and abs(f[-1] - f[-2]) <= 1e-6 * f[-1]
     _, _, h2 = O.hoqri(idx, vals, dims, K, start, sweeps=200, tol=1e-12, stop="err")
     assert len(h2["f_sweep"]) <= 200
+
+
+def test_rank_deficient_mode_is_kept_on_request():
+    # X = sum of two rank-one terms on a 6x7x8 support: every mode-0 unfolding has
+    # rank 2 < K_0 = 3, so A^(0) = X_(0) (U_1 kron U_2) G_(0)^T is rank deficient at
+    # every step while modes 1 and 2 (K = 2) update normally.
+    rng = np.random.default_rng(21)
+    dims, K = (6, 7, 8), (3, 2, 2)
+    X = sum(np.einsum("i,j,k->ijk", rng.standard_normal(6), rng.standard_normal(7), rng.standard_normal(8))
+            for _ in range(2))
+    idx = np.stack(np.unravel_index(np.arange(X.size), dims)).astype(np.int32)
+    vals = X.ravel()
+    U0 = O.orthonormal_start(synth.gaussian_start(dims, K, 4))
+    with pytest.raises(O.RankDeficient):
+        O.hoqri(idx, vals, dims, K, U0, sweeps=2)
+    U, G, h = O.hoqri(idx, vals, dims, K, U0, sweeps=3, on_breakdown="keep")
+    assert h["skipped"] == 3                      # mode 0 in each of the 3 sweeps
+    np.testing.assert_array_equal(U[0], U0[0])    # kept exactly
+    assert not np.array_equal(U[1], U0[1])        # the other modes moved
+    f = h["f_step"] + [h["f_sweep"][-1]]
+    assert all(b >= a - 1e-12 * abs(b) for a, b in zip(f, f[1:]))  # Theorem 1 still holds
