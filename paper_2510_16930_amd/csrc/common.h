@@ -31,10 +31,12 @@ constexpr int kMaxSweeps = 4096;
 // Per-mode data of a plan: the nonzeros stably sorted by their mode-n index,
 // stored as structure of arrays, and the table of nonempty slices.
 struct ModeData {
-  // oidx[m'] for the m'-th other mode (ascending, mode n skipped): the factor
-  // element offset i_m * K_m of each nonzero, in mode-n sorted order.
-  int32_t* oidx[kMaxOrder - 1];
-  float* val;          // values in mode-n sorted order
+  // The nonzeros in mode-n sorted order as block records: for every block of
+  // 16 nonzeros (e = 16b + 4t + g) and lane group g, N dwords-quads in turn:
+  // for each other mode m' (ascending, mode n skipped) the factor element
+  // offsets label(i_m) * K_m of nonzeros 4t+g (t = 0..3), then their values
+  // (float32 bits). rec[b][g][a][t], 16 N dwords per block; padding is zero.
+  int32_t* rec;
   int32_t* seg_row;    // [R]   mode-n index of each nonempty slice (ascending)
   int32_t* seg_off;    // [R+1] first nonzero of each slice in sorted order
   int32_t* lab;        // [I_n] new label of original index i (descending slice size)
@@ -60,6 +62,9 @@ struct Scratch {
   int32_t* status;     // device status flags [4]
   double* f_dev;       // scalars [64]
   double* fsweep;      // f after each sweep inside hoqri_run [kMaxSweeps + 1]
+  float* ybuf;         // core pass rows y_i of the core mode [ybuf_rows][B_c * 256] (row-writing path)
+  float* ycarry;       // their split-slice partials [core_w][2][B_c * 256]
+  int32_t* ymeta;      // [core_w][4]
   size_t orth_ws_bytes;
 };
 
@@ -85,7 +90,10 @@ struct hoqri_plan {
   double normx2;       // ||X||^2 (float64)
   double maxabs_x;     // max |x| over the merged nonzeros
   int32_t core_mode;   // mode whose sorted copy the core pass reads (fewest slices)
-  int32_t core_groups; // workgroups of the core pass (partials to reduce)
+  int32_t core_groups; // partials the core reduction sums
+  int32_t core_rows;   // the core pass writes slice rows (see Layout)
+  int64_t ybuf_rows;
+  int32_t core_w;
   hoqri::ModeData md[hoqri::kMaxOrder];
   hoqri::Scratch sc;
   void* ws;
@@ -105,8 +113,13 @@ struct Layout {
   size_t run_scratch;  // scratch of the passes (overlaps build_tmp)
   size_t sort_tmp;     // rocPRIM temporary storage
   int32_t ranges[kMaxOrder];
-  int32_t core_groups;
+  int32_t core_groups;   // partial blocks reduced by the core pass
+  int32_t core_mode;     // mode whose sorted copy the core pass reads
+  int32_t core_rows;     // nonzero: core pass writes slice rows y_i, then a small product with U^(c)
+  int64_t ybuf_rows;     // rows of the slice-row buffer (>= nonempty slices of the core mode)
+  int32_t core_w;        // work ranges of the row-writing core pass
 };
+constexpr int kCoreChunk = 256;  // rows per partial of the core product U^(c)T Y
 
 hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L);
 hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz);

@@ -18,8 +18,7 @@
 namespace hoqri {
 
 struct SegArgs {
-  const int32_t* oidx[3];   // other-mode element offsets (i_m * K_m), mode-sorted
-  const float* val;
+  const int32_t* rec;       // mode-sorted block records (ModeData::rec)
   const int32_t* seg_off;   // [R+1]
   const int32_t* seg_row;   // [R]
   int32_t R;
@@ -75,6 +74,20 @@ struct CoreRedArgs {
   double* fpart;
 };
 
+// Core product of the row-writing core pass: partial[chunk][b][kc][j'] =
+// sum over the chunk's rows v of U^(c)(label(v), kc) * row_v[b][j'], where the
+// rows are the complete slice rows ybuf[0..R) followed by the split-slice
+// partials ycarry[w][head / tail] (valid ones only, per ymeta).
+struct CoreGemmArgs {
+  const float* ybuf;
+  const float* ycarry;
+  const int32_t* ymeta;
+  const int32_t* seg_row;
+  const float* Uc;
+  int32_t Kc, KC, R, W, B;
+  float* gpart;
+};
+
 struct SumArgs {
   const double* part;
   int32_t n;
@@ -96,10 +109,12 @@ struct TtmJob {
 };
 
 struct CoreJob {
-  int key, threads;
+  int key, threads;  // key + 1000: row-writing core pass
   size_t shmem;
   SegArgs seg;
   int seg_blocks;
+  CoreGemmArgs gemm;  // row-writing path only
+  int gemm_blocks;
   CoreRedArgs red;
   int red_blocks;
   SumArgs sum;
@@ -221,7 +236,7 @@ struct TtmGroup {
 struct CoreGroup {
   int key, threads;
   size_t shmem;
-  BatchTable seg, red, sum;
+  BatchTable seg, gemm, red, sum;
 };
 struct OrthGroup {
   BatchTable g1, r1, c1, g2, r2, c2, ap;

@@ -4,6 +4,7 @@
 //
 // Integer and sort dominated; runs once per tensor. Sorting uses rocPRIM's
 // stable radix sort; every other step is a small kernel of this file.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <cstdlib>
@@ -184,40 +185,39 @@ struct GatherArgs {
   int64_t stride, nnz;
   int32_t N, mode;
   int32_t K[kMaxOrder];
-  int32_t* oidx[kMaxOrder - 1];
-  float* val;
+  int32_t* rec;
   int32_t* modeidx;
   const int32_t* lab[kMaxOrder];  // label maps: stored offsets and slice rows use labels
 };
 
-// Mode-n sorted copy: other-mode factor offsets i_m * K_m, values, and i_n.
-// The copy is stored in blocks of 16 nonzeros, each 4x4-transposed: logical
-// position 16b + 4t + g lives at physical 16b + 4g + t, so one 16-byte load of
-// lane group g in the segment passes returns logical 16b + g + {0, 4, 8, 12}.
+// Mode-n sorted copy as block records (see ModeData::rec): nonzero
+// j = 16b + 4t + g stores its other-mode factor offsets label(i_m) * K_m at
+// rec[b][g][c][t] (c-th other mode) and its value at rec[b][g][N-1][t]; a lane
+// group of the segment passes reads its record with one dword per lane.
 // Positions nnz .. nnz_pad-1 (padding to a multiple of 16) hold zeros.
-__device__ inline int64_t phys16(int64_t j) { return (j & ~int64_t(15)) + 4 * (j & 3) + ((j & 15) >> 2); }
-
 __global__ void k_gather_mode(GatherArgs a) {
   const int64_t npad = (a.nnz + 15) / 16 * 16;
+  const int N = a.N;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < npad;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t pj = phys16(j);
+    const int64_t b = j >> 4;
+    const int t = (int)((j & 15) >> 2), g = (int)(j & 3);
+    int32_t* r = a.rec + b * 16 * N + g * 4 * N + t;
     if (j >= a.nnz) {
-      for (int c = 0; c < a.N - 1; ++c) a.oidx[c][pj] = 0;
-      a.val[pj] = 0.f;
+      for (int c = 0; c < N; ++c) r[4 * c] = 0;
       continue;
     }
     int64_t src = a.perm ? a.perm[j] : j;
     int c = 0;
-    for (int m = 0; m < a.N; ++m) {
+    for (int m = 0; m < N; ++m) {
       const int32_t i = a.cidx[(int64_t)m * a.stride + src];
       if (m == a.mode) {
         a.modeidx[j] = i;  // original index: slice boundaries
       } else {
-        a.oidx[c++][pj] = a.lab[m][i] * a.K[m];
+        r[4 * c++] = a.lab[m][i] * a.K[m];
       }
     }
-    a.val[pj] = a.cval[src];
+    r[4 * (N - 1)] = __float_as_int(a.cval[src]);
   }
 }
 
@@ -380,8 +380,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   // persistent
   const int64_t npad = (nnz + 15) / 16 * 16;
   for (int n = 0; n < N; ++n) {
-    for (int m = 0; m < N - 1; ++m) c.take<int32_t>(npad);
-    c.take<float>(npad);
+    c.take<int32_t>(npad * N);  // block records
     int64_t rmax = dims[n] < nnz ? dims[n] : nnz;
     c.take<int32_t>(rmax);
     c.take<int32_t>(rmax + 1);
@@ -430,6 +429,42 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     L->ranges[n] = choose_ranges(nnz);
     if (L->ranges[n] > rmax) rmax = L->ranges[n];
   }
+  // core mode, from the shape alone: cost ~ nnz / K_n (Kronecker work) plus an
+  // upper bound min(I_n, nnz) of its nonempty slices (per-slice work)
+  int cm = 0;
+  double best = 0;
+  for (int n = 0; n < N; ++n) {
+    const double cost = (double)nnz / K[n] + (double)(dims[n] < nnz ? dims[n] : nnz);
+    if (n == 0 || cost < best) {
+      cm = n;
+      best = cost;
+    }
+  }
+  L->core_mode = cm;
+  // row-writing core pass when its row buffer stays small next to the
+  // nonzero streams (otherwise per-wave partials in LDS)
+  {
+    int om[kMaxOrder];
+    const int no = other_modes(N, cm, om);
+    int64_t krow = 1;
+    for (int q = 0; q < no - 1; ++q) krow *= K[om[q]];
+    const int64_t Bc = ((krow + 15) / 16) * ((K[om[no - 1]] + 15) / 16);
+    const int64_t KC = 16 * ((K[cm] + 15) / 16);
+    const int64_t rows = dims[cm] < nnz ? dims[cm] : nnz;
+    const int64_t ybytes = rows * Bc * 256 * 4;
+    const int64_t stream = nnz * 4 * N;
+    int64_t w = nnz / 4096;
+    if (w < 1) w = 1;
+    if (w > 8192) w = 8192;
+    L->core_rows = (Bc <= 8 && ybytes <= std::max<int64_t>(2 * stream, 16 << 20)) ? 1 : 0;
+    L->ybuf_rows = L->core_rows ? rows : 0;
+    L->core_w = L->core_rows ? (int32_t)w : 0;
+    if (L->core_rows) {
+      const int64_t chunks = (rows + 2 * w + kCoreChunk - 1) / kCoreChunk;
+      groups = (int32_t)chunks;
+      gpart = (size_t)(Bc * KC * 256);
+    }
+  }
   L->core_groups = groups;
   int64_t IKsum = 0;
   for (int n = 0; n < N; ++n) IKsum += dims[n] * K[n];
@@ -448,6 +483,12 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   r.take<int32_t>(64);                  // status
   r.take<double>(64);                   // scalars
   r.take<double>(kMaxSweeps + 1);       // f after each sweep
+  if (L->core_rows) {
+    const int64_t row = (int64_t)(gpart / (16 * ((K[L->core_mode] + 15) / 16)));  // B_c * 256
+    r.take<float>((size_t)(L->ybuf_rows * row));             // slice rows
+    r.take<float>((size_t)L->core_w * 2 * row);               // split-slice partials
+    r.take<int32_t>((size_t)L->core_w * 4);                   // their metadata
+  }
   size_t run = r.off;
   L->persistent = persistent;
   L->build_tmp = build;
@@ -483,8 +524,7 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   const int64_t npad_in = (nnz_in + 15) / 16 * 16;
   for (int n = 0; n < N; ++n) {
     ModeData& md = p->md[n];
-    for (int m = 0; m < N - 1; ++m) md.oidx[m] = c.take<int32_t>(npad_in);
-    md.val = c.take<float>(npad_in);
+    md.rec = c.take<int32_t>(npad_in * N);
     int64_t rmax = p->dims[n] < nnz_in ? p->dims[n] : nnz_in;
     md.seg_row = c.take<int32_t>(rmax);
     md.seg_off = c.take<int32_t>(rmax + 1);
@@ -618,8 +658,7 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
     ga.N = N;
     ga.mode = n;
     for (int m = 0; m < N; ++m) ga.K[m] = p->K[m];
-    for (int m = 0; m < N - 1; ++m) ga.oidx[m] = md.oidx[m];
-    ga.val = md.val;
+    ga.rec = md.rec;
     ga.modeidx = modeidx;
     k_gather_mode<<<grid_for(nnz + 16), kThreads, 0, s>>>(ga);
     k_head_flags<<<grid_for(nnz), kThreads, 0, s>>>(modeidx, nnz, head);
@@ -632,22 +671,17 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   int64_t Rh[kMaxOrder];
   HOQRI_HIP_TRY(hipMemcpyAsync(Rh, small + 2, N * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HOQRI_HIP_TRY(hipStreamSynchronize(s));
-  int best = 0;
-  double best_cost = 0;
   for (int n = 0; n < N; ++n) {
     p->md[n].R = Rh[n];
     p->md[n].E = p->dims[n] - Rh[n];
     p->md[n].empty_row = p->md[n].inv + Rh[n];  // original indices of the empty slices
     p->md[n].ranges = L.ranges[n];
-    // core pass cost on mode n ~ nnz / K_n + R_n (per unit prod K)
-    double cost = (double)nnz / p->K[n] + (double)Rh[n];
-    if (n == 0 || cost < best_cost) {
-      best = n;
-      best_cost = cost;
-    }
   }
-  p->core_mode = best;
+  p->core_mode = L.core_mode;
   p->core_groups = L.core_groups;
+  p->core_rows = L.core_rows;
+  p->ybuf_rows = L.ybuf_rows;
+  p->core_w = L.core_w;
   return HOQRI_OK;
 }
 
@@ -664,6 +698,13 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
     pass_sizes(p->N, p->K, n, &g1, &g2);
     if (g1 > gtop_max) gtop_max = g1;
     if (g2 > gpart) gpart = g2;
+  }
+  size_t row = 0;  // B_c * 256 (row-writing core pass)
+  if (L.core_rows) {
+    size_t g1, g2;
+    pass_sizes(p->N, p->K, L.core_mode, &g1, &g2);
+    gpart = g2;
+    row = g2 / (16 * ((p->K[L.core_mode] + 15) / 16));
   }
   int32_t rmax = 0;
   for (int n = 0; n < p->N; ++n)
@@ -684,6 +725,13 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
   p->sc.status = r.take<int32_t>(64);
   p->sc.f_dev = r.take<double>(64);
   p->sc.fsweep = r.take<double>(kMaxSweeps + 1);
+  p->sc.ybuf = p->sc.ycarry = nullptr;
+  p->sc.ymeta = nullptr;
+  if (L.core_rows) {
+    p->sc.ybuf = r.take<float>((size_t)(L.ybuf_rows * row));
+    p->sc.ycarry = r.take<float>((size_t)L.core_w * 2 * row);
+    p->sc.ymeta = r.take<int32_t>((size_t)L.core_w * 4);
+  }
 }
 
 extern "C" hoqri_status hoqri_plan_create(hoqri_plan** plan, int32_t order, const int64_t* dims,

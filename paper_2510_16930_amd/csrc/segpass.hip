@@ -44,6 +44,10 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
 constexpr int YS = 260;                      // LDS floats per staged y_i block (256 + pad)
+// finished slices staged per stage-two product: 8 when a y_i tile is one
+// wave's (more waves fit in LDS), 16 when it spans several waves (halves the
+// cross-wave reductions)
+__host__ __device__ inline int stage_slots(int B) { return B > 1 ? 16 : 8; }
 constexpr int KIND_COMPLETE = 0, KIND_HEAD = 1, KIND_TAIL = 2;
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
@@ -186,26 +190,36 @@ __device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uin
 // two steps earlier.
 template <int NM1>
 struct PipeSet {
-  f4 x;
+  int32_t rec;     // this lane's dword of the block record (indices and values, see below)
   float ga[4];     // row-factor part of the A operand (float32)
   uint32_t gb[4];  // column-factor entry: float32 bits, or 16-bit raw bits
-  i4 j0, j1, j2;
 };
+
+// Lane n of each 16-lane row, broadcast to the whole row (DPP row_newbcast).
+template <int N>
+__device__ inline int32_t row_bcast(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+}
+// Dwords 4A .. 4A+3 of this row's group record.
+template <int A>
+__device__ inline i4 group_quad(int32_t v) {
+  return i4{row_bcast<4 * A + 0>(v), row_bcast<4 * A + 1>(v), row_bcast<4 * A + 2>(v), row_bcast<4 * A + 3>(v)};
+}
 
 template <int NM1, int PREC, typename OnSeg>
 __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
                                   uint32_t ka4, uint32_t kb4, uint32_t kc4, int lane, int32_t* wlds,
                                   OnSeg&& on_seg) {
   const int g = lane >> 4;
-  const uint32_t nb4 = (uint32_t)a.nnz_pad * 4u;
-  const auto rI0 = make_rsrc(a.oidx[0], nb4);
-  const auto rI1 = make_rsrc(a.oidx[1], NM1 >= 2 ? nb4 : 0u);
-  const auto rI2 = make_rsrc(a.oidx[2], NM1 >= 3 ? nb4 : 0u);
-  const auto rX = make_rsrc(a.val, nb4);
+  // block records: 16 (NM1 + 1) dwords per 16 nonzeros; lane group g reads its
+  // 4 (NM1 + 1) dwords (one per lane, the last lanes repeat the last dword)
+  constexpr int GD = 4 * (NM1 + 1);
+  const auto rRec = make_rsrc(a.rec, (uint32_t)a.nnz_pad * 4u * (NM1 + 1));
+  const int qd = (lane & 15) < GD ? (lane & 15) : GD - 1;
+  const uint32_t goff = (uint32_t)(g * GD + qd) * 4u;
   const auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
   const auto rU1 = make_rsrc(a.U[1], NM1 >= 2 ? a.Ubytes[1] : 0u);
   const auto rU2 = make_rsrc(a.U[2], NM1 >= 3 ? a.Ubytes[2] : 0u);
-  const uint32_t goff = (uint32_t)g * 16u;
 
   lo = __builtin_amdgcn_readfirstlane(lo);
   hi = __builtin_amdgcn_readfirstlane(hi);
@@ -215,41 +229,46 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   const int32_t nblk = ((hi - 1) >> 4) - b0 + 1;
   const int32_t bmax = (a.nnz_pad >> 4) - 1;
 
-  // (bit-cast whole vectors: a bit-cast of one vector element reads element 0)
+  // one dword per lane; the 16 lanes of group g then share the group's record
+  // by row broadcasts (instead of every lane loading all of it)
   auto load_idx = [&](int32_t blk, PipeSet<NM1>& S) {
     blk = blk <= bmax ? blk : bmax;
-    const uint32_t so = (uint32_t)blk * 64u;
-    S.x = __builtin_bit_cast(f4, ld_i4(rX, goff, so));
-    S.j0 = ld_i4(rI0, goff, so);
-    if constexpr (NM1 >= 2) S.j1 = ld_i4(rI1, goff, so);
-    if constexpr (NM1 >= 3) S.j2 = ld_i4(rI2, goff, so);
+    S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
   // element offset j + k of a factor row: byte offset (j + k) * esize
   auto gather = [&](PipeSet<NM1>& S) {
+    const i4 j0 = group_quad<0>(S.rec);
+    i4 j1 = i4{0, 0, 0, 0}, j2 = i4{0, 0, 0, 0};
+    if constexpr (NM1 >= 2) j1 = group_quad<1>(S.rec);
+    if constexpr (NM1 >= 3) j2 = group_quad<2>(S.rec);
+    struct {
+      i4 j0, j1, j2;
+    } J{j0, j1, j2};
+    auto& SJ = J;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if constexpr (PREC == P_FP32) {
         if constexpr (NM1 == 1) {
           S.ga[t] = 1.f;
-          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU0, ((uint32_t)S.j0[t] << 2) + kc4, 0, 0);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU0, ((uint32_t)SJ.j0[t] << 2) + kc4, 0, 0);
         } else if constexpr (NM1 == 2) {
-          S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4);
-          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU1, ((uint32_t)S.j1[t] << 2) + kc4, 0, 0);
+          S.ga[t] = ld_f(rU0, ((uint32_t)SJ.j0[t] << 2) + ka4);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU1, ((uint32_t)SJ.j1[t] << 2) + kc4, 0, 0);
         } else {
-          S.ga[t] = ld_f(rU0, ((uint32_t)S.j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)S.j1[t] << 2) + kb4);
-          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU2, ((uint32_t)S.j2[t] << 2) + kc4, 0, 0);
+          S.ga[t] = ld_f(rU0, ((uint32_t)SJ.j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)SJ.j1[t] << 2) + kb4);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU2, ((uint32_t)SJ.j2[t] << 2) + kc4, 0, 0);
         }
       } else {  // 16-bit copies: offsets in 2-byte units (ka4 etc. hold 2 * k here)
         if constexpr (NM1 == 1) {
           S.ga[t] = 1.f;
-          S.gb[t] = ld_u16(rU0, ((uint32_t)S.j0[t] << 1) + kc4);
+          S.gb[t] = ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + kc4);
         } else if constexpr (NM1 == 2) {
-          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)S.j0[t] << 1) + ka4));
-          S.gb[t] = ld_u16(rU1, ((uint32_t)S.j1[t] << 1) + kc4);
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + ka4));
+          S.gb[t] = ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + kc4);
         } else {
-          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)S.j0[t] << 1) + ka4)) *
-                    f16bits_to_f32<PREC>(ld_u16(rU1, ((uint32_t)S.j1[t] << 1) + kb4));
-          S.gb[t] = ld_u16(rU2, ((uint32_t)S.j2[t] << 1) + kc4);
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + ka4)) *
+                    f16bits_to_f32<PREC>(ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + kb4));
+          S.gb[t] = ld_u16(rU2, ((uint32_t)SJ.j2[t] << 1) + kc4);
         }
       }
     }
@@ -275,10 +294,11 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   auto step = [&](int32_t blk, PipeSet<NM1>& C, PipeSet<NM1>& N2, const int ci) {
     float xa[4];
     uint32_t xb[4];
+    const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       // FP16: the scale goes first, so no intermediate can exceed the bound
-      const float xv = (PREC == P_FP16) ? C.x[t] * a.ascale : C.x[t];
+      const float xv = (PREC == P_FP16) ? xq[t] * a.ascale : xq[t];
       xa[t] = (NM1 == 1) ? xv : xv * C.ga[t];
       xb[t] = C.gb[t];
     }
@@ -327,7 +347,6 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   };
 
   PipeSet<NM1> S0, S1, S2;
-  S0.j1 = S0.j2 = S1.j1 = S1.j2 = S2.j1 = S2.j2 = i4{0, 0, 0, 0};
   load_idx(b0, S0);
   load_idx(b0 + 1, S1);
   load_idx(b0 + 2, S2);
@@ -358,19 +377,18 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
   const int32_t w = wg * a.RPW + rr;
   const bool multi = a.B > 1;
 
-  float* ybat = lds + wv * (16 * YS);
-  float* red = lds + a.B * a.RPW * 16 * YS + rr * (a.B * KN2 * 256);
-  int32_t* slot_base = reinterpret_cast<int32_t*>(lds + a.B * a.RPW * 16 * YS + (multi ? a.RPW * a.B * KN2 * 256 : 0));
+  const int SLOTS = stage_slots(a.B);
+  float* ybat = lds + wv * (SLOTS * YS);
+  float* red = lds + a.B * a.RPW * SLOTS * YS + rr * (a.B * KN2 * 256);
+  int32_t* slot_base =
+      reinterpret_cast<int32_t*>(lds + a.B * a.RPW * SLOTS * YS + (multi ? a.RPW * a.B * KN2 * 256 : 0));
   int32_t* slot_row = slot_base + rr * 32;
   int32_t* slot_kind = slot_row + 16;
   int32_t* wlds = slot_base + a.RPW * 32 + wv * 128;  // slice-table window of this wave
 
-  // stage-two operand of this block: gt[kb][t] = G_(n)^T[64 g + t][16 kb + q]
-  float gt[KN2][64];
-#pragma unroll
-  for (int kb = 0; kb < KN2; ++kb)
-#pragma unroll
-    for (int t = 0; t < 64; ++t) gt[kb][t] = a.gtop[(((size_t)b * KN2 + kb) * 64 + t) * 64 + lane];
+  // stage-two operand of this block, read from memory (L1/L2-resident) when
+  // needed: gtl[kb][t] = G_(n)^T[64 g + t][16 kb + q]
+  const float* gtl = a.gtop + ((size_t)b * KN2 * 64 + lane) * 64;
 
   uint32_t ka4, kb4, kc4;
   lane_offsets<NM1, PREC>(a, rb, cb, q, &ka4, &kb4, &kc4);
@@ -396,13 +414,17 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
     f4 d[KN2];
 #pragma unroll
     for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+    // rows q >= SLOTS of the product are not used: they re-read staged rows
+    const float* yrow = ybat + (q & (SLOTS - 1)) * YS + 64 * g;
+#pragma unroll 4
     for (int u = 0; u < 16; ++u) {
-      const f4 yv = *reinterpret_cast<const f4*>(ybat + q * YS + 64 * g + 4 * u);
+      const f4 yv = *reinterpret_cast<const f4*>(yrow + 4 * u);
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+      for (int kb = 0; kb < KN2; ++kb) {
+        const f4 gv = *reinterpret_cast<const f4*>(gtl + (size_t)kb * 4096 + 4 * u);
 #pragma unroll
-        for (int kb = 0; kb < KN2; ++kb) d[kb] = mfma4(yv[v], gt[kb][4 * u + v], d[kb]);
+        for (int v = 0; v < 4; ++v) d[kb] = mfma4(yv[v], gv[v], d[kb]);
+      }
     }
     if (multi) {
 #pragma unroll
@@ -453,7 +475,7 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
       slot_row[slot] = a.out_map ? a.out_map[row] : row;
       slot_kind[slot] = kind;
     }
-    if (++slot == 16) stage_two();
+    if (++slot == SLOTS) stage_two();
   });
   if (slot > 0) stage_two();
 }
@@ -523,14 +545,15 @@ __global__ void k_zero_rows(const int32_t* empty_row, int64_t row0, int64_t E, i
 }
 
 
-// gtop[b][kb][t][lane] = G_(n)^T[j'][kn] with j' = 64 (lane/16) + t inside block b
-// (j' = c*16 + r), kn = 16 kb + lane%16; zero in padding.
+// gtop[b][kb][lane][t] = G_(n)^T[j'][kn] with j' = 64 (lane/16) + t inside block b
+// (j' = c*16 + r), kn = 16 kb + lane%16; zero in padding. A lane's 64 values
+// are contiguous (16-byte loads in stage two).
 __device__ inline void prep_body(const PrepArgs& p, const int blk) {
   const int64_t total = (int64_t)p.B * p.KN2 * 4096;
   for (int64_t idx = blk * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)p.nblk * blockDim.x) {
-    const int lane = (int)(idx & 63);
-    const int t = (int)((idx >> 6) & 63);
+    const int t = (int)(idx & 63);
+    const int lane = (int)((idx >> 6) & 63);
     const int64_t rest = idx >> 12;
     const int kb = (int)(rest % p.KN2);
     const int b = (int)(rest / p.KN2);
@@ -559,6 +582,112 @@ __global__ void k_prep_gtop(PrepArgs p) { prep_body(p, blockIdx.x); }
 __global__ void k_prep_gtop_b(const PrepArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
   prep_body(d[r], blockIdx.x - first[r]);
+}
+
+// ---------------------------------------------------------------------------
+// Core pass, row-writing form: y_i of every slice of the core mode c is
+// written out (complete slices to their row of ybuf, partial rows of slices
+// split across ranges to ycarry), then G_(c) = U^(c)T Y_(c) by a small product
+// over the rows. Y_(c) has one row per nonempty slice of c (the mode with the
+// fewest), so it is small; the walk itself keeps no partial G and needs LDS
+// only for the slice-table window.
+// ---------------------------------------------------------------------------
+template <int NM1, int KN2, int PREC>
+__device__ inline void core_rows_body(const SegArgs& a, const int wg) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rr = wv / a.B;
+  const int b = wv - rr * a.B;
+  const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
+  const int g = lane >> 4, q = lane & 15;
+  const int32_t w = wg * a.RPW + rr;
+  int32_t* wlds = reinterpret_cast<int32_t*>(lds) + wv * 128;
+  const size_t row = (size_t)a.B * 256;  // floats per slice row
+  uint32_t ka4, kb4, kc4;
+  lane_offsets<NM1, PREC>(a, rb, cb, q, &ka4, &kb4, &kc4);
+  if (w >= a.W) return;  // only when B == 1 (no workgroup barriers)
+  const int32_t lo = range_lo(w, a.W, a.nnz);
+  const int32_t hi = range_lo(w + 1, a.W, a.nnz);
+  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
+  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  const bool head_clip = a.seg_off[s_first] < lo;
+  const bool tail_clip = a.seg_off[s_last + 1] > hi;
+  if (b == 0 && lane == 0) {
+    a.meta[w * 4 + 0] = s_first;
+    a.meta[w * 4 + 1] = s_last;
+    a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
+    a.meta[w * 4 + 3] = 0;
+  }
+  const int jo = b * 256 + q * 16 + 4 * g;  // this lane's 4 entries of the row (j' = c*16 + r)
+  walk_range<NM1, PREC>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t lrow, f4 y) {
+    float* own = a.A + (size_t)lrow * row;
+    float* dst = own;
+    if (s == s_first && head_clip) dst = a.carry + ((size_t)w * 2 + 0) * row;
+    else if (s == s_last && tail_clip) dst = a.carry + ((size_t)w * 2 + 1) * row;
+    *reinterpret_cast<f4*>(dst + jo) = y;
+    // a split slice's own row holds zeros (every range holding part of it
+    // writes the same zeros); its partials enter the product from ycarry
+    if (dst != own) *reinterpret_cast<f4*>(own + jo) = f4{0.f, 0.f, 0.f, 0.f};
+  });
+}
+
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_core_rows(SegArgs a) {
+  core_rows_body<NM1, KN2, PREC>(a, blockIdx.x);
+}
+
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) void k_core_rows_b(const SegArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  core_rows_body<NM1, KN2, PREC>(d[r], blockIdx.x - first[r]);
+}
+
+// One block per (chunk of kCoreChunk rows, y-tile b); thread t owns column j'
+// = t of tile b and every kc: fixed summation order over the chunk's rows.
+__device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
+  const int chunk = blk / p.B, b = blk - chunk * p.B;
+  const int t = threadIdx.x;
+  const size_t row = (size_t)p.B * 256;
+  float acc[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+  const int64_t v0 = (int64_t)chunk * kCoreChunk;
+  const int64_t nv = (int64_t)p.R + 2 * (int64_t)p.W;
+  const int64_t v1 = v0 + kCoreChunk < nv ? v0 + kCoreChunk : nv;
+  for (int64_t v = v0; v < v1; ++v) {
+    const float* src;
+    int32_t label;
+    if (v < p.R) {
+      src = p.ybuf + (size_t)v * row;
+      label = (int32_t)v;
+    } else {
+      const int64_t w = (v - p.R) >> 1;
+      const int kind = (int)((v - p.R) & 1);
+      const int32_t sf = p.ymeta[w * 4 + 0], sl = p.ymeta[w * 4 + 1], fl = p.ymeta[w * 4 + 2];
+      const bool head = fl & 1;
+      const bool tail = (fl & 2) && !(sf == sl && head);  // a slice clipped on both sides is a head
+      if (kind == 0 ? !head : !tail) continue;
+      src = p.ycarry + ((size_t)w * 2 + kind) * row;
+      label = p.seg_row[kind == 0 ? sf : sl];
+    }
+    const float y = src[b * 256 + t];
+    const float* u = p.Uc + (size_t)__builtin_amdgcn_readfirstlane(label) * p.Kc;
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if (k < p.Kc) acc[k] += u[k] * y;
+  }
+  float* out = p.gpart + ((size_t)chunk * p.B + b) * p.KC * 256;
+#pragma unroll
+  for (int k = 0; k < 32; ++k)
+    if (k < p.KC) out[(size_t)k * 256 + t] = acc[k];
+}
+
+__global__ __launch_bounds__(256) void k_core_gemm(CoreGemmArgs p) { core_gemm_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_core_gemm_b(const CoreGemmArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  core_gemm_body(d[r], blockIdx.x - first[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -721,7 +850,6 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   const ModeData& md = p->md[mode];
   const int es = op.prec == OP_FP32 ? 4 : 2;
   for (int c = 0; c < 3; ++c) {
-    a.oidx[c] = c < g.nm1 ? md.oidx[c] : md.oidx[0];
     const int m = c < g.nm1 ? g.om[c] : g.om[0];
     a.U[c] = op.prec == OP_FP32 ? (const void*)op.U32[m] : (const void*)op.U16[m];
     a.Ubytes[c] = (uint32_t)(p->dims[m] * p->K[m] * es);
@@ -729,7 +857,7 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   a.ascale = 1.f;
   a.yscale = 1.f;
   if (op.prec == OP_FP16 && !fp16_scales(p, g.nm1, &a.ascale, &a.yscale)) return false;
-  a.val = md.val;
+  a.rec = md.rec;
   a.seg_off = md.seg_off;
   a.seg_row = md.seg_row;
   a.R = (int32_t)md.R;
@@ -749,12 +877,15 @@ struct SegKernels {
   const void* ttm_b;
   const void* core;
   const void* core_b;
+  const void* rows;
+  const void* rows_b;
 };
 
 template <int NM1, int KN2, int PREC>
 SegKernels seg_kernels_t() {
-  return SegKernels{(const void*)k_ttm<NM1, KN2, PREC>, (const void*)k_ttm_b<NM1, KN2, PREC>,
-                    (const void*)k_core<NM1, KN2, PREC>, (const void*)k_core_b<NM1, KN2, PREC>};
+  return SegKernels{(const void*)k_ttm<NM1, KN2, PREC>,       (const void*)k_ttm_b<NM1, KN2, PREC>,
+                    (const void*)k_core<NM1, KN2, PREC>,      (const void*)k_core_b<NM1, KN2, PREC>,
+                    (const void*)k_core_rows<NM1, KN2, PREC>, (const void*)k_core_rows_b<NM1, KN2, PREC>};
 }
 
 template <int PREC>
@@ -771,6 +902,7 @@ bool seg_kernels_p(int nm1, int kn2, SegKernels* k) {
 }
 
 bool seg_kernels(int key, SegKernels* k) {
+  key %= 1000;
   const int nm1 = key / 100, kn2 = (key / 10) % 10, prec = key % 10;
   if (prec == P_FP32) return seg_kernels_p<P_FP32>(nm1, kn2, k);
   if (prec == P_BF16) return seg_kernels_p<P_BF16>(nm1, kn2, k);
@@ -877,7 +1009,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   a.meta = p->sc.meta;
   a.out_map = out_map;
   job->threads = 64 * g.B * a.RPW;
-  job->shmem = (size_t)(g.B * a.RPW * 16 * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 +
+  job->shmem = (size_t)(g.B * a.RPW * stage_slots(g.B) * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 +
                         g.B * a.RPW * 128) * 4;
   job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
   // split slices
@@ -906,6 +1038,59 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
   job->key = seg_key(g.nm1, KN2, op.prec);
   SegArgs& a = job->seg;
   if (!fill_common(a, p, mode, g, op)) return HOQRI_ERR_UNSUPPORTED;
+  if (p->core_rows) {
+    job->key += 1000;
+    int64_t W = p->core_w;
+    if (W > p->nnz) W = p->nnz;
+    a.W = (int32_t)W;
+    a.RPW = g.B == 1 ? 4 : 1;
+    a.A = p->sc.ybuf;
+    a.carry = p->sc.ycarry;
+    a.meta = p->sc.ymeta;
+    job->threads = 64 * g.B * a.RPW;
+    job->shmem = (size_t)g.B * a.RPW * 128 * 4;
+    job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
+    CoreGemmArgs& m = job->gemm;
+    m.ybuf = p->sc.ybuf;
+    m.ycarry = p->sc.ycarry;
+    m.ymeta = p->sc.ymeta;
+    m.seg_row = p->md[mode].seg_row;
+    m.Uc = op.U32[mode];
+    m.Kc = p->K[mode];
+    m.KC = 16 * KN2;
+    m.R = (int32_t)p->md[mode].R;
+    m.W = a.W;
+    m.B = g.B;
+    m.gpart = p->sc.gpart;
+    const int64_t chunks = ((int64_t)m.R + 2 * (int64_t)m.W + kCoreChunk - 1) / kCoreChunk;
+    job->gemm_blocks = (int)(chunks * g.B);
+    CoreRedArgs& r = job->red;
+    r.gpart = p->sc.gpart;
+    r.groups = (int32_t)chunks;
+    r.B = g.B;
+    r.CB = g.CB;
+    r.KN2 = KN2;
+    r.krow = g.krow;
+    r.kcol = g.kcol;
+    r.Kc = p->K[mode];
+    r.mode = mode;
+    r.nm1 = g.nm1;
+    for (int c = 0; c < 3; ++c) {
+      r.om[c] = c < g.nm1 ? g.om[c] : 0;
+      r.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
+    }
+    g_strides(p, r.gstride);
+    r.G = G;
+    r.fpart = p->sc.fpart;
+    const int total = g.B * 16 * KN2 * 256;
+    job->red_blocks = (total + 63) / 64;
+    job->sum.part = p->sc.fpart;
+    job->sum.n = job->red_blocks;
+    job->sum.out = f_out ? f_out : p->sc.f_dev;
+    SegKernels k;
+    if (!seg_kernels(job->key, &k)) return HOQRI_ERR_UNSUPPORTED;
+    return HOQRI_OK;
+  }
   // each wave keeps its partial (16*KN2 x 256 floats) in LDS: at most 160 KB per workgroup
   const int per_wave = 16 * KN2 * 256 * 4 + 128 * 4;
   int rpw = (160 * 1024) / (per_wave * g.B);
@@ -990,10 +1175,12 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
   seg_kernels(job.key, &k);
   {
     TimerScope ts(p, HOQRI_KERNEL_CORE, s);
-    HOQRI_HIP_TRY(set_shmem(k.core, job.shmem));
+    const void* kern = job.key >= 1000 ? k.rows : k.core;
+    HOQRI_HIP_TRY(set_shmem(kern, job.shmem));
     void* args[] = {(void*)&job.seg};
-    HOQRI_HIP_TRY(hipLaunchKernel(k.core, dim3(job.seg_blocks), dim3(job.threads), args, job.shmem, s));
+    HOQRI_HIP_TRY(hipLaunchKernel(kern, dim3(job.seg_blocks), dim3(job.threads), args, job.shmem, s));
   }
+  if (job.key >= 1000) hipLaunchKernelGGL(k_core_gemm, dim3(job.gemm_blocks), dim3(256), 0, s, job.gemm);
   hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(256), 0, s, job.red);
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
   HOQRI_HIP_TRY(hipGetLastError());
@@ -1027,20 +1214,25 @@ bool stage_ttm_group(const TtmJob* const* jobs, int n, Staging& st, TtmGroup* g)
 bool stage_core_group(const CoreJob* const* jobs, int n, Staging& st, CoreGroup* g) {
   if (n < 1 || n > 1024) return false;
   std::vector<SegArgs> seg(n);
+  std::vector<CoreGemmArgs> gemm(n);
   std::vector<CoreRedArgs> red(n);
   std::vector<SumArgs> sum(n);
-  std::vector<int32_t> nb_seg(n), nb_red(n), ones(n);
+  std::vector<int32_t> nb_seg(n), nb_gemm(n), nb_red(n), ones(n);
   for (int i = 0; i < n; ++i) {
     seg[i] = jobs[i]->seg;
+    gemm[i] = jobs[i]->gemm;
     red[i] = jobs[i]->red;
     sum[i] = jobs[i]->sum;
     nb_seg[i] = jobs[i]->seg_blocks;
+    nb_gemm[i] = jobs[i]->gemm_blocks;
     nb_red[i] = jobs[i]->red_blocks;
     ones[i] = 1;
   }
   g->key = jobs[0]->key;
   g->threads = jobs[0]->threads;
   g->shmem = jobs[0]->shmem;
+  g->gemm = BatchTable{nullptr, nullptr, 0, 0};
+  if (g->key >= 1000 && !stage_table(st, gemm.data(), nb_gemm.data(), n, &g->gemm)) return false;
   return stage_table(st, seg.data(), nb_seg.data(), n, &g->seg) &&
          stage_table(st, red.data(), nb_red.data(), n, &g->red) && stage_table(st, sum.data(), ones.data(), n, &g->sum);
 }
@@ -1065,12 +1257,16 @@ hoqri_status launch_ttm_group(const TtmGroup& g, hipStream_t s) {
 hoqri_status launch_core_group(const CoreGroup& g, hipStream_t s) {
   SegKernels k;
   if (!seg_kernels(g.key, &k)) return HOQRI_ERR_UNSUPPORTED;
-  HOQRI_HIP_TRY(set_shmem(k.core_b, g.shmem));
+  const void* kern = g.key >= 1000 ? k.rows_b : k.core_b;
+  HOQRI_HIP_TRY(set_shmem(kern, g.shmem));
   const SegArgs* d = (const SegArgs*)g.seg.descs;
   const int32_t* first = g.seg.first;
   int count = g.seg.count;
   void* args[] = {(void*)&d, (void*)&first, (void*)&count};
-  HOQRI_HIP_TRY(hipLaunchKernel(k.core_b, dim3(g.seg.blocks), dim3(g.threads), args, g.shmem, s));
+  HOQRI_HIP_TRY(hipLaunchKernel(kern, dim3(g.seg.blocks), dim3(g.threads), args, g.shmem, s));
+  if (g.key >= 1000)
+    hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(256), 0, s, (const CoreGemmArgs*)g.gemm.descs,
+                       g.gemm.first, g.gemm.count);
   hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(256), 0, s, (const CoreRedArgs*)g.red.descs,
                      g.red.first, g.red.count);
   hipLaunchKernelGGL(k_sum_f_b, dim3(g.sum.blocks), dim3(256), 0, s, (const SumArgs*)g.sum.descs, g.sum.first,
