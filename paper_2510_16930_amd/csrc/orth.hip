@@ -1,13 +1,18 @@
 // QR step of HOQRI (Alg. 2): an orthonormal basis of A (I x K, K <= 32) by
-// CholeskyQR2 with float64 Gram matrices and Cholesky factors:
-//   W1 = A^T A, R1 = chol(W1), Q1 = A R1^-1 (never stored), W2 = Q1^T Q1,
-//   R2 = chol(W2), U = A (R2 R1)^-1 = A M with M = R1^-1 R2^-1.
-// Both Cholesky factors have a positive diagonal, so U is the thin QR factor
-// with diag(R) > 0 (the basis the paper leaves free, made unique).
+// Cholesky QR in float64, refined once (the second step of CholeskyQR2):
+//   W1 = A^T A, R1 = chol(W1), W2 = R1^-T W1 R1^-1, R2 = chol(W2),
+//   U = A (R2 R1)^-1 = A M with M = R1^-1 R2^-1.
+// W1 is formed from the float32 A with float64 products on the float64
+// matrix cores (v_mfma_f64_16x16x4_f64), so its error is ~1e-16 relative;
+// the second factorisation then removes the rounding of the first one, which
+// is what forming Q1 = A R1^-1 explicitly and taking its Gram would do, up
+// to float64 rounding (Q1 is never formed). Both Cholesky factors have a
+// positive diagonal, so U is the thin QR factor with diag(R) > 0 (the basis
+// the paper leaves free, made unique).
 // A Cholesky pivot <= 1e-13 * trace(W) (or not finite) flags breakdown: A is
 // numerically rank deficient; U is then left untouched.
 //
-// Memory traffic: two reads of A for the Grams and one read + one write for
+// Memory traffic: one read of A for the Gram and one read + one write for
 // the final product; the K x K work runs in a single workgroup.
 #include "passes.h"
 
@@ -27,69 +32,58 @@ int gram_blocks(int64_t rows) {
   return (int)nb;
 }
 
-// Partial Gram of rows [r0, r1): part[e * nb + block] for entry e = p*K + q.
-// With M != null the rows are first multiplied by the upper-triangular M
-// (float64), i.e. the Gram of A M.
-__device__ inline int batch_item(const int32_t* first, int count, int b) {
-  int lo = 0, hi = count;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= b) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
+// Partial Gram of the rows [r0, r1) of block blk, on the float64 matrix cores:
+// each wave takes 4 rows at a time (lane group g: row 4s + g, lane q: columns
+// 16 pb + q), W tile (pb, qb) += A_rows^T A_rows; the 4 waves' tiles are added
+// in order. part[e * nb + blk] for entry e = p*K + q.
 __device__ inline void gram_body(const GramArgs& g, const int blk) {
-  __shared__ double rowsd[kChunk][kMaxRank + 1];
-  __shared__ double Ms[kMaxRank][kMaxRank];
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[kT / 64][kMaxRank * kMaxRank];
   const float* A = g.A;
   const int64_t rows = g.rows;
   const int K = g.K;
-  const double* M = g.M;
-  double* part = g.part;
   const int nb = g.nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane & 15, gg = lane >> 4;
   const int64_t per = (rows + nb - 1) / nb;
   const int64_t r0 = blk * per;
   int64_t r1 = r0 + per;
   if (r1 > rows) r1 = rows;
-  if (M)
-    for (int t = threadIdx.x; t < K * K; t += kT) Ms[t / K][t % K] = M[t];
-  const int KK = K * K;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  __syncthreads();
-  for (int64_t base = r0; base < r1; base += kChunk) {
-    const int nr = (int)((r1 - base) < kChunk ? (r1 - base) : kChunk);
-    // stage rows (coalesced), optionally times M
-    for (int t = threadIdx.x; t < kChunk * K; t += kT) {
-      const int r = t / K, c = t - (t / K) * K;
-      double v = 0.0;
-      if (r < nr) {
-        if (M) {
-          const float* ar = A + (base + r) * K;
-          for (int k = 0; k <= c; ++k) v += (double)ar[k] * Ms[k][c];
-        } else {
-          v = (double)A[(base + r) * K + c];
-        }
-      }
-      rowsd[r][c] = v;
-    }
-    __syncthreads();
+  d4 D[2][2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int e = threadIdx.x + j * kT;
-      if (e < KK) {
-        const int p = e / K, q = e - (e / K) * K;
-        double s = 0.0;
-        for (int r = 0; r < nr; ++r) s += rowsd[r][p] * rowsd[r][q];
-        acc[j] += s;
-      }
+  for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) D[pb][qb] = d4{0.0, 0.0, 0.0, 0.0};
+  const bool two = K > 16;
+#pragma unroll 4
+  for (int64_t base = r0 + 4 * wv; base < r1; base += 4 * (kT / 64)) {
+    const int64_t row = base + gg;
+    const bool ok = row < r1;
+    const double a0 = (ok && q < K) ? (double)A[row * K + q] : 0.0;
+    D[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, D[0][0], 0, 0, 0);
+    if (two) {
+      const double a1 = (ok && 16 + q < K) ? (double)A[row * K + 16 + q] : 0.0;
+      D[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, D[0][1], 0, 0, 0);
+      D[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, D[1][0], 0, 0, 0);
+      D[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, D[1][1], 0, 0, 0);
     }
-    __syncthreads();
   }
+  // float64 16x16 result layout: tile (pb, qb) holds entry (16 pb + 4 v + gg,
+  // 16 qb + q) in D[pb][qb][v]
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int e = threadIdx.x + j * kT;
-    if (e < KK) part[(size_t)e * nb + blk] = acc[j];
+  for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pr = 16 * pb + 4 * v + gg, pc = 16 * qb + q;
+        if (pr < K && pc < K) red[wv][pr * K + pc] = D[pb][qb][v];
+      }
+  __syncthreads();
+  for (int e = threadIdx.x; e < K * K; e += kT) {
+    double t = red[0][e];
+    for (int w = 1; w < kT / 64; ++w) t += red[w][e];
+    g.part[(size_t)e * nb + blk] = t;
   }
 }
 
@@ -124,44 +118,15 @@ __global__ __launch_bounds__(kT) void k_gram_reduce_b(const GRedArgs* d, const i
   gred_body(d[r], blockIdx.x - first[r]);
 }
 
-// Cholesky W = R^T R (R upper, positive diagonal) and Rinv = R^-1, in one
-// workgroup. First pass (Mprev null): Mout = Rinv, Rout = R, *flag = breakdown.
-// Second pass: Mout = Mprev * Rinv, Rout = R * Rprev, *flag |= breakdown, and
-// on breakdown either *skipped += 1 (when a counter is given: the factor is
-// left as it was) or *status = HOQRI_ERR_BREAKDOWN; without breakdown *status
-// = 0 unless `sticky` (then an earlier breakdown recorded in *status is kept).
-__device__ inline void chol_body(const CholArgs& c) {
-  const double* W = c.W;
-  const int K = c.K;
-  const double* Mprev = c.Mprev;
-  const double* Rprev = c.Rprev;
-  double* Mout = c.Mout;
-  double* Rout = c.Rout;
-  int32_t* flag = c.flag;
-  int32_t* status = c.status;
-  const int sticky = c.sticky;
-  int32_t* skipped = c.skipped;
-  __shared__ double L[kMaxRank][kMaxRank + 1];   // holds R (upper)
-  __shared__ double Ri[kMaxRank][kMaxRank + 1];  // R^-1
-  __shared__ double tr;
-  __shared__ int bad;
+// Upper Cholesky factor of the symmetric L (in place, upper triangle) and its
+// inverse Ri, by all threads of the workgroup; *bad is set when a pivot is
+// <= 1e-13 * tr or not finite.
+__device__ inline void chol_inv(double (*L)[kMaxRank + 1], double (*Ri)[kMaxRank + 1], int K, double tr, int* bad) {
   const int t = threadIdx.x;
-  for (int e = t; e < K * K; e += kT) {
-    L[e / K][e % K] = W[e];
-    Ri[e / K][e % K] = 0.0;
-  }
-  if (t == 0) {
-    double s = 0.0;
-    for (int k = 0; k < K; ++k) s += W[k * K + k];
-    tr = s;
-    bad = (Mprev && *flag != 0) ? 1 : 0;
-  }
-  __syncthreads();
-  // right-looking Cholesky on the upper triangle: row k of R
   for (int k = 0; k < K; ++k) {
     if (t == 0) {
       const double piv = L[k][k];
-      if (!(piv > kBreakRel * tr) || !(piv < 1e300)) bad = 1;
+      if (!(piv > kBreakRel * tr) || !(piv < 1e300)) *bad = 1;
       L[k][k] = sqrt(piv > 0.0 ? piv : 1.0);
     }
     __syncthreads();
@@ -174,7 +139,8 @@ __device__ inline void chol_body(const CholArgs& c) {
     }
     __syncthreads();
   }
-  // inverse of the upper-triangular R, one column per thread
+  for (int e = t; e < K * K; e += kT) Ri[e / K][e % K] = 0.0;
+  __syncthreads();
   for (int j = t; j < K; j += kT) {
     for (int i = j; i >= 0; --i) {
       double s = (i == j) ? 1.0 : 0.0;
@@ -183,31 +149,79 @@ __device__ inline void chol_body(const CholArgs& c) {
     }
   }
   __syncthreads();
+}
+
+// W1 -> R1 = chol(W1), W2 = R1^-T W1 R1^-1, R2 = chol(W2); Mout = R1^-1 R2^-1,
+// Rout = R2 R1 (optional). On breakdown either *skipped += 1 (when a counter
+// is given: the factor is left as it was) or *status = HOQRI_ERR_BREAKDOWN;
+// without breakdown *status = 0 unless `sticky` (then an earlier breakdown
+// recorded in *status is kept). *flag = breakdown (read by the apply kernel).
+__device__ inline void chol_body(const CholArgs& c) {
+  __shared__ double L[kMaxRank][kMaxRank + 1];
+  __shared__ double Ri[kMaxRank][kMaxRank + 1];
+  __shared__ double W[kMaxRank][kMaxRank + 1];
+  __shared__ double T[kMaxRank][kMaxRank + 1];
+  __shared__ double R1[kMaxRank][kMaxRank + 1];
+  __shared__ double tr;
+  __shared__ int bad;
+  const int K = c.K;
+  const int t = threadIdx.x;
+  for (int e = t; e < K * K; e += kT) {
+    L[e / K][e % K] = c.W[e];
+    W[e / K][e % K] = c.W[e];
+  }
+  if (t == 0) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += c.W[k * K + k];
+    tr = s;
+    bad = 0;
+  }
+  __syncthreads();
+  chol_inv(L, Ri, K, tr, &bad);  // L: R1, Ri: R1^-1
+  // T = W1 R1^-1, then W2 = R1^-T T (kept in L after saving R1)
+  for (int e = t; e < K * K; e += kT) {
+    const int i = e / K, j = e % K;
+    double s = 0.0;
+    for (int k = 0; k <= j; ++k) s += W[i][k] * Ri[k][j];
+    T[i][j] = s;
+    R1[i][j] = (j >= i) ? L[i][j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < K * K; e += kT) {
+    const int i = e / K, j = e % K;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) s += Ri[k][i] * T[k][j];
+    W[i][j] = s;  // W2
+  }
+  __syncthreads();
+  for (int e = t; e < K * K; e += kT) {
+    L[e / K][e % K] = W[e / K][e % K];
+    T[e / K][e % K] = Ri[e / K][e % K];  // keep R1^-1
+  }
+  if (t == 0) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += W[k][k];
+    tr = s;
+  }
+  __syncthreads();
+  chol_inv(L, Ri, K, tr, &bad);  // L: R2, Ri: R2^-1
   for (int e = t; e < K * K; e += kT) {
     const int i = e / K, j = e % K;
     double m = 0.0, r = 0.0;
-    if (Mprev) {
-      // (Mprev * Rinv)[i][j], both upper triangular
-      for (int k = i; k <= j; ++k) m += Mprev[i * K + k] * Ri[k][j];
-      if (Rout && Rprev)
-        for (int k = i; k <= j; ++k) r += L[i][k] * Rprev[k * K + j];
-    } else {
-      m = (j >= i) ? Ri[i][j] : 0.0;
-      r = (j >= i) ? L[i][j] : 0.0;
+    if (j >= i) {
+      for (int k = i; k <= j; ++k) m += T[i][k] * Ri[k][j];  // R1^-1 R2^-1
+      for (int k = i; k <= j; ++k) r += L[i][k] * R1[k][j];  // R2 R1
     }
-    if (j < i) m = r = 0.0;
-    Mout[e] = m;
-    if (Rout) Rout[e] = r;
+    c.Mout[e] = m;
+    if (c.Rout) c.Rout[e] = r;
   }
   if (t == 0) {
-    *flag = bad;
-    if (Mprev) {
-      if (bad) {
-        if (skipped) *skipped += 1;  // the caller keeps its previous factor
-        else *status = HOQRI_ERR_BREAKDOWN;
-      } else if (!sticky) {
-        *status = 0;
-      }
+    *c.flag = bad;
+    if (bad) {
+      if (c.skipped) *c.skipped += 1;  // the caller keeps its previous factor
+      else *c.status = HOQRI_ERR_BREAKDOWN;
+    } else if (!c.sticky) {
+      *c.status = 0;
     }
   }
 }
@@ -319,10 +333,7 @@ hoqri_status prepare_orth(int64_t rows, int32_t K, const float* A, float* U, dou
   *job = OrthJob{};
   job->g1 = GramArgs{A, rows, K, nullptr, o.part, nb};
   job->r1 = GRedArgs{o.part, nb, o.W};
-  job->c1 = CholArgs{o.W, K, nullptr, nullptr, o.M1, o.R1, o.flag, status, (int32_t)sticky, skipped};
-  job->g2 = GramArgs{A, rows, K, o.M1, o.part, nb};
-  job->r2 = GRedArgs{o.part, nb, o.W};
-  job->c2 = CholArgs{o.W, K, o.M1, o.R1, o.M, R ? R : o.R, o.flag, status, (int32_t)sticky, skipped};
+  job->c = CholArgs{o.W, K, nullptr, nullptr, o.M, R ? R : o.R, o.flag, status, (int32_t)sticky, skipped};
   int64_t ab = (rows + 63) / 64;
   if (ab > 4096) ab = 4096;
   job->ap = ApplyArgs{A, rows, K, o.M, U, o.flag, (int32_t)ab, zero_to > rows ? zero_to : rows};
@@ -338,10 +349,7 @@ hoqri_status launch_orth(int64_t rows, int32_t K, const float* A, float* U, doub
   HOQRI_TRY(prepare_orth(rows, K, A, U, R, status, ws, ws_bytes, sticky, &j, skipped, zero_to));
   hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g1);
   hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r1);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c1);
-  hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g2);
-  hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r2);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c2);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c);
   hipLaunchKernelGGL(k_apply, dim3(j.apply_blocks), dim3(kT), 0, s, j.ap);
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
@@ -349,18 +357,15 @@ hoqri_status launch_orth(int64_t rows, int32_t K, const float* A, float* U, doub
 
 bool stage_orth_group(const OrthJob* const* jobs, int n, Staging& st, OrthGroup* g) {
   if (n < 1 || n > 1024) return false;
-  std::vector<GramArgs> g1(n), g2(n);
-  std::vector<GRedArgs> r1(n), r2(n);
-  std::vector<CholArgs> c1(n), c2(n);
+  std::vector<GramArgs> g1(n);
+  std::vector<GRedArgs> r1(n);
+  std::vector<CholArgs> c(n);
   std::vector<ApplyArgs> ap(n);
   std::vector<int32_t> nb_g(n), nb_r(n), ones(n), nb_a(n);
   for (int i = 0; i < n; ++i) {
     g1[i] = jobs[i]->g1;
-    g2[i] = jobs[i]->g2;
     r1[i] = jobs[i]->r1;
-    r2[i] = jobs[i]->r2;
-    c1[i] = jobs[i]->c1;
-    c2[i] = jobs[i]->c2;
+    c[i] = jobs[i]->c;
     ap[i] = jobs[i]->ap;
     nb_g[i] = jobs[i]->gram_blocks;
     nb_r[i] = jobs[i]->red_blocks;
@@ -368,20 +373,14 @@ bool stage_orth_group(const OrthJob* const* jobs, int n, Staging& st, OrthGroup*
     nb_a[i] = jobs[i]->apply_blocks;
   }
   return stage_table(st, g1.data(), nb_g.data(), n, &g->g1) && stage_table(st, r1.data(), nb_r.data(), n, &g->r1) &&
-         stage_table(st, c1.data(), ones.data(), n, &g->c1) && stage_table(st, g2.data(), nb_g.data(), n, &g->g2) &&
-         stage_table(st, r2.data(), nb_r.data(), n, &g->r2) && stage_table(st, c2.data(), ones.data(), n, &g->c2) &&
-         stage_table(st, ap.data(), nb_a.data(), n, &g->ap);
+         stage_table(st, c.data(), ones.data(), n, &g->c) && stage_table(st, ap.data(), nb_a.data(), n, &g->ap);
 }
 
 hoqri_status launch_orth_group(const OrthGroup& g, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_b, dim3(g.g1.blocks), dim3(kT), 0, s, (const GramArgs*)g.g1.descs, g.g1.first, g.g1.count);
   hipLaunchKernelGGL(k_gram_reduce_b, dim3(g.r1.blocks), dim3(kT), 0, s, (const GRedArgs*)g.r1.descs, g.r1.first,
                      g.r1.count);
-  hipLaunchKernelGGL(k_chol_b, dim3(g.c1.blocks), dim3(kT), 0, s, (const CholArgs*)g.c1.descs, g.c1.first, g.c1.count);
-  hipLaunchKernelGGL(k_gram_b, dim3(g.g2.blocks), dim3(kT), 0, s, (const GramArgs*)g.g2.descs, g.g2.first, g.g2.count);
-  hipLaunchKernelGGL(k_gram_reduce_b, dim3(g.r2.blocks), dim3(kT), 0, s, (const GRedArgs*)g.r2.descs, g.r2.first,
-                     g.r2.count);
-  hipLaunchKernelGGL(k_chol_b, dim3(g.c2.blocks), dim3(kT), 0, s, (const CholArgs*)g.c2.descs, g.c2.first, g.c2.count);
+  hipLaunchKernelGGL(k_chol_b, dim3(g.c.blocks), dim3(kT), 0, s, (const CholArgs*)g.c.descs, g.c.first, g.c.count);
   hipLaunchKernelGGL(k_apply_b, dim3(g.ap.blocks), dim3(kT), 0, s, (const ApplyArgs*)g.ap.descs, g.ap.first,
                      g.ap.count);
   HOQRI_HIP_TRY(hipGetLastError());

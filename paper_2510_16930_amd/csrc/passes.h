@@ -94,6 +94,16 @@ struct SumArgs {
   double* out;
 };
 
+// Item of a batched launch that owns block b: first[r] <= b < first[r+1].
+__device__ inline int batch_item(const int32_t* first, int count, int b) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Kernel instance of a segment pass: tensor order, rank blocks, precision.
 inline int seg_key(int nm1, int kn2, int prec) { return nm1 * 100 + kn2 * 10 + prec; }
 
@@ -142,8 +152,8 @@ struct GRedArgs {
 struct CholArgs {
   const double* W;
   int32_t K;
-  const double* Mprev;
-  const double* Rprev;
+  const double* unused0;
+  const double* unused1;
   double* Mout;
   double* Rout;
   int32_t* flag;
@@ -162,9 +172,9 @@ struct ApplyArgs {
   int64_t zero_to;  // rows [rows, zero_to) of U are zeroed with the update
 };
 struct OrthJob {
-  GramArgs g1, g2;
-  GRedArgs r1, r2;
-  CholArgs c1, c2;
+  GramArgs g1;
+  GRedArgs r1;
+  CholArgs c;
   ApplyArgs ap;
   int gram_blocks, red_blocks, apply_blocks;
 };
@@ -239,7 +249,7 @@ struct CoreGroup {
   BatchTable seg, gemm, red, sum;
 };
 struct OrthGroup {
-  BatchTable g1, r1, c1, g2, r2, c2, ap;
+  BatchTable g1, r1, c, ap;
 };
 
 // Jobs of one group must share key, threads and shmem.

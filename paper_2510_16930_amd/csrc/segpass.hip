@@ -71,16 +71,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Item of a batched launch that owns block b: first[r] <= b < first[r+1].
-__device__ inline int batch_item(const int32_t* first, int count, int b) {
-  int lo = 0, hi = count;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (first[mid] <= b) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 __device__ inline f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
