@@ -119,7 +119,7 @@ struct Layout {
   int64_t ybuf_rows;     // rows of the slice-row buffer (>= nonempty slices of the core mode)
   int32_t core_w;        // work ranges of the row-writing core pass
 };
-constexpr int kCoreChunk = 256;  // rows per partial of the core product U^(c)T Y
+constexpr int kCoreChunk = 64;  // rows per partial of the core product U^(c)T Y
 
 hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L);
 hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz);

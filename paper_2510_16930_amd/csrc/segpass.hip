@@ -504,8 +504,21 @@ __device__ inline void fix_body(const FixArgs& f, const int32_t w) {
   const int32_t w1 = (int32_t)(((e_last + 1) * (int64_t)W - 1) / nnz);
   const int kn = threadIdx.x & 31, grp = threadIdx.x >> 5;
   double acc = 0.0;
-  if (kn < Kn)
-    for (int32_t w2 = w + 1 + grp; w2 <= w1; w2 += 8) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + kn];
+  if (kn < Kn) {
+    // group grp adds ranges w+1+grp, w+9+grp, ... in order, four loads in flight
+    int32_t w2 = w + 1 + grp;
+    for (; w2 + 24 <= w1; w2 += 32) {
+      const float c0 = carry[((size_t)w2 * 2 + 0) * 32 + kn];
+      const float c1 = carry[((size_t)(w2 + 8) * 2 + 0) * 32 + kn];
+      const float c2 = carry[((size_t)(w2 + 16) * 2 + 0) * 32 + kn];
+      const float c3 = carry[((size_t)(w2 + 24) * 2 + 0) * 32 + kn];
+      acc += (double)c0;
+      acc += (double)c1;
+      acc += (double)c2;
+      acc += (double)c3;
+    }
+    for (; w2 <= w1; w2 += 8) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + kn];
+  }
   part[grp][kn] = acc;
   __syncthreads();
   if (threadIdx.x < 32 && kn < Kn) {
@@ -645,27 +658,40 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   const int64_t v0 = (int64_t)chunk * kCoreChunk;
   const int64_t nv = (int64_t)p.R + 2 * (int64_t)p.W;
   const int64_t v1 = v0 + kCoreChunk < nv ? v0 + kCoreChunk : nv;
-  for (int64_t v = v0; v < v1; ++v) {
-    const float* src;
-    int32_t label;
+  // row v of the product: its source row and the label of its slice (-1: none)
+  auto source = [&](int64_t v, const float** src) -> int32_t {
+    if (v >= v1) return -1;
     if (v < p.R) {
-      src = p.ybuf + (size_t)v * row;
-      label = (int32_t)v;
-    } else {
-      const int64_t w = (v - p.R) >> 1;
-      const int kind = (int)((v - p.R) & 1);
-      const int32_t sf = p.ymeta[w * 4 + 0], sl = p.ymeta[w * 4 + 1], fl = p.ymeta[w * 4 + 2];
-      const bool head = fl & 1;
-      const bool tail = (fl & 2) && !(sf == sl && head);  // a slice clipped on both sides is a head
-      if (kind == 0 ? !head : !tail) continue;
-      src = p.ycarry + ((size_t)w * 2 + kind) * row;
-      label = p.seg_row[kind == 0 ? sf : sl];
+      *src = p.ybuf + (size_t)v * row;
+      return (int32_t)v;
     }
-    const float y = src[b * 256 + t];
-    const float* u = p.Uc + (size_t)__builtin_amdgcn_readfirstlane(label) * p.Kc;
+    const int64_t w = (v - p.R) >> 1;
+    const int kind = (int)((v - p.R) & 1);
+    const int32_t sf = p.ymeta[w * 4 + 0], sl = p.ymeta[w * 4 + 1], fl = p.ymeta[w * 4 + 2];
+    const bool head = fl & 1;
+    const bool tail = (fl & 2) && !(sf == sl && head);  // a slice clipped on both sides is a head
+    if (kind == 0 ? !head : !tail) return -1;
+    *src = p.ycarry + ((size_t)w * 2 + kind) * row;
+    return p.seg_row[kind == 0 ? sf : sl];
+  };
+  for (int64_t v = v0; v < v1; v += 4) {
+    // four rows at a time (loads in flight together), added in row order
+    const float* src[4] = {p.ybuf, p.ybuf, p.ybuf, p.ybuf};
+    int32_t lab[4];
+    float y[4];
 #pragma unroll
-    for (int k = 0; k < 32; ++k)
-      if (k < p.Kc) acc[k] += u[k] * y;
+    for (int i = 0; i < 4; ++i) {
+      lab[i] = __builtin_amdgcn_readfirstlane(source(v + i, &src[i]));
+      y[i] = lab[i] >= 0 ? src[i][b * 256 + t] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (lab[i] < 0) continue;
+      const float* u = p.Uc + (size_t)lab[i] * p.Kc;
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        if (k < p.Kc) acc[k] += u[k] * y[i];
+    }
   }
   float* out = p.gpart + ((size_t)chunk * p.B + b) * p.KC * 256;
 #pragma unroll
