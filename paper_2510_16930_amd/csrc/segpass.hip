@@ -355,6 +355,14 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
 // ---------------------------------------------------------------------------
 // TTMcTC pass
 // ---------------------------------------------------------------------------
+// LDS of the TTMcTC pass (floats): staged y_i, cross-wave reduction (several
+// tiles), slot table, slice-table windows.
+__host__ __device__ inline int ttm_lds_floats(const SegArgs& a, int KN2) {
+  const int multi = a.B > 1;
+  return a.B * a.RPW * stage_slots(a.B) * YS + (multi ? a.RPW * a.B * KN2 * 256 : 0) + a.RPW * 32 +
+         a.B * a.RPW * 128;
+}
+
 template <int NM1, int KN2, int PREC>
 __device__ inline void ttm_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
@@ -376,9 +384,10 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
   int32_t* slot_kind = slot_row + 16;
   int32_t* wlds = slot_base + a.RPW * 32 + wv * 128;  // slice-table window of this wave
 
-  // stage-two operand of this block, read from memory (L1/L2-resident) when
-  // needed: gtl[kb][t] = G_(n)^T[64 g + t][16 kb + q]
-  const float* gtl = a.gtop + ((size_t)b * KN2 * 64 + lane) * 64;
+  // stage-two operand of this block, read from memory (L1/L2-resident: the
+  // same few kilobytes for every workgroup): step u reads the contiguous
+  // kilobyte gtl[(kb * 16 + u) * 256 ..], G_(n)^T[64 g + 4u + v][16 kb + q]
+  const float* gtl = a.gtop + (size_t)b * KN2 * 4096 + lane * 4;
 
   uint32_t ka4, kb4, kc4;
   lane_offsets<NM1, PREC>(a, rb, cb, q, &ka4, &kb4, &kc4);
@@ -411,7 +420,7 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
       const f4 yv = *reinterpret_cast<const f4*>(yrow + 4 * u);
 #pragma unroll
       for (int kb = 0; kb < KN2; ++kb) {
-        const f4 gv = *reinterpret_cast<const f4*>(gtl + (size_t)kb * 4096 + 4 * u);
+        const f4 gv = *reinterpret_cast<const f4*>(gtl + (kb * 16 + u) * 256);
 #pragma unroll
         for (int v = 0; v < 4; ++v) d[kb] = mfma4(yv[v], gv[v], d[kb]);
       }
@@ -548,15 +557,15 @@ __global__ void k_zero_rows(const int32_t* empty_row, int64_t row0, int64_t E, i
 }
 
 
-// gtop[b][kb][lane][t] = G_(n)^T[j'][kn] with j' = 64 (lane/16) + t inside block b
-// (j' = c*16 + r), kn = 16 kb + lane%16; zero in padding. A lane's 64 values
-// are contiguous (16-byte loads in stage two).
+// gtop[b][kb][u][lane][v] = G_(n)^T[j'][kn] with j' = 64 (lane/16) + 4u + v
+// inside block b (j' = c*16 + r), kn = 16 kb + lane%16; zero in padding. Step
+// u of stage two reads one contiguous kilobyte (16 bytes per lane).
 __device__ inline void prep_body(const PrepArgs& p, const int blk) {
   const int64_t total = (int64_t)p.B * p.KN2 * 4096;
   for (int64_t idx = blk * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)p.nblk * blockDim.x) {
-    const int t = (int)(idx & 63);
-    const int lane = (int)((idx >> 6) & 63);
+    const int t = (int)(((idx >> 8) & 15) * 4 + (idx & 3));
+    const int lane = (int)((idx >> 2) & 63);
     const int64_t rest = idx >> 12;
     const int kb = (int)(rest % p.KN2);
     const int b = (int)(rest / p.KN2);
@@ -1025,8 +1034,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   a.meta = p->sc.meta;
   a.out_map = out_map;
   job->threads = 64 * g.B * a.RPW;
-  job->shmem = (size_t)(g.B * a.RPW * stage_slots(g.B) * YS + (g.B > 1 ? a.RPW * g.B * KN2 * 256 : 0) + a.RPW * 32 +
-                        g.B * a.RPW * 128) * 4;
+  job->shmem = (size_t)ttm_lds_floats(a, KN2) * 4;
   job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
   // split slices
   FixArgs& f = job->fix;
