@@ -127,6 +127,11 @@ typedef struct {
   int32_t orthonormalize_input; /* nonzero: first replace each U^(n) by its orthonormal basis */
   int32_t keep_on_breakdown;  /* nonzero: a rank-deficient A^(n) leaves U^(n) unchanged for that
                                  step (counted in skipped_updates) instead of ending the run */
+  double* d_grad_hist;  /* optional (device, max_sweeps * N doubles): squared norm of the
+                           Riemannian gradient of f with respect to U^(n) at every mode step
+                           (§5.2: grad_n = 2 (A^(n) - U^(n) G_(n) G_(n)^T), evaluated before
+                           U^(n) is updated); NULL and grad_tol == 0 turn the monitor off */
+  double grad_tol;      /* > 0: also stop when sqrt(sum_n ||grad_n||^2) over a sweep <= grad_tol * f_t */
 } hoqri_run_opts;
 
 typedef struct {
@@ -137,6 +142,7 @@ typedef struct {
   double rel_change;    /* |f_t - f_{t-1}| / f_t at the last sweep */
   double orth_err_max;  /* max_n ||U^(n)T U^(n) - I||_F of the returned factors */
   int32_t skipped_updates; /* mode updates skipped for rank deficiency (keep_on_breakdown) */
+  double grad_norm2;    /* sum_n ||grad_n||^2 of the last sweep (-1 when the monitor is off) */
 } hoqri_run_stats;
 
 /* HOQRI (Alg. 2): for each sweep, for n = 1..N: G from the current factors,

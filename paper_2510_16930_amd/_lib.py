@@ -43,13 +43,14 @@ class HoqriError(RuntimeError):
 class RunOpts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("prec", ctypes.c_int),
                 ("check_every", ctypes.c_int32), ("orthonormalize_input", ctypes.c_int32),
-                ("keep_on_breakdown", ctypes.c_int32)]
+                ("keep_on_breakdown", ctypes.c_int32), ("d_grad_hist", ctypes.c_void_p),
+                ("grad_tol", ctypes.c_double)]
 
 
 class RunStats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("norm_x2", ctypes.c_double), ("f", ctypes.c_double),
                 ("fit", ctypes.c_double), ("rel_change", ctypes.c_double), ("orth_err_max", ctypes.c_double),
-                ("skipped_updates", ctypes.c_int32)]
+                ("skipped_updates", ctypes.c_int32), ("grad_norm2", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -280,10 +281,12 @@ class Stats:
     rel_change: float
     orth_err_max: float
     skipped_updates: int = 0
+    grad_norm2: float = -1.0
 
 
 def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp32", check_every: int = 1,
-              orthonormalize_input: bool = False, G=None, f_hist=None, stream=None, keep_on_breakdown: bool = False):
+              orthonormalize_input: bool = False, G=None, f_hist=None, stream=None, keep_on_breakdown: bool = False,
+              grad_hist=None, grad_tol: float = 0.0):
     """Runs HOQRI in place on Us. Returns (G, Stats)."""
     import torch
     L = load()
@@ -291,12 +294,16 @@ def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp
         _need_cuda(U, torch.float32, "U")
     if G is None:
         G = torch.empty(plan.ranks, dtype=torch.float32, device=Us[0].device)
+    if grad_hist is not None:
+        _need_cuda(grad_hist, torch.float64, "grad_hist")
     opts = RunOpts(int(max_sweeps), float(tol), PREC[prec], int(check_every), int(bool(orthonormalize_input)),
-                   int(bool(keep_on_breakdown)))
+                   int(bool(keep_on_breakdown)), ctypes.c_void_p(grad_hist.data_ptr()) if grad_hist is not None else None,
+                   float(grad_tol))
     st = RunStats()
     _check(L.hoqri_run(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f_hist) if f_hist is not None else None,
                        ctypes.byref(opts), ctypes.byref(st), _stream(stream)), "hoqri_run")
-    return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max, st.skipped_updates)
+    return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max, st.skipped_updates,
+                    st.grad_norm2)
 
 
 def hoqri_timing_enable(plan: Plan, enable: bool = True):

@@ -62,6 +62,7 @@ struct Scratch {
   int32_t* status;     // device status flags [4]
   double* f_dev;       // scalars [64]
   double* fsweep;      // f after each sweep inside hoqri_run [kMaxSweeps + 1]
+  double* gscr;        // gradient monitor: G_(n) G_(n)^T [32*32], block partials [4096], history
   float* ybuf;         // core pass rows y_i of the core mode [ybuf_rows][B_c * 256] (row-writing path)
   float* ycarry;       // their split-slice partials [core_w][2][B_c * 256]
   int32_t* ymeta;      // [core_w][4]
@@ -152,6 +153,11 @@ hoqri_status from_labels(hoqri_plan* p, float* const* U, hipStream_t s);
 // Zeroes the label-order rows of mode n's empty slices (rows R_n .. I_n-1).
 hoqri_status zero_empty_rows(hoqri_plan* p, int n, hipStream_t s);
 hoqri_status fill_i32(int32_t* x, int n, int32_t v, hipStream_t s);
+
+// Riemannian gradient monitor (run.hip): ||2 (A - U G_(n) G_(n)^T)||_F^2 into *out.
+hoqri_status launch_grad(hoqri_plan* p, int mode, const float* A, const float* U, const float* G, double* out,
+                         hipStream_t s);
+constexpr int kGradParts = 4096;
 
 // CholeskyQR2 (orth.hip).
 size_t orth_ws_bytes(int64_t rows, int32_t cols);

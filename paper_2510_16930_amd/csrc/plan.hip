@@ -483,6 +483,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   r.take<int32_t>(64);                  // status
   r.take<double>(64);                   // scalars
   r.take<double>(kMaxSweeps + 1);       // f after each sweep
+  r.take<double>(kMaxRank * kMaxRank + kGradParts + (size_t)kMaxSweeps * kMaxOrder);  // gradient monitor
   if (L->core_rows) {
     const int64_t row = (int64_t)(gpart / (16 * ((K[L->core_mode] + 15) / 16)));  // B_c * 256
     r.take<float>((size_t)(L->ybuf_rows * row));             // slice rows
@@ -725,6 +726,7 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
   p->sc.status = r.take<int32_t>(64);
   p->sc.f_dev = r.take<double>(64);
   p->sc.fsweep = r.take<double>(kMaxSweeps + 1);
+  p->sc.gscr = r.take<double>(kMaxRank * kMaxRank + kGradParts + (size_t)kMaxSweeps * kMaxOrder);
   p->sc.ybuf = p->sc.ycarry = nullptr;
   p->sc.ymeta = nullptr;
   if (L.core_rows) {

@@ -56,6 +56,76 @@ __global__ void k_fill_f32(float* x, int64_t n, float v) {
     x[i] = v;
 }
 
+// GG[p][q] = sum over the other indices of G(p, .) G(q, .) in mode n (float64).
+__global__ __launch_bounds__(256) void k_ggt(const float* G, int N, int mode, int32_t K0, int32_t K1, int32_t K2,
+                                             int32_t K3, double* GG) {
+  const int32_t Kd[4] = {K0, K1, K2, K3};
+  const int Kn = Kd[mode];
+  int64_t stride = 1, other = 1;
+  for (int m = N - 1; m > mode; --m) stride *= Kd[m];
+  for (int m = 0; m < N; ++m)
+    if (m != mode) other *= Kd[m];
+  // element (p, o) of the unfolding: o = hi * stride + lo with lo < stride
+  for (int e = threadIdx.x; e < Kn * Kn; e += blockDim.x) {
+    const int pr = e / Kn, pc = e - (e / Kn) * Kn;
+    double acc = 0.0;
+    for (int64_t o = 0; o < other; ++o) {
+      const int64_t hi = o / stride, lo = o - hi * stride;
+      const int64_t base = hi * stride * Kn + lo;
+      acc += (double)G[base + (int64_t)pr * stride] * (double)G[base + (int64_t)pc * stride];
+    }
+    GG[e] = acc;
+  }
+}
+
+// Per-block partial of ||A - U GG||_F^2 over rows x K elements (float64).
+__global__ __launch_bounds__(256) void k_grad_rows(const float* A, const float* U, const double* GG, int64_t rows,
+                                                   int32_t K, double* part) {
+  __shared__ double gg[32 * 32];
+  __shared__ double sh[256];
+  for (int e = threadIdx.x; e < K * K; e += 256) gg[e] = GG[e];
+  __syncthreads();
+  const int64_t total = rows * K;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int64_t r = t / K;
+    const int c = (int)(t - r * K);
+    double v = (double)A[t];
+    for (int k = 0; k < K; ++k) v -= (double)U[r * K + k] * gg[k * K + c];
+    acc += v * v;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// out = 4 * (sum of the partials), in order
+__global__ void k_grad_final(const double* part, int n, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = 4.0 * sh[0];
+}
+
+// sum of the N values of row t of the history
+__global__ void k_grad_sweep(const double* hist, int t, int N, double* out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int n = 0; n < N; ++n) s += hist[(size_t)t * N + n];
+    out[0] = s;
+  }
+}
+
 int grid_of(int64_t n) {
   int64_t g = (n + 255) / 256;
   return (int)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
@@ -113,6 +183,23 @@ hoqri_status zero_empty_rows(hoqri_plan* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(ne)), dim3(256), 0, s, p->sc.Up[n] + Rn * p->K[n], ne, 0.f);
     HOQRI_HIP_TRY(hipGetLastError());
   }
+  return HOQRI_OK;
+}
+
+hoqri_status launch_grad(hoqri_plan* p, int mode, const float* A, const float* U, const float* G, double* out,
+                         hipStream_t s) {
+  double* GG = p->sc.gscr;
+  double* part = p->sc.gscr + kMaxRank * kMaxRank;
+  int32_t Kd[4] = {1, 1, 1, 1};
+  for (int m = 0; m < p->N; ++m) Kd[m] = p->K[m];
+  hipLaunchKernelGGL(k_ggt, dim3(1), dim3(256), 0, s, G, p->N, mode, Kd[0], Kd[1], Kd[2], Kd[3], GG);
+  const int64_t total = p->dims[mode] * p->K[mode];
+  int64_t nb = (total + 255) / 256;
+  if (nb > kGradParts) nb = kGradParts;
+  hipLaunchKernelGGL(k_grad_rows, dim3((unsigned)nb), dim3(256), 0, s, A, U, (const double*)GG, p->dims[mode],
+                     p->K[mode], part);
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), 0, s, (const double*)part, (int)nb, out);
+  HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
 }
 
@@ -194,6 +281,9 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   int T = 0;
   double f_last = 0.0, f_prev = 0.0, rel = 0.0;
   bool have_prev = false;
+  if (!(opts->grad_tol >= 0.0)) return HOQRI_ERR_ARG;
+  const bool grad_on = opts->d_grad_hist != nullptr || opts->grad_tol > 0.0;
+  double* ghist = p->sc.gscr + kMaxRank * kMaxRank + kGradParts;  // [kMaxSweeps][N]
   for (int t = 0; t < opts->max_sweeps; ++t) {
     for (int n = 0; n < N; ++n) {
       if (n > 0) {
@@ -201,6 +291,9 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
         HOQRI_TRY(launch_core(p, ops, d_G_out, fdst, stream));
       }
       HOQRI_TRY(launch_ttmctc(p, n, ops, d_G_out, p->sc.A, nullptr, stream));
+      // Riemannian gradient at the current point, before U^(n) moves (A rows of
+      // empty slices are zero, all I_n rows of U take part)
+      if (grad_on) HOQRI_TRY(launch_grad(p, n, p->sc.A, Up[n], d_G_out, ghist + (size_t)t * N + n, stream));
       // rows R_n.. of A are zero (empty slices): orthonormalise the first R_n rows
       // and keep the remaining rows of the factor at zero
       const int64_t Rn = p->md[n].R;
@@ -214,9 +307,14 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     T = t + 1;
     if (T % opts->check_every == 0 || T == opts->max_sweeps) {
       double fv[2];
+      double gsum = 0.0;
       int32_t st = 0;
       HOQRI_HIP_TRY(hipMemcpyAsync(fv, fsw + T - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
       HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      if (opts->grad_tol > 0.0) {
+        hipLaunchKernelGGL(k_grad_sweep, dim3(1), dim3(64), 0, stream, (const double*)ghist, T - 1, N, p->sc.f_dev + 16);
+        HOQRI_HIP_TRY(hipMemcpyAsync(&gsum, p->sc.f_dev + 16, sizeof(double), hipMemcpyDeviceToHost, stream));
+      }
       HOQRI_HIP_TRY(hipStreamSynchronize(stream));
       if (st != 0) return HOQRI_ERR_BREAKDOWN;
       f_prev = fv[0];
@@ -224,11 +322,20 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       have_prev = true;
       rel = f_last > 0 ? std::fabs(f_last - f_prev) / f_last : 0.0;
       if (opts->tol > 0.0 && std::fabs(f_last - f_prev) <= opts->tol * f_last) break;
+      if (opts->grad_tol > 0.0 && std::sqrt(std::fmax(gsum, 0.0)) <= opts->grad_tol * f_last) break;
     }
   }
   // the returned core and f are those of the final factors with float32
   // operands, whatever form the sweeps used
   if (op != OP_FP32) HOQRI_TRY(launch_core(p, plan_operands(p, OP_FP32), d_G_out, fsw + T, stream));
+  if (opts->d_grad_hist && T > 0)
+    HOQRI_HIP_TRY(hipMemcpyAsync(opts->d_grad_hist, ghist, (size_t)T * N * sizeof(double), hipMemcpyDeviceToDevice,
+                                 stream));
+  double glast = -1.0;
+  if (grad_on && T > 0) {
+    hipLaunchKernelGGL(k_grad_sweep, dim3(1), dim3(64), 0, stream, (const double*)ghist, T - 1, N, p->sc.f_dev + 16);
+    HOQRI_HIP_TRY(hipMemcpyAsync(&glast, p->sc.f_dev + 16, sizeof(double), hipMemcpyDeviceToHost, stream));
+  }
   if (d_f_hist && T > 0) {
     hipLaunchKernelGGL(k_hist_first, dim3(1), dim3(256), 0, stream, fsw, T, N, d_f_hist);
     HOQRI_HIP_TRY(hipGetLastError());
@@ -249,6 +356,7 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   if (st != 0) return HOQRI_ERR_BREAKDOWN;
   (void)have_prev;
   stats->skipped_updates = skips;
+  stats->grad_norm2 = glast;
   stats->sweeps = T;
   stats->norm_x2 = p->normx2;
   stats->f = fend;

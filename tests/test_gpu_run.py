@@ -178,3 +178,32 @@ def test_rank_deficient_mode_kept_like_oracle():
     for n in (1, 2):
         assert np.abs(Us[n].cpu().numpy() - Uo[n]).max() < 1e-4
     assert st.f == pytest.approx(h["f_sweep"][-1], rel=1e-5)
+
+
+def test_riemannian_gradient_monitor():
+    # ||grad_n||^2 = ||2 (A^(n) - U^(n) G_(n) G_(n)^T)||^2 at every mode step (§5.2), before
+    # U^(n) moves; the oracle evaluates the equivalent 4 (||A||^2 - ||G_(n) G_(n)^T||^2) in float64
+    dims, K = (200, 200, 200), (5, 5, 5)
+    idx, vals = synth.coo_uniform(dims, 20000, seed=11)
+    U0 = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 111))]
+    plan = H.hoqri_plan_create(dev(idx), dev(vals.astype(np.float32)), dims, K)
+    Us = [dev(u) for u in U0]
+    gh = torch.zeros(6 * 3, dtype=torch.float64, device=DEV)
+    G, st = H.hoqri_run(plan, Us, max_sweeps=6, grad_hist=gh)
+    Uo, Go, h = O.hoqri(idx, vals.astype(np.float32).astype(np.float64), dims, K, [u.astype(np.float64) for u in U0],
+                        sweeps=6, record_A=True)
+    ref = np.array([O.grad_norm2_mode(A, Gs, i % 3) for i, (A, Gs) in enumerate(zip(h["A"], h["G_step"]))])
+    got = gh.cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-4)
+    assert st.grad_norm2 == pytest.approx(float(ref[-3:].sum()), rel=1e-4)
+    # stop rule on the gradient: the run ends at the first sweep whose gradient is small enough
+    r = [float(np.sqrt(ref[3 * t:3 * t + 3].sum()) / h["f_sweep"][t]) for t in range(6)]
+    assert r[0] > r[1] > r[2]
+    tol = float(np.sqrt(r[1] * r[2]))  # met after sweep 3, not before
+    Us = [dev(u) for u in U0]
+    G, st2 = H.hoqri_run(plan, Us, max_sweeps=20, grad_tol=tol)
+    assert st2.sweeps == 3
+    # off by default
+    Us = [dev(u) for u in U0]
+    G, st3 = H.hoqri_run(plan, Us, max_sweeps=2)
+    assert st3.grad_norm2 == -1.0
