@@ -12,12 +12,19 @@
 // request's f = ||G||^2 and breakdown flag, decides which requests finish
 // (stop rule at a sweep boundary, or max_sweeps), and launches the rest.
 // Admission is first-come first-served by footprint: the head of the queue is
-// admitted when a slot is free and its plan workspace fits in the arena.
+// taken when a slot is (about to be) free and its plan workspace fits in the
+// arena. Plans are built by a builder thread on its own stream, so building
+// (sorts, slice tables, two synchronisations) overlaps the engine steps;
+// built plans join the batch at the next step.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -96,6 +103,12 @@ struct Pending {
   hoqri_status pre;  // error found at submit/admission, reported as the result
 };
 
+struct Built {
+  Pending q;
+  hoqri_plan* plan;
+  size_t off;
+};
+
 struct Active {
   Pending q;
   hoqri_plan* plan;
@@ -128,11 +141,21 @@ struct hoqri_server {
   double* h_f = nullptr;
   int32_t* h_stat = nullptr;
   int32_t* h_skip = nullptr;
-  std::deque<hoqri::Pending> queue;
-  std::vector<hoqri::Active> active;
-  std::vector<int> free_slots;
-  std::deque<hoqri_result> done;  // finished, not yet handed out
+  std::vector<hoqri::Active> active;  // engine thread only
+  std::vector<int> free_slots;        // engine thread only
   int64_t step_no = 0;
+  // shared with the builder thread (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv_build;   // builder: work or memory became available
+  std::condition_variable cv_ready;   // engine: a plan was built (or failed)
+  std::deque<hoqri::Pending> queue;
+  std::deque<hoqri::Built> ready;
+  std::deque<hoqri_result> done;      // finished, not yet handed out
+  int n_active = 0;
+  int building = 0;
+  bool stop = false;
+  hoqri_status builder_error = HOQRI_OK;
+  std::thread builder;
 };
 
 using namespace hoqri;
@@ -163,46 +186,95 @@ hoqri_status finish_copy(hoqri_server* S, Active& a, hipStream_t s, double* d_er
   return HOQRI_OK;
 }
 
-hoqri_status admit(hoqri_server* S, hipStream_t s) {
-  int admitted = 0;
-  while (!S->queue.empty() && !S->free_slots.empty() &&
-         (S->o.max_admit_per_step <= 0 || admitted < S->o.max_admit_per_step)) {
-    Pending& q = S->queue.front();
+// Builder thread: takes the head of the queue when the batch has room for it
+// (slots in use + built + building below max_slots plus a small lookahead)
+// and its workspace fits in the arena, builds its plan on its own stream, and
+// hands it to the engine. A request that does not fit waits; none overtakes it.
+void builder_loop(hoqri_server* S) {
+  hipStream_t bs = nullptr;
+  hoqri_status err = HOQRI_OK;
+  if (hipSetDevice(S->device) != hipSuccess || hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess)
+    err = HOQRI_ERR_HIP;
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (err != HOQRI_OK) {
+    S->builder_error = err;
+    S->cv_ready.notify_all();
+    return;
+  }
+  const int lookahead = 2;
+  while (true) {
+    size_t off = 0;
+    S->cv_build.wait(lk, [&] {
+      if (S->stop) return true;
+      if (S->queue.empty()) return false;
+      if (S->n_active + (int)S->ready.size() >= S->o.max_slots + lookahead) return false;
+      const Pending& q = S->queue.front();
+      if (q.pre != HOQRI_OK || q.need > S->arena->size()) return true;  // fails at once
+      return S->arena->alloc(q.need, &off);
+    });
+    if (S->stop) break;
+    Pending q = std::move(S->queue.front());
+    S->queue.pop_front();
     if (q.pre != HOQRI_OK || q.need > S->arena->size()) {
       S->done.push_back(make_result(q, q.pre != HOQRI_OK ? q.pre : HOQRI_ERR_NOMEM));
-      S->queue.pop_front();
+      S->cv_ready.notify_all();
       continue;
     }
-    size_t off = 0;
-    if (!S->arena->alloc(q.need, &off)) break;  // wait for memory: no overtaking
+    S->building = 1;
+    lk.unlock();
     hoqri_plan* plan = nullptr;
     hoqri_status st = hoqri_plan_create(&plan, q.r.order, q.dims.data(), q.ranks.data(), q.r.nnz, q.r.d_idx,
-                                        q.r.d_vals, S->base + off, q.need, s);
+                                        q.r.d_vals, S->base + off, q.need, bs);
     if (st == HOQRI_OK)
       for (int n = 0; n < plan->N; ++n) {
         if (!segpass_supported(plan, n)) st = HOQRI_ERR_UNSUPPORTED;
         else if (plan->md[n].R < plan->K[n]) st = HOQRI_ERR_BREAKDOWN;  // fewer nonempty slices than K_n
       }
+    lk.lock();
+    S->building = 0;
     if (st != HOQRI_OK) {
       if (plan) hoqri_plan_destroy(plan);
       S->arena->release(off);
       S->done.push_back(make_result(q, st));
-      S->queue.pop_front();
-      continue;
+    } else {
+      S->ready.push_back(Built{std::move(q), plan, off});
     }
+    S->cv_ready.notify_all();
+  }
+  lk.unlock();
+  (void)hipStreamDestroy(bs);
+}
+
+// Engine thread: built plans join the batch (their plan build has completed:
+// the builder synchronised its stream).
+hoqri_status admit(hoqri_server* S, hipStream_t s) {
+  std::deque<Built> take;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->builder_error != HOQRI_OK) return S->builder_error;
+    if (S->active.empty() && S->ready.empty() && (S->building || !S->queue.empty()))
+      S->cv_ready.wait_for(lk, std::chrono::milliseconds(2));  // nothing to run yet
+    int room = (int)S->free_slots.size();
+    if (S->o.max_admit_per_step > 0 && room > S->o.max_admit_per_step) room = S->o.max_admit_per_step;
+    while (room > 0 && !S->ready.empty()) {
+      take.push_back(std::move(S->ready.front()));
+      S->ready.pop_front();
+      --room;
+    }
+    S->n_active += (int)take.size();
+  }
+  for (Built& b : take) {
     Active a{};
-    a.q = std::move(q);
-    S->queue.pop_front();
-    a.plan = plan;
-    a.off = off;
+    a.q = std::move(b.q);
+    a.plan = b.plan;
+    a.off = b.off;
     a.slot = S->free_slots.back();
     S->free_slots.pop_back();
     a.admitted = S->step_no;
-    HOQRI_TRY(to_labels(plan, a.q.U.data(), s));
+    HOQRI_TRY(to_labels(a.plan, a.q.U.data(), s));
     HOQRI_TRY(fill_i32(S->d_stat + a.slot, 1, 0, s));
     HOQRI_TRY(fill_i32(S->d_skip + a.slot, 1, 0, s));
     S->active.push_back(std::move(a));
-    ++admitted;
   }
   return HOQRI_OK;
 }
@@ -304,6 +376,14 @@ extern "C" hoqri_status hoqri_server_create(const hoqri_server_opts* opts, hoqri
     return HOQRI_ERR_NOMEM;
   }
   for (int i = slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+  try {
+    S->builder = std::thread(builder_loop, S);
+  } catch (...) {
+    (void)hipHostFree(S->pinned);
+    delete S->arena;
+    delete S;
+    return HOQRI_ERR_NOMEM;
+  }
   *server = S;
   return HOQRI_OK;
 }
@@ -324,7 +404,11 @@ extern "C" hoqri_status hoqri_server_submit(hoqri_server* S, const hoqri_request
   q.need = 0;
   q.pre = hoqri_plan_workspace_size(r->order, q.dims.data(), q.ranks.data(), r->nnz, &q.need);
   if (q.pre == HOQRI_ERR_HIP) return q.pre;
-  S->queue.push_back(std::move(q));
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->queue.push_back(std::move(q));
+  }
+  S->cv_build.notify_one();
   return HOQRI_OK;
 }
 
@@ -434,12 +518,17 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
           HOQRI_HIP_TRY(hipMemcpy(e, a.plan->sc.f_dev + 8, a.plan->N * sizeof(double), hipMemcpyDeviceToHost));
           for (int n = 0; n < a.plan->N; ++n) r.orth_err_max = std::max(r.orth_err_max, e[n]);
         }
-        S->done.push_back(r);
-        S->arena->release(a.off);
+        {
+          std::lock_guard<std::mutex> lk(S->mu);
+          S->done.push_back(r);
+          S->arena->release(a.off);
+          --S->n_active;
+        }
         S->free_slots.push_back(a.slot);
         hoqri_plan_destroy(a.plan);
         a.plan = nullptr;
       }
+      S->cv_build.notify_one();
       std::vector<Active> keep;
       keep.reserve(act.size());
       for (Active& a : act)
@@ -449,9 +538,12 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
   }
   ++S->step_no;
   int32_t k = 0;
-  while (k < cap && !S->done.empty()) {
-    results[k++] = S->done.front();
-    S->done.pop_front();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    while (k < cap && !S->done.empty()) {
+      results[k++] = S->done.front();
+      S->done.pop_front();
+    }
   }
   *n_results = k;
   return HOQRI_OK;
@@ -459,14 +551,25 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
 
 extern "C" hoqri_status hoqri_server_info(const hoqri_server* S, int32_t* queued, int32_t* active, size_t* used) {
   if (!S) return HOQRI_ERR_ARG;
-  if (queued) *queued = (int32_t)S->queue.size();
-  if (active) *active = (int32_t)S->active.size();
-  if (used) *used = S->arena->used();
+  hoqri_server* M = const_cast<hoqri_server*>(S);
+  std::lock_guard<std::mutex> lk(M->mu);
+  // waiting, being built, built but not yet in the batch; results not yet handed out count as active
+  if (queued) *queued = (int32_t)(M->queue.size() + M->ready.size()) + M->building;
+  if (active) *active = M->n_active + (int32_t)M->done.size();
+  if (used) *used = M->arena->used();
   return HOQRI_OK;
 }
 
 extern "C" void hoqri_server_destroy(hoqri_server* S) {
   if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_build.notify_all();
+  if (S->builder.joinable()) S->builder.join();
+  for (Built& b : S->ready)
+    if (b.plan) hoqri_plan_destroy(b.plan);
   for (Active& a : S->active)
     if (a.plan) hoqri_plan_destroy(a.plan);
   if (S->pinned) (void)hipHostFree(S->pinned);
