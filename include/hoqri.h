@@ -158,6 +158,19 @@ typedef struct {
 hoqri_status hoqri_run(hoqri_plan* plan, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
                        const hoqri_run_opts* opts, hoqri_run_stats* stats, hipStream_t stream);
 
+/* HOSVD-style start for Alg. 2 (which may start from HOSVD), by a randomized
+ * range finder of every unfolding: A^(n) = X_(n) (kron over m != n of Omega_m)
+ * Gamma_(n)^T, i.e. TTMcTC (definition in §4.1) with the factors replaced by
+ * d_Omega and the core by d_Gamma, then U^(n) = the orthonormal basis of A^(n)
+ * with positive-diagonal R (as hoqri_orth). Every mode is sketched from X alone.
+ * d_Omega: host array of N device pointers, Omega_m row-major I_m x K_m float32
+ * (random draws, e.g. N(0,1), supplied by the caller); d_Gamma: K_1 x ... x K_N
+ * float32 (C order, random). d_U_out: host array of N device pointers, written
+ * I_n x K_n (rows of empty slices zero). HOQRI_ERR_BREAKDOWN if some sketch is
+ * rank deficient (fewer than K_n nonempty slices, or degenerate draws). */
+hoqri_status hoqri_sketch_start(hoqri_plan* plan, const float* const* d_Omega, const float* d_Gamma,
+                                float* const* d_U_out, hipStream_t stream);
+
 /* Kernel timing (diagnostics). When enabled on a plan, every launch of the
  * listed kernels made through that plan is bracketed by HIP events recorded on
  * the launch stream, and hoqri_timing_read returns the number of launches and

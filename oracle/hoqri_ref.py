@@ -19,7 +19,9 @@ Rank Approximation of Large and Sparse Tensors"):
   rule of §5), with the QR step taken as a Householder QR whose R has a
   positive diagonal;
 * the quantities of the convergence analysis (§5): the objective f = ||G||^2,
-  the Riemannian gradient norm, the subspace distance d(U, V).
+  the Riemannian gradient norm, the subspace distance d(U, V);
+* a HOSVD-style start (Alg. 2 allows one) by a randomized range finder of
+  every unfolding, computed as TTMcTC with random factors and a random core.
 
 Readings where the paper is silent (all also listed in the design doc):
 * QR basis: the thin QR with diag(R) > 0, unique for full-rank A (the paper
@@ -72,6 +74,7 @@ __all__ = [
     "grad_norm2_mode",
     "grad_norm2_direct",
     "tucker_dense",
+    "sketch_start",
 ]
 
 BREAKDOWN_REL = 1e-13
@@ -429,3 +432,22 @@ def grad_norm2_direct(A: np.ndarray, U: np.ndarray, G: np.ndarray, n: int) -> fl
     Gn = unfold(G, n)
     R = 2 * A - 2 * U @ (Gn @ Gn.T)
     return float(np.sum(R * R))
+
+
+# --------------------------------------------------------------------------
+# Start from a randomized range finder (HOSVD-style start of Alg. 2)
+# --------------------------------------------------------------------------
+
+def sketch_start(idx, vals, dims, ranks, Omega: Sequence[np.ndarray], Gamma: np.ndarray):
+    """Alg. 2 may start from HOSVD. A randomized range finder for the leading
+    left singular subspace of every unfolding X_(n): the sketch
+    A^(n) = X_(n) (kron over m != n of Omega_m) Gamma_(n)^T, which is exactly
+    TTMcTC with the factors replaced by the random Omega_m and the core by the
+    random Gamma (definition in §4.1), then U^(n) = the positive-diagonal QR
+    basis of A^(n). Every mode is sketched from X alone (not Gauss-Seidel).
+    Omega_m (I_m x K_m) and Gamma (K_1 x ... x K_N) are inputs (random draws
+    belong to the caller)."""
+    idx, vals = coalesce(idx, vals, dims)
+    Om = [np.asarray(o, dtype=np.float64) for o in Omega]
+    Ga = np.asarray(Gamma, dtype=np.float64)
+    return [qr_positive(ttmctc_segment(idx, vals, Om, n, Ga))[0] for n in range(len(dims))]

@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     hoqri_plan_info,
     hoqri_plan_workspace_size,
     hoqri_run,
+    hoqri_sketch_start,
     hoqri_status_string,
     hoqri_timing_enable,
     hoqri_timing_read,

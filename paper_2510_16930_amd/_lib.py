@@ -30,6 +30,7 @@ EXPORTS = (
     "hoqri_status_string", "hoqri_timing_enable", "hoqri_timing_read",
     "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats", "hoqri_arena_destroy",
     "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info", "hoqri_server_destroy",
+    "hoqri_sketch_start",
 )
 KERNEL = {"ttmctc": 0, "core": 1, "orth": 2, "fixup": 3}
 
@@ -97,6 +98,7 @@ def load() -> ctypes.CDLL:
     L.hoqri_orth_workspace_size.restype = sz
     L.hoqri_orth.argtypes = [i64, i32, vp, vp, vp, vp, vp, sz, vp]
     L.hoqri_run.argtypes = [vp, P(vp), vp, vp, P(RunOpts), P(RunStats), vp]
+    L.hoqri_sketch_start.argtypes = [vp, P(vp), vp, P(vp), vp]
     L.hoqri_timing_enable.argtypes = [vp, i32]
     L.hoqri_timing_read.argtypes = [vp, i32, P(i64), P(dbl)]
     L.hoqri_status_string.argtypes = [ctypes.c_int]
@@ -116,7 +118,8 @@ def load() -> ctypes.CDLL:
     for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
                  "hoqri_ttmctc", "hoqri_orth", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
                  "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats",
-                 "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info"):
+                 "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info",
+                 "hoqri_sketch_start"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -304,6 +307,21 @@ def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp
                        ctypes.byref(opts), ctypes.byref(st), _stream(stream)), "hoqri_run")
     return G, Stats(st.sweeps, st.norm_x2, st.f, st.fit, st.rel_change, st.orth_err_max, st.skipped_updates,
                     st.grad_norm2)
+
+
+def hoqri_sketch_start(plan: Plan, Omega, Gamma, U=None, stream=None):
+    """HOSVD-style start by a randomized range finder (hoqri_sketch_start): Omega is
+    a list of random I_m x K_m float32 tensors, Gamma a random K_1 x ... x K_N core.
+    Returns the N orthonormal factors (float32, I_n x K_n)."""
+    import torch
+    for O_ in Omega:
+        _need_cuda(O_, torch.float32, "Omega")
+    _need_cuda(Gamma, torch.float32, "Gamma")
+    if U is None:
+        U = [torch.empty((d, k), dtype=torch.float32, device=Gamma.device) for d, k in zip(plan.dims, plan.ranks)]
+    _check(load().hoqri_sketch_start(plan.handle, _ptr_array(Omega), _ptr(Gamma), _ptr_array(U), _stream(stream)),
+           "hoqri_sketch_start")
+    return U
 
 
 def hoqri_timing_enable(plan: Plan, enable: bool = True):

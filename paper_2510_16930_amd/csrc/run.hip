@@ -240,6 +240,36 @@ extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* c
   return launch_ttmctc(p, mode, plan_operands(p, op), d_G, d_A, p->md[mode].inv, stream);
 }
 
+extern "C" hoqri_status hoqri_sketch_start(hoqri_plan* p, const float* const* d_Omega, const float* d_Gamma,
+                                          float* const* d_U_out, hipStream_t stream) {
+  HOQRI_TRY(check_plan(p));
+  if (!d_Omega || !d_Gamma || !d_U_out) return HOQRI_ERR_ARG;
+  for (int n = 0; n < p->N; ++n)
+    if (!d_Omega[n] || !d_U_out[n]) return HOQRI_ERR_ARG;
+  for (int n = 0; n < p->N; ++n)
+    if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
+  for (int n = 0; n < p->N; ++n)
+    if (p->md[n].R < p->K[n]) return HOQRI_ERR_BREAKDOWN;
+  // the random factors in label order (the pass reads them there)
+  HOQRI_TRY(to_labels(p, d_Omega, stream));
+  const Operands ops = plan_operands(p, OP_FP32);
+  int32_t* status = p->sc.status;
+  HOQRI_TRY(fill_i32(status, 4, 0, stream));
+  for (int n = 0; n < p->N; ++n) {
+    // sketch of mode n (label-order rows), its basis in place, rows of empty slices zeroed
+    HOQRI_TRY(launch_ttmctc(p, n, ops, d_Gamma, p->sc.A, nullptr, stream));
+    HOQRI_TRY(launch_orth(p->md[n].R, p->K[n], p->sc.A, p->sc.A, nullptr, status, p->sc.orth_ws,
+                          p->sc.orth_ws_bytes, stream, true, nullptr, p->dims[n]));
+    hipLaunchKernelGGL(k_rows_from_labels, dim3(grid_of(p->dims[n] * p->K[n])), dim3(256), 0, stream, p->sc.A,
+                       p->md[n].inv, p->dims[n], p->K[n], d_U_out[n]);
+    HOQRI_HIP_TRY(hipGetLastError());
+  }
+  int32_t st = 0;
+  HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HOQRI_HIP_TRY(hipStreamSynchronize(stream));
+  return st != 0 ? HOQRI_ERR_BREAKDOWN : HOQRI_OK;
+}
+
 extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float* d_G_out, double* d_f_hist,
                                   const hoqri_run_opts* opts, hoqri_run_stats* stats, hipStream_t stream) {
   HOQRI_TRY(check_plan(p));

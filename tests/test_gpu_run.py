@@ -207,3 +207,40 @@ def test_riemannian_gradient_monitor():
     Us = [dev(u) for u in U0]
     G, st3 = H.hoqri_run(plan, Us, max_sweeps=2)
     assert st3.grad_norm2 == -1.0
+
+
+def test_sketch_start_matches_oracle_and_recovers_planted():
+    # c1 shape: GPU range-finder start against the oracle's (same random draws)
+    dims, K = (200, 200, 200), (5, 5, 5)
+    idx, vals = synth.coo_uniform(dims, 20000, seed=11)
+    rng = np.random.default_rng(41)
+    Om = [rng.standard_normal((d, k)).astype(np.float32) for d, k in zip(dims, K)]
+    Ga = rng.standard_normal(K).astype(np.float32)
+    plan = H.hoqri_plan_create(dev(idx), dev(vals.astype(np.float32)), dims, K)
+    U = [u.cpu().numpy().astype(np.float64) for u in H.hoqri_sketch_start(plan, [dev(o) for o in Om], dev(Ga))]
+    Uo = O.sketch_start(idx, vals.astype(np.float32).astype(np.float64), dims, K,
+                        [o.astype(np.float64) for o in Om], Ga.astype(np.float64))
+    for n in range(3):
+        assert np.abs(U[n] - Uo[n]).max() < 1e-3
+        assert O.subspace_dist(U[n], Uo[n]) < 1e-6
+        np.testing.assert_allclose(U[n].T @ U[n], np.eye(K[n]), atol=1e-5)
+        empty = np.setdiff1d(np.arange(dims[n]), idx[n])
+        assert np.all(U[n][empty] == 0.0)
+    # planted exact multilinear rank: the start already spans the planted subspaces
+    rng = np.random.default_rng(42)
+    dims, K, support = (400, 500, 600), (3, 4, 2), (9, 11, 9)
+    U0t, rows = [], []
+    for d, k, s in zip(dims, K, support):
+        r = np.sort(rng.choice(d, size=s, replace=False))
+        M = np.zeros((d, k))
+        M[r] = rng.standard_normal((s, k))
+        U0t.append(np.linalg.qr(M)[0])
+        rows.append(r)
+    block = O.tucker_dense(rng.standard_normal(K), [u[r] for u, r in zip(U0t, rows)])
+    grids = np.meshgrid(*rows, indexing="ij")
+    pidx = np.stack([g.ravel() for g in grids]).astype(np.int32)
+    plan = H.hoqri_plan_create(dev(pidx), dev(block.ravel().astype(np.float32)), dims, K)
+    Om = [dev(rng.standard_normal((d, k)).astype(np.float32)) for d, k in zip(dims, K)]
+    U = H.hoqri_sketch_start(plan, Om, dev(rng.standard_normal(K).astype(np.float32)))
+    for n in range(3):
+        assert O.subspace_dist(U[n].cpu().numpy().astype(np.float64), U0t[n]) < 1e-7

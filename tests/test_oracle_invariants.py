@@ -199,3 +199,23 @@ def test_rank_deficient_mode_is_kept_on_request():
     assert not np.array_equal(U[1], U0[1])        # the other modes moved
     f = h["f_step"] + [h["f_sweep"][-1]]
     assert all(b >= a - 1e-12 * abs(b) for a, b in zip(f, f[1:]))  # Theorem 1 still holds
+
+
+def test_sketch_start_recovers_planted_subspaces_and_hosvd():
+    # exact multilinear rank K: the range finder spans the column space of every
+    # unfolding, which is span(U0_n) (probability one over the Gaussian draws)
+    rng = np.random.default_rng(31)
+    dims, K = (30, 25, 20), (3, 4, 2)
+    U0 = [np.linalg.qr(rng.standard_normal((d, k)))[0] for d, k in zip(dims, K)]
+    X = O.tucker_dense(rng.standard_normal(K), U0)
+    idx = np.stack(np.unravel_index(np.arange(X.size), dims)).astype(np.int32)
+    Om = [rng.standard_normal((d, k)) for d, k in zip(dims, K)]
+    Ga = rng.standard_normal(K)
+    U = O.sketch_start(idx, X.ravel(), dims, K, Om, Ga)
+    for n in range(3):
+        assert O.subspace_dist(U[n], U0[n]) < 1e-12
+        np.testing.assert_allclose(U[n].T @ U[n], np.eye(K[n]), atol=1e-12)
+    # against the dense definition: the sketch of X_(n) is X_(n) (kron Omega) Gamma_(n)^T
+    n = 1
+    S = O.unfold(X, n) @ O.kron_except(Om, n) @ O.unfold(Ga, n).T
+    np.testing.assert_allclose(U[n], O.qr_positive(S)[0], atol=1e-12)
