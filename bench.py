@@ -75,7 +75,8 @@ def pass_work(dims, ranks, nnz, R, su=4):
 
 
 TRAFFIC_PROFILES = {("c2", "fp32"): "profiles/ttmctc_fp32_c2_traffic.txt"}
-KERNEL_SOURCES = ("paper_2510_16930_amd/csrc/segpass.hip", "paper_2510_16930_amd/csrc/common.h")
+KERNEL_SOURCES = ("paper_2510_16930_amd/csrc/segpass.hip", "paper_2510_16930_amd/csrc/common.h",
+                  "paper_2510_16930_amd/csrc/passes.h")
 
 
 def measured_traffic(config, prec):
