@@ -63,9 +63,10 @@ struct Scratch {
   double* f_dev;       // scalars [64]
   double* fsweep;      // f after each sweep inside hoqri_run [kMaxSweeps + 1]
   double* gscr;        // gradient monitor: G_(n) G_(n)^T [32*32], block partials [4096], history
-  float* ybuf;         // core pass rows y_i of the core mode [ybuf_rows][B_c * 256] (row-writing path)
-  float* ycarry;       // their split-slice partials [core_w][2][B_c * 256]
-  int32_t* ymeta;      // [core_w][4]
+  float* ybuf;         // slice rows y_i: of the core mode [ybuf_rows][B_c * 256] (row-writing core
+                       // pass), or of a TTMcTC pass's mode [R_n][B_n * 256] (stored rows)
+  float* ycarry;       // their split-slice partials [ranges][2][B * 256]
+  int32_t* ymeta;      // [core_w][4] (the TTMcTC pass keeps its range metadata in meta)
   size_t orth_ws_bytes;
 };
 
@@ -95,6 +96,7 @@ struct hoqri_plan {
   int32_t core_rows;   // the core pass writes slice rows (see Layout)
   int64_t ybuf_rows;
   int32_t core_w;
+  int32_t yfuse;       // TTMcTC passes can store Y_(n) and the core follows from it
   hoqri::ModeData md[hoqri::kMaxOrder];
   hoqri::Scratch sc;
   void* ws;
@@ -119,8 +121,13 @@ struct Layout {
   int32_t core_rows;     // nonzero: core pass writes slice rows y_i, then a small product with U^(c)
   int64_t ybuf_rows;     // rows of the slice-row buffer (>= nonempty slices of the core mode)
   int32_t core_w;        // work ranges of the row-writing core pass
+  int32_t yfuse;         // every mode's TTMcTC pass can store its slice rows
+  size_t ybuf_floats;    // slice-row buffer
+  size_t ycarry_floats;  // its split-slice partials
+  size_t gpart_floats;   // core partials
 };
-constexpr int kCoreChunk = 64;  // rows per partial of the core product U^(c)T Y
+constexpr int kCoreChunk = 64;  // rows per partial of the core product U^(c)T Y (core-mode pass)
+constexpr int kYChunks = 1024;  // most partials of the core product from stored rows
 
 hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L);
 hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz);
@@ -138,8 +145,12 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
 // out_map null: A rows in label order and rows R..I-1 zeroed; otherwise row r is
 // written at out_map[r] (original order) and the empty slices' original rows
 // are zeroed.
+// rows: the pass also stores Y_(mode) for launch_ycore (requires yfuse).
 hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
-                           const int32_t* out_map, hipStream_t s);
+                           const int32_t* out_map, hipStream_t s, bool rows = false);
+// G = X x {U^T} from the rows Y_(mode) stored by the last TTMcTC pass of `mode`
+// and the (updated) factor U^(mode) in the plan's scratch; ||G||^2 into *f_out.
+hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s);
 bool segpass_supported(const hoqri_plan* p, int mode);
 // Power-of-two scales of the FP16 form for this plan (false: the values' range
 // does not allow them; use another precision).

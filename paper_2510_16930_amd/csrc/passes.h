@@ -39,6 +39,8 @@ struct SegArgs {
   float* carry;             // [W][2][32]
   int32_t* meta;            // [W][4]
   const int32_t* out_map;   // null: A rows in label order; else row r goes to out_map[r]
+  float* yrow;              // non-null: the TTMcTC pass also stores every y_i, [R][B * 256] by label
+  float* ycarry;            // with yrow: partial rows of split slices [W][2][B * 256]
   // core
   const float* Uc;          // factor of the pass mode
   int32_t Kc;
@@ -85,6 +87,7 @@ struct CoreGemmArgs {
   const int32_t* seg_row;
   const float* Uc;
   int32_t Kc, KC, R, W, B;
+  int32_t chunk;  // rows per partial
   float* gpart;
 };
 
@@ -130,11 +133,24 @@ struct CoreJob {
   SumArgs sum;
 };
 
+// Core from the slice rows a TTMcTC pass stored (G_(n) = U^(n)T Y_(n) with the
+// updated factor U^(n)): product over chunks of rows, fixed-order reduction.
+struct YCoreJob {
+  CoreGemmArgs gemm;
+  int gemm_blocks;
+  CoreRedArgs red;
+  int red_blocks;
+  SumArgs sum;
+};
+
 // Fills a job for one plan (no device work). G: the core the TTMcTC pass
-// multiplies by; A: its output (rows in label order when out_map is null).
+// multiplies by; A: its output (rows in label order when out_map is null);
+// rows: the pass also stores Y_(n) for prepare_ycore.
 hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
-                         const int32_t* out_map, TtmJob* job);
+                         const int32_t* out_map, TtmJob* job, bool rows = false);
 hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, CoreJob* job);
+// After the TTMcTC pass of `mode` with rows and the update of U^(mode) (float32, label order).
+hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job);
 
 struct GramArgs {
   const float* A;
@@ -251,13 +267,18 @@ struct CoreGroup {
 struct OrthGroup {
   BatchTable g1, r1, c, ap;
 };
+struct YCoreGroup {
+  BatchTable gemm, red, sum;
+};
 
 // Jobs of one group must share key, threads and shmem.
 bool stage_ttm_group(const TtmJob* const* jobs, int n, Staging& st, TtmGroup* g);
 bool stage_core_group(const CoreJob* const* jobs, int n, Staging& st, CoreGroup* g);
 bool stage_orth_group(const OrthJob* const* jobs, int n, Staging& st, OrthGroup* g);
+bool stage_ycore_group(const YCoreJob* const* jobs, int n, Staging& st, YCoreGroup* g);
 hoqri_status launch_ttm_group(const TtmGroup& g, hipStream_t s);
 hoqri_status launch_core_group(const CoreGroup& g, hipStream_t s);
 hoqri_status launch_orth_group(const OrthGroup& g, hipStream_t s);
+hoqri_status launch_ycore_group(const YCoreGroup& g, hipStream_t s);
 
 }  // namespace hoqri

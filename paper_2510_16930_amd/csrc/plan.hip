@@ -466,6 +466,38 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     }
   }
   L->core_groups = groups;
+  // stored slice rows: every mode's TTMcTC pass keeps Y_(n) (rows bounded by
+  // min(I_n, nnz)) when every mode's tiles fit the pass kernels
+  size_t ybuf_f = 0, ycarry_f = 0, gpart_f = (size_t)groups * gpart;
+  if (L->core_rows) {
+    const size_t row = gpart / (16 * ((K[L->core_mode] + 15) / 16));  // B_c * 256
+    ybuf_f = (size_t)L->ybuf_rows * row;
+    ycarry_f = (size_t)L->core_w * 2 * row;
+  }
+  L->yfuse = 1;
+  {
+    size_t yrows = 0, yrow = 0, ygp = 0;
+    for (int n = 0; n < N; ++n) {
+      int om[kMaxOrder];
+      const int no = other_modes(N, n, om);
+      int64_t krow = 1;
+      for (int q = 0; q < no - 1; ++q) krow *= K[om[q]];
+      const int64_t Bn = ((krow + 15) / 16) * ((K[om[no - 1]] + 15) / 16);
+      if (Bn > 8 || K[n] > 32) L->yfuse = 0;
+      const size_t rows = (size_t)(dims[n] < nnz ? dims[n] : nnz);
+      yrows = std::max(yrows, rows);
+      yrow = std::max(yrow, (size_t)Bn * 256);
+      ygp = std::max(ygp, (size_t)kYChunks * Bn * 16 * ((K[n] + 15) / 16) * 256);
+    }
+    if (L->yfuse) {
+      ybuf_f = std::max(ybuf_f, yrows * yrow);
+      ycarry_f = std::max(ycarry_f, (size_t)std::max<int32_t>(rmax, L->core_w) * 2 * yrow);
+      gpart_f = std::max(gpart_f, ygp);
+    }
+  }
+  L->ybuf_floats = ybuf_f;
+  L->ycarry_floats = ycarry_f;
+  L->gpart_floats = gpart_f;
   int64_t IKsum = 0;
   for (int n = 0; n < N; ++n) IKsum += dims[n] * K[n];
   Carver r{nullptr, 0};
@@ -473,7 +505,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   for (int n = 0; n < N; ++n) r.take<uint16_t>(dims[n] * K[n]);  // their 16-bit copies
   r.take<float>(IKmax);                 // A
   r.take<float>(PK);                    // G
-  r.take<float>((size_t)groups * gpart);// core partials
+  r.take<float>(gpart_f);               // core partials
   r.take<double>(4096);                 // fpart
   r.take<float>(gtop_max);              // stage-two operand
   r.take<float>((size_t)rmax * 2 * 32); // carries
@@ -484,12 +516,9 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   r.take<double>(64);                   // scalars
   r.take<double>(kMaxSweeps + 1);       // f after each sweep
   r.take<double>(kMaxRank * kMaxRank + kGradParts + (size_t)kMaxSweeps * kMaxOrder);  // gradient monitor
-  if (L->core_rows) {
-    const int64_t row = (int64_t)(gpart / (16 * ((K[L->core_mode] + 15) / 16)));  // B_c * 256
-    r.take<float>((size_t)(L->ybuf_rows * row));             // slice rows
-    r.take<float>((size_t)L->core_w * 2 * row);               // split-slice partials
-    r.take<int32_t>((size_t)L->core_w * 4);                   // their metadata
-  }
+  r.take<float>(ybuf_f);                // slice rows
+  r.take<float>(ycarry_f);              // split-slice partials
+  r.take<int32_t>((size_t)L->core_w * 4);  // core-pass range metadata
   size_t run = r.off;
   L->persistent = persistent;
   L->build_tmp = build;
@@ -683,6 +712,7 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
   p->core_rows = L.core_rows;
   p->ybuf_rows = L.ybuf_rows;
   p->core_w = L.core_w;
+  p->yfuse = L.yfuse;
   return HOQRI_OK;
 }
 
@@ -693,19 +723,11 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
     if (p->dims[n] > Imax) Imax = p->dims[n];
     PK *= p->K[n];
   }
-  size_t gtop_max = 0, gpart = 0;
+  size_t gtop_max = 0;
   for (int n = 0; n < p->N; ++n) {
     size_t g1, g2;
     pass_sizes(p->N, p->K, n, &g1, &g2);
     if (g1 > gtop_max) gtop_max = g1;
-    if (g2 > gpart) gpart = g2;
-  }
-  size_t row = 0;  // B_c * 256 (row-writing core pass)
-  if (L.core_rows) {
-    size_t g1, g2;
-    pass_sizes(p->N, p->K, L.core_mode, &g1, &g2);
-    gpart = g2;
-    row = g2 / (16 * ((p->K[L.core_mode] + 15) / 16));
   }
   int32_t rmax = 0;
   for (int n = 0; n < p->N; ++n)
@@ -715,7 +737,7 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
   for (int n = 0; n < p->N; ++n) p->sc.Uh[n] = r.take<uint16_t>(p->dims[n] * p->K[n]);
   p->sc.A = r.take<float>(IKmax);
   p->sc.G = r.take<float>(PK);
-  p->sc.gpart = r.take<float>((size_t)L.core_groups * gpart);
+  p->sc.gpart = r.take<float>(L.gpart_floats);
   p->sc.fpart = r.take<double>(4096);
   p->sc.gtop = r.take<float>(gtop_max);
   p->sc.carry = r.take<float>((size_t)rmax * 2 * 32);
@@ -727,13 +749,9 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
   p->sc.f_dev = r.take<double>(64);
   p->sc.fsweep = r.take<double>(kMaxSweeps + 1);
   p->sc.gscr = r.take<double>(kMaxRank * kMaxRank + kGradParts + (size_t)kMaxSweeps * kMaxOrder);
-  p->sc.ybuf = p->sc.ycarry = nullptr;
-  p->sc.ymeta = nullptr;
-  if (L.core_rows) {
-    p->sc.ybuf = r.take<float>((size_t)(L.ybuf_rows * row));
-    p->sc.ycarry = r.take<float>((size_t)L.core_w * 2 * row);
-    p->sc.ymeta = r.take<int32_t>((size_t)L.core_w * 4);
-  }
+  p->sc.ybuf = r.take<float>(L.ybuf_floats);
+  p->sc.ycarry = r.take<float>(L.ycarry_floats);
+  p->sc.ymeta = r.take<int32_t>((size_t)L.core_w * 4);
 }
 
 extern "C" hoqri_status hoqri_plan_create(hoqri_plan** plan, int32_t order, const int64_t* dims,

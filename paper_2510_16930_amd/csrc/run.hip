@@ -314,13 +314,17 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   if (!(opts->grad_tol >= 0.0)) return HOQRI_ERR_ARG;
   const bool grad_on = opts->d_grad_hist != nullptr || opts->grad_tol > 0.0;
   double* ghist = p->sc.gscr + kMaxRank * kMaxRank + kGradParts;  // [kMaxSweeps][N]
+  // With stored rows, the pass of mode n keeps Y_(n) (which does not involve
+  // U^(n)), and the core of the updated factors is U^(n)T Y_(n): no separate
+  // core pass between mode updates.
+  const bool fuse = p->yfuse != 0;
   for (int t = 0; t < opts->max_sweeps; ++t) {
     for (int n = 0; n < N; ++n) {
-      if (n > 0) {
+      if (n > 0 && !fuse) {
         double* fdst = d_f_hist ? d_f_hist + (size_t)t * N + n : p->sc.f_dev;
         HOQRI_TRY(launch_core(p, ops, d_G_out, fdst, stream));
       }
-      HOQRI_TRY(launch_ttmctc(p, n, ops, d_G_out, p->sc.A, nullptr, stream));
+      HOQRI_TRY(launch_ttmctc(p, n, ops, d_G_out, p->sc.A, nullptr, stream, fuse));
       // Riemannian gradient at the current point, before U^(n) moves (A rows of
       // empty slices are zero, all I_n rows of U take part)
       if (grad_on) HOQRI_TRY(launch_grad(p, n, p->sc.A, Up[n], d_G_out, ghist + (size_t)t * N + n, stream));
@@ -332,8 +336,13 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       HOQRI_TRY(launch_orth(Rn, p->K[n], p->sc.A, Up[n], nullptr, status, p->sc.orth_ws, p->sc.orth_ws_bytes,
                             stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n]));
       HOQRI_TRY(refresh16(p, op, n, stream));
+      if (fuse) {
+        // f after mode n: the next mode's starting point, or the sweep's end
+        double* fdst = n + 1 < N ? (d_f_hist ? d_f_hist + (size_t)t * N + n + 1 : p->sc.f_dev) : fsw + t + 1;
+        HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream));
+      }
     }
-    HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + t + 1, stream));
+    if (!fuse) HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + t + 1, stream));
     T = t + 1;
     if (T % opts->check_every == 0 || T == opts->max_sweeps) {
       double fv[2];

@@ -459,6 +459,28 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
         }
       }
     }
+    if (a.yrow) {
+      // keep the staged y_s for the core of the updated factor: row by label
+      // (slot_row: out_map is null here); a split slice leaves its partial per
+      // range and zeros in its own row
+      // (buffer stores: row bases in scalar registers, no per-lane 64-bit addresses)
+      const size_t yrowf = (size_t)a.B * 256;
+      const uint32_t vo = (uint32_t)(b * 256 + 4 * lane) * 4u;
+      for (int sl = 0; sl < slot; ++sl) {
+        const int32_t row = __builtin_amdgcn_readfirstlane(slot_row[sl]);
+        const int kind = __builtin_amdgcn_readfirstlane(slot_kind[sl]);
+        const i4 yv = __builtin_bit_cast(i4, *reinterpret_cast<const f4*>(ybat + sl * YS + 4 * lane));
+        const auto own = make_rsrc(a.yrow + (size_t)row * yrowf, (uint32_t)(yrowf * 4));
+        if (kind == KIND_COMPLETE) {
+          __builtin_amdgcn_raw_buffer_store_b128(yv, own, vo, 0, 0);
+        } else {
+          const auto dst = make_rsrc(a.ycarry + ((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * yrowf,
+                                     (uint32_t)(yrowf * 4));
+          __builtin_amdgcn_raw_buffer_store_b128(yv, dst, vo, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(i4{0, 0, 0, 0}, own, vo, 0, 0);
+        }
+      }
+    }
     if (multi) __syncthreads();
     else wave_sync();
     slot = 0;
@@ -482,6 +504,17 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
 template <int NM1, int KN2, int PREC>
 __global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
   ttm_body<NM1, KN2, PREC>(a, blockIdx.x);
+}
+
+// The same pass held to 128 registers (four waves per SIMD) for the instance
+// whose allocation lands just above that without spilling when held to it
+template <int NM1, int KN2, int PREC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_ttm_w4(SegArgs a) {
+  ttm_body<NM1, KN2, PREC>(a, blockIdx.x);
+}
+template <int NM1, int KN2, int PREC>
+constexpr bool ttm_hold4() {
+  return NM1 == 2 && KN2 == 1 && PREC == P_FP32;
 }
 
 template <int NM1, int KN2, int PREC>
@@ -655,18 +688,27 @@ __global__ __launch_bounds__(512) void k_core_rows_b(const SegArgs* d, const int
   core_rows_body<NM1, KN2, PREC>(d[r], blockIdx.x - first[r]);
 }
 
-// One block per (chunk of kCoreChunk rows, y-tile b); thread t owns column j'
-// = t of tile b and every kc: fixed summation order over the chunk's rows.
+// One block per (chunk of p.chunk rows, y-tile b): the partial product
+// U^T Y over the chunk's rows on the matrix cores, 4 rows per product. Wave w
+// owns columns j' = 64w .. 64w+63 of tile b: lane (g, q) loads entries
+// 64w + 4q .. 4q+3 of row 4s+g as one vector, and product c of a step takes
+// component c, so its output column q stands for j' = 64w + 4q + c. Rows are
+// added in a fixed order (steps of 4 rows, in row order).
 __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   const int chunk = blk / p.B, b = blk - chunk * p.B;
-  const int t = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, q = lane & 15;
   const size_t row = (size_t)p.B * 256;
-  float acc[32];
+  const int KT = p.KC >> 4;  // 1 or 2 tiles of kc
+  f4 acc[2][4];
 #pragma unroll
-  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
-  const int64_t v0 = (int64_t)chunk * kCoreChunk;
+  for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[kt][c] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t v0 = (int64_t)chunk * p.chunk;
   const int64_t nv = (int64_t)p.R + 2 * (int64_t)p.W;
-  const int64_t v1 = v0 + kCoreChunk < nv ? v0 + kCoreChunk : nv;
+  const int64_t v1 = v0 + p.chunk < nv ? v0 + p.chunk : nv;
+  const int col = b * 256 + 64 * wv + 4 * q;
   // row v of the product: its source row and the label of its slice (-1: none)
   auto source = [&](int64_t v, const float** src) -> int32_t {
     if (v >= v1) return -1;
@@ -683,29 +725,44 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
     *src = p.ycarry + ((size_t)w * 2 + kind) * row;
     return p.seg_row[kind == 0 ? sf : sl];
   };
-  for (int64_t v = v0; v < v1; v += 4) {
-    // four rows at a time (loads in flight together), added in row order
-    const float* src[4] = {p.ybuf, p.ybuf, p.ybuf, p.ybuf};
-    int32_t lab[4];
-    float y[4];
+  constexpr int NS = 4;  // steps of 4 rows in flight
+  for (int64_t v = v0; v < v1; v += 4 * NS) {
+    f4 yv[NS];
+    float ua[NS][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      lab[i] = __builtin_amdgcn_readfirstlane(source(v + i, &src[i]));
-      y[i] = lab[i] >= 0 ? src[i][b * 256 + t] : 0.f;
+    for (int st = 0; st < NS; ++st) {
+      const float* src = p.ybuf;
+      const int32_t lab = source(v + 4 * st + g, &src);
+      yv[st] = lab >= 0 ? *reinterpret_cast<const f4*>(src + col) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        const int k = 16 * kt + q;
+        ua[st][kt] = (lab >= 0 && kt < KT && k < p.Kc) ? p.Uc[(size_t)lab * p.Kc + k] : 0.f;
+      }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (lab[i] < 0) continue;
-      const float* u = p.Uc + (size_t)lab[i] * p.Kc;
+    for (int st = 0; st < NS; ++st)
 #pragma unroll
-      for (int k = 0; k < 32; ++k)
-        if (k < p.Kc) acc[k] += u[k] * y[i];
-    }
+      for (int kt = 0; kt < 2; ++kt) {
+        if (kt >= KT) continue;
+        acc[kt][0] = mfma4(ua[st][kt], yv[st].x, acc[kt][0]);
+        acc[kt][1] = mfma4(ua[st][kt], yv[st].y, acc[kt][1]);
+        acc[kt][2] = mfma4(ua[st][kt], yv[st].z, acc[kt][2]);
+        acc[kt][3] = mfma4(ua[st][kt], yv[st].w, acc[kt][3]);
+      }
   }
+  // lane (g, q) holds D[kc = 16 kt + 4g + r][j' = 64 wv + 4q + c] in acc[kt][c][r]
   float* out = p.gpart + ((size_t)chunk * p.B + b) * p.KC * 256;
 #pragma unroll
-  for (int k = 0; k < 32; ++k)
-    if (k < p.KC) out[(size_t)k * 256 + t] = acc[k];
+  for (int kt = 0; kt < 2; ++kt) {
+    if (kt >= KT) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kc = 16 * kt + 4 * g + r;
+      *reinterpret_cast<f4*>(out + (size_t)kc * 256 + 64 * wv + 4 * q) =
+          f4{acc[kt][0][r], acc[kt][1][r], acc[kt][2][r], acc[kt][3][r]};
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_core_gemm(CoreGemmArgs p) { core_gemm_body(p, blockIdx.x); }
@@ -779,53 +836,62 @@ __global__ __launch_bounds__(512) void k_core_b(const SegArgs* d, const int32_t*
 
 // Sums the workgroup partials in order (float64), scatters into G (C order),
 // and leaves per-block partial sums of squares for ||G||^2.
+// 16 outputs per block of 1024 threads: thread (phase ph, output o) sums the
+// partials of groups ph, ph + 64, ... in float64; the 64 phase sums are then
+// added by a fixed tree. Output e = ((b * 16 KN2) + kc) * 256 + j' is scattered
+// into the C-order core; the block's sum of squares goes to fpart[blk].
+constexpr int kRedOut = 16;
+constexpr int kRedThreads = 1024;
 __device__ inline void red_body(const CoreRedArgs& p, const int blk) {
-  __shared__ double sh[256];
+  __shared__ double sh[kRedThreads];
   const int total = p.B * 16 * p.KN2 * 256;
-  const int e = blk * 64 + (threadIdx.x & 63);
-  const int sp = threadIdx.x >> 6;
+  const int o = threadIdx.x % kRedOut, ph = threadIdx.x / kRedOut;
+  constexpr int NPH = kRedThreads / kRedOut;
+  const int e = blk * kRedOut + o;
   double acc = 0.0;
   if (e < total)
-    for (int gi = sp; gi < p.groups; gi += 4) acc += (double)p.gpart[(size_t)gi * total + e];
+    for (int gi = ph; gi < p.groups; gi += NPH) acc += (double)p.gpart[(size_t)gi * total + e];
   sh[threadIdx.x] = acc;
   __syncthreads();
+  for (int st = NPH / 2; st > 0; st >>= 1) {
+    if (ph < st) sh[threadIdx.x] += sh[threadIdx.x + st * kRedOut];
+    __syncthreads();
+  }
   double sq = 0.0;
-  if (threadIdx.x < 64) {
-    double v = sh[threadIdx.x] + sh[threadIdx.x + 64] + sh[threadIdx.x + 128] + sh[threadIdx.x + 192];
-    if (e < total) {
-      // e = ((b * 16 KN2) + kc) * 256 + j', j' = c*16 + r within block b
-      const int jp = e & 255;
-      const int kc = (e >> 8) % (16 * p.KN2);
-      const int b = (e >> 8) / (16 * p.KN2);
-      const int rb = b / p.CB, cb = b % p.CB;
-      const int rg = 16 * rb + (jp & 15), cg = 16 * cb + (jp >> 4);
-      if (rg < p.krow && cg < p.kcol && kc < p.Kc) {
-        int64_t flat = (int64_t)rg * p.kcol + cg;
-        int64_t off = (int64_t)kc * p.gstride[p.mode];
-        for (int m = p.nm1 - 1; m >= 0; --m) {
-          const int64_t k = flat % p.Ko[m];
-          flat /= p.Ko[m];
-          off += k * p.gstride[p.om[m]];
-        }
-        const float vf = (float)v;
-        p.G[off] = vf;
-        sq = (double)vf * (double)vf;
+  if (threadIdx.x < kRedOut && e < total) {
+    const double v = sh[threadIdx.x];
+    // e = ((b * 16 KN2) + kc) * 256 + j', j' = c*16 + r within block b
+    const int jp = e & 255;
+    const int kc = (e >> 8) % (16 * p.KN2);
+    const int b = (e >> 8) / (16 * p.KN2);
+    const int rb = b / p.CB, cb = b % p.CB;
+    const int rg = 16 * rb + (jp & 15), cg = 16 * cb + (jp >> 4);
+    if (rg < p.krow && cg < p.kcol && kc < p.Kc) {
+      int64_t flat = (int64_t)rg * p.kcol + cg;
+      int64_t off = (int64_t)kc * p.gstride[p.mode];
+      for (int m = p.nm1 - 1; m >= 0; --m) {
+        const int64_t k = flat % p.Ko[m];
+        flat /= p.Ko[m];
+        off += k * p.gstride[p.om[m]];
       }
+      const float vf = (float)v;
+      p.G[off] = vf;
+      sq = (double)vf * (double)vf;
     }
   }
   __syncthreads();
-  sh[threadIdx.x] = sq;
+  if (threadIdx.x < kRedOut) sh[threadIdx.x] = sq;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kRedOut; ++i) t += sh[i];
+    p.fpart[blk] = t;
   }
-  if (threadIdx.x == 0) p.fpart[blk] = sh[0];
 }
 
-__global__ void k_core_reduce(CoreRedArgs p) { red_body(p, blockIdx.x); }
+__global__ __launch_bounds__(1024) void k_core_reduce(CoreRedArgs p) { red_body(p, blockIdx.x); }
 
-__global__ void k_core_reduce_b(const CoreRedArgs* d, const int32_t* first, int count) {
+__global__ __launch_bounds__(1024) void k_core_reduce_b(const CoreRedArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
   red_body(d[r], blockIdx.x - first[r]);
 }
@@ -908,7 +974,10 @@ struct SegKernels {
 
 template <int NM1, int KN2, int PREC>
 SegKernels seg_kernels_t() {
-  return SegKernels{(const void*)k_ttm<NM1, KN2, PREC>,       (const void*)k_ttm_b<NM1, KN2, PREC>,
+  const void* ttm;
+  if constexpr (ttm_hold4<NM1, KN2, PREC>()) ttm = (const void*)k_ttm_w4<NM1, KN2, PREC>;
+  else ttm = (const void*)k_ttm<NM1, KN2, PREC>;
+  return SegKernels{ttm,                                      (const void*)k_ttm_b<NM1, KN2, PREC>,
                     (const void*)k_core<NM1, KN2, PREC>,      (const void*)k_core_b<NM1, KN2, PREC>,
                     (const void*)k_core_rows<NM1, KN2, PREC>, (const void*)k_core_rows_b<NM1, KN2, PREC>};
 }
@@ -992,8 +1061,9 @@ hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh
 }
 
 hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
-                         const int32_t* out_map, TtmJob* job) {
+                         const int32_t* out_map, TtmJob* job, bool rows) {
   if (!segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
+  if (rows && (!p->yfuse || out_map)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
   const ModeData& md = p->md[mode];
@@ -1033,6 +1103,8 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   a.carry = p->sc.carry;
   a.meta = p->sc.meta;
   a.out_map = out_map;
+  a.yrow = rows ? p->sc.ybuf : nullptr;
+  a.ycarry = rows ? p->sc.ycarry : nullptr;
   job->threads = 64 * g.B * a.RPW;
   job->shmem = (size_t)ttm_lds_floats(a, KN2) * 4;
   job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
@@ -1085,6 +1157,7 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
     m.R = (int32_t)p->md[mode].R;
     m.W = a.W;
     m.B = g.B;
+    m.chunk = kCoreChunk;
     m.gpart = p->sc.gpart;
     const int64_t chunks = ((int64_t)m.R + 2 * (int64_t)m.W + kCoreChunk - 1) / kCoreChunk;
     job->gemm_blocks = (int)(chunks * g.B);
@@ -1107,7 +1180,7 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
     r.G = G;
     r.fpart = p->sc.fpart;
     const int total = g.B * 16 * KN2 * 256;
-    job->red_blocks = (total + 63) / 64;
+    job->red_blocks = (total + kRedOut - 1) / kRedOut;
     job->sum.part = p->sc.fpart;
     job->sum.n = job->red_blocks;
     job->sum.out = f_out ? f_out : p->sc.f_dev;
@@ -1153,7 +1226,7 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
   r.G = G;
   r.fpart = p->sc.fpart;
   const int total = g.B * 16 * KN2 * 256;
-  job->red_blocks = (total + 63) / 64;
+  job->red_blocks = (total + kRedOut - 1) / kRedOut;
   job->sum.part = p->sc.fpart;
   job->sum.n = job->red_blocks;
   job->sum.out = f_out ? f_out : p->sc.f_dev;
@@ -1163,9 +1236,9 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
 }
 
 hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
-                           const int32_t* out_map, hipStream_t s) {
+                           const int32_t* out_map, hipStream_t s, bool rows) {
   TtmJob job;
-  HOQRI_TRY(prepare_ttm(p, mode, op, G, A, out_map, &job));
+  HOQRI_TRY(prepare_ttm(p, mode, op, G, A, out_map, &job, rows));
   SegKernels k;
   seg_kernels(job.key, &k);
   {
@@ -1205,7 +1278,74 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
     HOQRI_HIP_TRY(hipLaunchKernel(kern, dim3(job.seg_blocks), dim3(job.threads), args, job.shmem, s));
   }
   if (job.key >= 1000) hipLaunchKernelGGL(k_core_gemm, dim3(job.gemm_blocks), dim3(256), 0, s, job.gemm);
-  hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(256), 0, s, job.red);
+  hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
+  hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+// Core from the rows Y_(mode) that the last TTMcTC pass of `mode` stored and
+// the updated factor U^(mode): G_(mode) = U^(mode)T Y_(mode). The rows (nonempty
+// slices, then the split-slice partials) are cut into at most kYChunks chunks
+// of equal length; partials are reduced in chunk order.
+hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job) {
+  if (!p->yfuse || !segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
+  const PassGeom g = geom(p, mode);
+  const int KN2 = (p->K[mode] + 15) / 16;
+  *job = YCoreJob{};
+  int64_t W = p->md[mode].ranges;
+  if (W > p->nnz) W = p->nnz;
+  CoreGemmArgs& m = job->gemm;
+  m.ybuf = p->sc.ybuf;
+  m.ycarry = p->sc.ycarry;
+  m.ymeta = p->sc.meta;
+  m.seg_row = p->md[mode].seg_row;
+  m.Uc = p->sc.Up[mode];
+  m.Kc = p->K[mode];
+  m.KC = 16 * KN2;
+  m.R = (int32_t)p->md[mode].R;
+  m.W = (int32_t)W;
+  m.B = g.B;
+  const int64_t nv = (int64_t)m.R + 2 * W;
+  int64_t chunk = (nv + kYChunks - 1) / kYChunks;
+  chunk = (chunk + 15) / 16 * 16;
+  if (chunk < kCoreChunk) chunk = kCoreChunk;
+  m.chunk = (int32_t)chunk;
+  m.gpart = p->sc.gpart;
+  const int64_t chunks = (nv + chunk - 1) / chunk;
+  job->gemm_blocks = (int)(chunks * g.B);
+  CoreRedArgs& r = job->red;
+  r.gpart = p->sc.gpart;
+  r.groups = (int32_t)chunks;
+  r.B = g.B;
+  r.CB = g.CB;
+  r.KN2 = KN2;
+  r.krow = g.krow;
+  r.kcol = g.kcol;
+  r.Kc = p->K[mode];
+  r.mode = mode;
+  r.nm1 = g.nm1;
+  for (int c = 0; c < 3; ++c) {
+    r.om[c] = c < g.nm1 ? g.om[c] : 0;
+    r.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
+  }
+  g_strides(p, r.gstride);
+  r.G = G;
+  r.fpart = p->sc.fpart;
+  const int total = g.B * 16 * KN2 * 256;
+  job->red_blocks = (total + kRedOut - 1) / kRedOut;
+  job->sum.part = p->sc.fpart;
+  job->sum.n = job->red_blocks;
+  job->sum.out = f_out ? f_out : p->sc.f_dev;
+  return HOQRI_OK;
+}
+
+hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s) {
+  YCoreJob job;
+  HOQRI_TRY(prepare_ycore(p, mode, G, f_out, &job));
+  TimerScope ts(p, HOQRI_KERNEL_CORE, s);
+  hipLaunchKernelGGL(k_core_gemm, dim3(job.gemm_blocks), dim3(256), 0, s, job.gemm);
+  hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
@@ -1261,6 +1401,35 @@ bool stage_core_group(const CoreJob* const* jobs, int n, Staging& st, CoreGroup*
          stage_table(st, red.data(), nb_red.data(), n, &g->red) && stage_table(st, sum.data(), ones.data(), n, &g->sum);
 }
 
+bool stage_ycore_group(const YCoreJob* const* jobs, int n, Staging& st, YCoreGroup* g) {
+  if (n < 1 || n > 1024) return false;
+  std::vector<CoreGemmArgs> gemm(n);
+  std::vector<CoreRedArgs> red(n);
+  std::vector<SumArgs> sum(n);
+  std::vector<int32_t> nb_gemm(n), nb_red(n), ones(n);
+  for (int i = 0; i < n; ++i) {
+    gemm[i] = jobs[i]->gemm;
+    red[i] = jobs[i]->red;
+    sum[i] = jobs[i]->sum;
+    nb_gemm[i] = jobs[i]->gemm_blocks;
+    nb_red[i] = jobs[i]->red_blocks;
+    ones[i] = 1;
+  }
+  return stage_table(st, gemm.data(), nb_gemm.data(), n, &g->gemm) &&
+         stage_table(st, red.data(), nb_red.data(), n, &g->red) && stage_table(st, sum.data(), ones.data(), n, &g->sum);
+}
+
+hoqri_status launch_ycore_group(const YCoreGroup& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(256), 0, s, (const CoreGemmArgs*)g.gemm.descs,
+                     g.gemm.first, g.gemm.count);
+  hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(kRedThreads), 0, s, (const CoreRedArgs*)g.red.descs,
+                     g.red.first, g.red.count);
+  hipLaunchKernelGGL(k_sum_f_b, dim3(g.sum.blocks), dim3(256), 0, s, (const SumArgs*)g.sum.descs, g.sum.first,
+                     g.sum.count);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
 hoqri_status launch_ttm_group(const TtmGroup& g, hipStream_t s) {
   SegKernels k;
   if (!seg_kernels(g.key, &k)) return HOQRI_ERR_UNSUPPORTED;
@@ -1291,7 +1460,7 @@ hoqri_status launch_core_group(const CoreGroup& g, hipStream_t s) {
   if (g.key >= 1000)
     hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(256), 0, s, (const CoreGemmArgs*)g.gemm.descs,
                        g.gemm.first, g.gemm.count);
-  hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(256), 0, s, (const CoreRedArgs*)g.red.descs,
+  hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(kRedThreads), 0, s, (const CoreRedArgs*)g.red.descs,
                      g.red.first, g.red.count);
   hipLaunchKernelGGL(k_sum_f_b, dim3(g.sum.blocks), dim3(256), 0, s, (const SumArgs*)g.sum.descs, g.sum.first,
                      g.sum.count);

@@ -115,6 +115,7 @@ struct Active {
   size_t off;
   int slot;
   int t, n;          // sweeps done, current mode
+  bool fresh;        // the core of the starting factors is still to be formed
   double f_prev;     // f at the start of the current sweep
   double rel;
   int64_t admitted;
@@ -227,7 +228,7 @@ void builder_loop(hoqri_server* S) {
                                         q.r.d_vals, S->base + off, q.need, bs);
     if (st == HOQRI_OK)
       for (int n = 0; n < plan->N; ++n) {
-        if (!segpass_supported(plan, n)) st = HOQRI_ERR_UNSUPPORTED;
+        if (!segpass_supported(plan, n) || !plan->yfuse) st = HOQRI_ERR_UNSUPPORTED;
         else if (plan->md[n].R < plan->K[n]) st = HOQRI_ERR_BREAKDOWN;  // fewer nonempty slices than K_n
       }
     lk.lock();
@@ -271,6 +272,7 @@ hoqri_status admit(hoqri_server* S, hipStream_t s) {
     a.slot = S->free_slots.back();
     S->free_slots.pop_back();
     a.admitted = S->step_no;
+    a.fresh = true;
     HOQRI_TRY(to_labels(a.plan, a.q.U.data(), s));
     HOQRI_TRY(fill_i32(S->d_stat + a.slot, 1, 0, s));
     HOQRI_TRY(fill_i32(S->d_skip + a.slot, 1, 0, s));
@@ -425,13 +427,17 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
   HOQRI_TRY(admit(S, s));
   std::vector<Active>& act = S->active;
   if (!act.empty()) {
-    // 1. cores of every admitted request (f into its slot)
-    std::vector<CoreJob> cj(act.size());
-    for (size_t i = 0; i < act.size(); ++i) {
-      Operands op{OP_FP32, act[i].plan->sc.Up, act[i].plan->sc.Uh};
-      HOQRI_TRY(prepare_core(act[i].plan, op, act[i].plan->sc.G, S->d_f + act[i].slot, &cj[i]));
+    // 1. cores of the starting factors of newly admitted requests (f into
+    // their slots); the others' cores came from their last mode update
+    std::vector<CoreJob> cj;
+    for (Active& a : act) {
+      if (!a.fresh) continue;
+      Operands op{OP_FP32, a.plan->sc.Up, a.plan->sc.Uh};
+      cj.emplace_back();
+      HOQRI_TRY(prepare_core(a.plan, op, a.plan->sc.G, S->d_f + a.slot, &cj.back()));
+      a.fresh = false;
     }
-    HOQRI_TRY((run_groups<CoreJob, CoreGroup>(cj, st, s, stage_core_group, launch_core_group)));
+    if (!cj.empty()) HOQRI_TRY((run_groups<CoreJob, CoreGroup>(cj, st, s, stage_core_group, launch_core_group)));
     const int slots = S->o.max_slots;
     HOQRI_HIP_TRY(hipMemcpyAsync(S->h_f, S->d_f, (size_t)slots * 8, hipMemcpyDeviceToHost, s));
     HOQRI_HIP_TRY(hipMemcpyAsync(S->h_stat, S->d_stat, (size_t)slots * 4, hipMemcpyDeviceToHost, s));
@@ -465,26 +471,34 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
       going.push_back((int)i);
     }
 
-    // 3. TTMcTC and orthonormalisation of the continuing requests
+    // 3. TTMcTC (storing Y_(n)), orthonormalisation and the core of the
+    // updated factors (f into the slot) for the continuing requests
     if (!going.empty()) {
       std::vector<TtmJob> tj(going.size());
       std::vector<OrthJob> oj(going.size());
+      std::vector<YCoreJob> yj(going.size());
       for (size_t k = 0; k < going.size(); ++k) {
         Active& a = act[going[k]];
         hoqri_plan* p = a.plan;
         Operands op{OP_FP32, p->sc.Up, p->sc.Uh};
-        HOQRI_TRY(prepare_ttm(p, a.n, op, p->sc.G, p->sc.A, nullptr, &tj[k]));
+        HOQRI_TRY(prepare_ttm(p, a.n, op, p->sc.G, p->sc.A, nullptr, &tj[k], true));
         HOQRI_TRY(prepare_orth(p->md[a.n].R, p->K[a.n], p->sc.A, p->sc.Up[a.n], nullptr, S->d_stat + a.slot,
                                p->sc.orth_ws, p->sc.orth_ws_bytes, true, &oj[k],
                                S->o.keep_on_breakdown ? S->d_skip + a.slot : nullptr, p->dims[a.n]));
+        HOQRI_TRY(prepare_ycore(p, a.n, p->sc.G, S->d_f + a.slot, &yj[k]));
       }
       HOQRI_TRY((run_groups<TtmJob, TtmGroup>(tj, st, s, stage_ttm_group, launch_ttm_group)));
       std::vector<const OrthJob*> op(oj.size());
       for (size_t k = 0; k < oj.size(); ++k) op[k] = &oj[k];
       OrthGroup og;
       if (!stage_orth_group(op.data(), (int)op.size(), st, &og)) return HOQRI_ERR_NOMEM;
+      std::vector<const YCoreJob*> yp(yj.size());
+      for (size_t k = 0; k < yj.size(); ++k) yp[k] = &yj[k];
+      YCoreGroup yg;
+      if (!stage_ycore_group(yp.data(), (int)yp.size(), st, &yg)) return HOQRI_ERR_NOMEM;
       HOQRI_HIP_TRY(st.upload(s));
       HOQRI_TRY(launch_orth_group(og, s));
+      HOQRI_TRY(launch_ycore_group(yg, s));
       for (int i : going) {
         Active& a = act[i];
         if (++a.n == a.plan->N) {
