@@ -26,9 +26,9 @@ constexpr int kChunk = 32;    // rows staged per step
 constexpr double kBreakRel = 1e-13;
 
 int gram_blocks(int64_t rows) {
-  int64_t nb = (rows + 1023) / 1024;
+  int64_t nb = (rows + 255) / 256;
   if (nb < 1) nb = 1;
-  if (nb > 1024) nb = 1024;
+  if (nb > 4096) nb = 4096;
   return (int)nb;
 }
 
@@ -55,17 +55,32 @@ __device__ inline void gram_body(const GramArgs& g, const int blk) {
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb) D[pb][qb] = d4{0.0, 0.0, 0.0, 0.0};
   const bool two = K > 16;
-#pragma unroll 4
-  for (int64_t base = r0 + 4 * wv; base < r1; base += 4 * (kT / 64)) {
-    const int64_t row = base + gg;
-    const bool ok = row < r1;
-    const double a0 = (ok && q < K) ? (double)A[row * K + q] : 0.0;
-    D[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, D[0][0], 0, 0, 0);
-    if (two) {
-      const double a1 = (ok && 16 + q < K) ? (double)A[row * K + 16 + q] : 0.0;
-      D[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, D[0][1], 0, 0, 0);
-      D[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, D[1][0], 0, 0, 0);
-      D[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, D[1][1], 0, 0, 0);
+  // 8 steps of 4 rows per group: the group's loads go to clamped (valid)
+  // addresses and are all issued before its products; rows past r1 and
+  // columns past K are masked afterwards
+  constexpr int NS = 8;
+  const int q0 = q < K ? q : 0, q1 = 16 + q < K ? 16 + q : 0;
+  for (int64_t base = r0 + 4 * wv; base < r1; base += 4 * NS * (kT / 64)) {
+    float x0[NS], x1[NS];
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int64_t row = base + st * 4 * (kT / 64) + gg;
+      const int64_t rr = row < r1 ? row : r0;
+      x0[st] = A[rr * K + q0];
+      x1[st] = A[rr * K + q1];  // (same line as x0; used only when K > 16)
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const bool ok = base + st * 4 * (kT / 64) + gg < r1;
+      const double a0 = (ok && q < K) ? (double)x0[st] : 0.0;
+      D[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, D[0][0], 0, 0, 0);
+      if (two) {
+        const double a1 = (ok && 16 + q < K) ? (double)x1[st] : 0.0;
+        D[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, D[0][1], 0, 0, 0);
+        D[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, D[1][0], 0, 0, 0);
+        D[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, D[1][1], 0, 0, 0);
+      }
     }
   }
   // float64 16x16 result layout: tile (pb, qb) holds entry (16 pb + 4 v + gg,
@@ -235,6 +250,9 @@ __global__ __launch_bounds__(kT) void k_chol_b(const CholArgs* d, const int32_t*
 // U = A M (M upper triangular), rows staged in LDS so U may alias A, then
 // rows [rows, zero_to) of U set to zero. Skipped entirely when this
 // factorisation broke down (*flag != 0): U keeps its previous contents.
+// Thread t takes column c = t mod Kp (Kp = K rounded up to a power of two)
+// and rows t / Kp + j 256 / Kp of each 64-row tile; an entry M(k, c) is read
+// once per tile for all of the thread's rows.
 __device__ inline void apply_body(const ApplyArgs& a, const int blk) {
   __shared__ float tile[64][kMaxRank + 1];
   __shared__ double Ms[kMaxRank][kMaxRank];
@@ -244,17 +262,45 @@ __device__ inline void apply_body(const ApplyArgs& a, const int blk) {
   const double* M = a.M;
   float* U = a.U;
   if (*a.flag != 0) return;
+  int Kp = 1;
+  while (Kp < K) Kp <<= 1;
+  const int c = threadIdx.x % Kp, r0 = threadIdx.x / Kp;
+  const int rstep = kT / Kp;                      // rows between a thread's rows
+  const int nrt = rstep >= 64 ? 1 : 64 / rstep;   // rows per thread per tile (<= 8)
   for (int t = threadIdx.x; t < K * K; t += kT) Ms[t / K][t % K] = M[t];
+  const int64_t last = rows * K - 1;
   for (int64_t base = blk * (int64_t)64; base < rows; base += (int64_t)a.nblk * 64) {
     const int nr = (int)((rows - base) < 64 ? (rows - base) : 64);
+    // the tile's loads (clamped addresses) are all issued before the LDS stores
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t e = base * K + threadIdx.x + i * kT;
+      v[i] = A[e < last ? e : last];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    for (int t = threadIdx.x; t < nr * K; t += kT) tile[t / K][t % K] = A[base * K + t];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int t = threadIdx.x + i * kT;
+      if (t < nr * K) tile[t / K][t % K] = v[i];
+    }
     __syncthreads();
-    for (int t = threadIdx.x; t < nr * K; t += kT) {
-      const int r = t / K, c = t - (t / K) * K;
-      double v = 0.0;
-      for (int k = 0; k <= c; ++k) v += (double)tile[r][k] * Ms[k][c];
-      U[base * K + t] = (float)v;
+    if (c < K && r0 < nr) {
+      double acc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+      for (int k = 0; k <= c; ++k) {
+        const double m = Ms[k][c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < nrt && r0 + j * rstep < nr) acc[j] += (double)tile[r0 + j * rstep][k] * m;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int r = r0 + j * rstep;
+        if (j < nrt && r < nr) U[(base + r) * K + c] = (float)acc[j];
+      }
     }
   }
   // rows [rows, zero_to) of U (rows of empty slices) become zero with the update

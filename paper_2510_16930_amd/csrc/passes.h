@@ -87,7 +87,7 @@ struct CoreGemmArgs {
   const int32_t* seg_row;
   const float* Uc;
   int32_t Kc, KC, R, W, B;
-  int32_t chunk;  // rows per partial
+  int32_t nchunk;  // partials: chunk c takes the 16-row groups c, c + nchunk, ...
   float* gpart;
 };
 

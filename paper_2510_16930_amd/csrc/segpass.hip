@@ -688,88 +688,163 @@ __global__ __launch_bounds__(512) void k_core_rows_b(const SegArgs* d, const int
   core_rows_body<NM1, KN2, PREC>(d[r], blockIdx.x - first[r]);
 }
 
-// One block per (chunk of p.chunk rows, y-tile b): the partial product
-// U^T Y over the chunk's rows on the matrix cores, 4 rows per product. Wave w
-// owns columns j' = 64w .. 64w+63 of tile b: lane (g, q) loads entries
-// 64w + 4q .. 4q+3 of row 4s+g as one vector, and product c of a step takes
-// component c, so its output column q stands for j' = 64w + 4q + c. Rows are
-// added in a fixed order (steps of 4 rows, in row order).
+// One block of 16 waves per (chunk, y-tile b): the partial product U^T Y over
+// the chunk's rows on the matrix cores, 4 rows per product. The rows (the R
+// complete slice rows, then the 2W split-slice partials) are taken in groups
+// of 16; chunk c owns groups c, c + NC, c + 2 NC, ... of each part (NC =
+// p.nchunk), so at any time the blocks read neighbouring groups rather than
+// addresses a chunk length apart. Wave (rl, cq) takes columns
+// j' = 64 cq .. 64 cq + 63 of tile b and every fourth of the chunk's groups,
+// starting at rl: lane (g, q) loads entries 64 cq + 4q .. 4q+3 of row 4s + g
+// of a group as one vector, and product c of a step takes component c, so its
+// output column q stands for j' = 64 cq + 4q + c. The four row lanes' sums are
+// added in order rl = 0, 1, 2, 3 (fixed order throughout).
+constexpr int kGemmThreads = 1024;
+template <int KTT>
 __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
+  constexpr int KTM = KTT == 0 ? 2 : KTT;
+  __shared__ f4 red[3][4][KTM * 4][64];  // row lanes 1..3, column quarter, accumulator, lane
   const int chunk = blk / p.B, b = blk - chunk * p.B;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int cq = wv & 3, rl = wv >> 2;
   const int g = lane >> 4, q = lane & 15;
   const size_t row = (size_t)p.B * 256;
-  const int KT = p.KC >> 4;  // 1 or 2 tiles of kc
-  f4 acc[2][4];
+  const int KT = KTT == 0 ? (p.KC >> 4) : KTT;
+  f4 acc[KTM][4];
 #pragma unroll
-  for (int kt = 0; kt < 2; ++kt)
+  for (int kt = 0; kt < KTM; ++kt)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[kt][c] = f4{0.f, 0.f, 0.f, 0.f};
-  const int64_t v0 = (int64_t)chunk * p.chunk;
-  const int64_t nv = (int64_t)p.R + 2 * (int64_t)p.W;
-  const int64_t v1 = v0 + p.chunk < nv ? v0 + p.chunk : nv;
-  const int col = b * 256 + 64 * wv + 4 * q;
-  // row v of the product: its source row and the label of its slice (-1: none)
-  auto source = [&](int64_t v, const float** src) -> int32_t {
-    if (v >= v1) return -1;
-    if (v < p.R) {
-      *src = p.ybuf + (size_t)v * row;
-      return (int32_t)v;
-    }
-    const int64_t w = (v - p.R) >> 1;
-    const int kind = (int)((v - p.R) & 1);
-    const int32_t sf = p.ymeta[w * 4 + 0], sl = p.ymeta[w * 4 + 1], fl = p.ymeta[w * 4 + 2];
-    const bool head = fl & 1;
-    const bool tail = (fl & 2) && !(sf == sl && head);  // a slice clipped on both sides is a head
-    if (kind == 0 ? !head : !tail) return -1;
-    *src = p.ycarry + ((size_t)w * 2 + kind) * row;
-    return p.seg_row[kind == 0 ? sf : sl];
-  };
-  constexpr int NS = 4;  // steps of 4 rows in flight
-  for (int64_t v = v0; v < v1; v += 4 * NS) {
-    f4 yv[NS];
-    float ua[NS][2];
+  const int64_t NC = p.nchunk;
+  const int64_t R = p.R;
+  const int col = b * 256 + 64 * cq + 4 * q;
+  auto product = [&](const f4* yv, float (*ua)[KTM]) {
 #pragma unroll
-    for (int st = 0; st < NS; ++st) {
-      const float* src = p.ybuf;
-      const int32_t lab = source(v + 4 * st + g, &src);
-      yv[st] = lab >= 0 ? *reinterpret_cast<const f4*>(src + col) : f4{0.f, 0.f, 0.f, 0.f};
+    for (int st = 0; st < 4; ++st)
 #pragma unroll
-      for (int kt = 0; kt < 2; ++kt) {
-        const int k = 16 * kt + q;
-        ua[st][kt] = (lab >= 0 && kt < KT && k < p.Kc) ? p.Uc[(size_t)lab * p.Kc + k] : 0.f;
-      }
-    }
-#pragma unroll
-    for (int st = 0; st < NS; ++st)
-#pragma unroll
-      for (int kt = 0; kt < 2; ++kt) {
+      for (int kt = 0; kt < KTM; ++kt) {
         if (kt >= KT) continue;
         acc[kt][0] = mfma4(ua[st][kt], yv[st].x, acc[kt][0]);
         acc[kt][1] = mfma4(ua[st][kt], yv[st].y, acc[kt][1]);
         acc[kt][2] = mfma4(ua[st][kt], yv[st].z, acc[kt][2]);
         acc[kt][3] = mfma4(ua[st][kt], yv[st].w, acc[kt][3]);
       }
+  };
+  // complete slice rows v < R (label v), groups j = chunk + NC (rl + 4i).
+  // Loads go to clamped (valid) addresses and rows past R are masked only
+  // after the barrier, so a group's loads are in flight together, and the
+  // next group's loads are issued before a group's products.
+  const int64_t NG = (R + 15) / 16;
+  auto load_rows = [&](int64_t j, f4* y, float (*u)[KTM]) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t v = 16 * j + 4 * st + g;
+      const int64_t vv = v < R ? v : 0;
+      y[st] = *reinterpret_cast<const f4*>(p.ybuf + (size_t)vv * row + col);
+#pragma unroll
+      for (int kt = 0; kt < KTM; ++kt) {
+        const int k = 16 * kt + q;
+        u[st][kt] = (kt < KT) ? p.Uc[(size_t)vv * p.Kc + (k < p.Kc ? k : 0)] : 0.f;
+      }
+    }
+  };
+  auto masked_product = [&](int64_t j, f4* y, float (*u)[KTM]) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const bool ok = j < NG && 16 * j + 4 * st + g < R;
+      y[st] = ok ? y[st] : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < KTM; ++kt) u[st][kt] = (ok && 16 * kt + q < p.Kc) ? u[st][kt] : 0.f;
+    }
+    product(y, u);
+  };
+  f4 yv[4], yn[4];
+  float ua[4][KTM], un[4][KTM];
+  const int64_t j0 = chunk + NC * rl, dj = 4 * NC;
+  if (j0 < NG) {
+    load_rows(j0, yv, ua);
+    for (int64_t j = j0; j < NG; j += 2 * dj) {
+      load_rows(j + dj, yn, un);
+      __builtin_amdgcn_sched_barrier(0);
+      masked_product(j, yv, ua);
+      load_rows(j + 2 * dj, yv, ua);
+      __builtin_amdgcn_sched_barrier(0);
+      masked_product(j + dj, yn, un);
+    }
   }
-  // lane (g, q) holds D[kc = 16 kt + 4g + r][j' = 64 wv + 4q + c] in acc[kt][c][r]
+  // split-slice partials v = R + 2w + kind (head 0 / tail 1 of range w), when
+  // valid; groups of 16 of them interleaved over the chunks the same way
+  const int64_t NP = 2 * (int64_t)p.W;
+  for (int64_t j = j0; 16 * j < NP; j += dj) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t x = 16 * j + 4 * st + g;
+      int32_t lab = -1;
+      const float* src = p.ycarry;
+      if (x < NP) {
+        const int64_t w = x >> 1;
+        const int kind = (int)(x & 1);
+        const int32_t sf = p.ymeta[w * 4 + 0], sl = p.ymeta[w * 4 + 1], fl = p.ymeta[w * 4 + 2];
+        const bool head = fl & 1;
+        const bool tail = (fl & 2) && !(sf == sl && head);  // a slice clipped on both sides is a head
+        if (kind == 0 ? head : tail) {
+          src = p.ycarry + ((size_t)w * 2 + kind) * row;
+          lab = p.seg_row[kind == 0 ? sf : sl];
+        }
+      }
+      yv[st] = lab >= 0 ? *reinterpret_cast<const f4*>(src + col) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < KTM; ++kt) {
+        const int k = 16 * kt + q;
+        const bool ok = lab >= 0 && kt < KT && k < p.Kc;
+        ua[st][kt] = ok ? p.Uc[(size_t)lab * p.Kc + k] : 0.f;
+      }
+    }
+    product(yv, ua);
+  }
+  // row lanes 1..3 hand their sums to row lane 0, which adds them in order
+  if (rl > 0) {
+#pragma unroll
+    for (int kt = 0; kt < KTM; ++kt)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[rl - 1][cq][kt * 4 + c][lane] = acc[kt][c];
+  }
+  __syncthreads();
+  if (rl > 0) return;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int kt = 0; kt < KTM; ++kt)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[kt][c] += red[r][cq][kt * 4 + c][lane];
+  // lane (g, q) holds D[kc = 16 kt + 4g + r][j' = 64 cq + 4q + c] in acc[kt][c][r]
   float* out = p.gpart + ((size_t)chunk * p.B + b) * p.KC * 256;
 #pragma unroll
-  for (int kt = 0; kt < 2; ++kt) {
+  for (int kt = 0; kt < KTM; ++kt) {
     if (kt >= KT) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int kc = 16 * kt + 4 * g + r;
-      *reinterpret_cast<f4*>(out + (size_t)kc * 256 + 64 * wv + 4 * q) =
+      *reinterpret_cast<f4*>(out + (size_t)kc * 256 + 64 * cq + 4 * q) =
           f4{acc[kt][0][r], acc[kt][1][r], acc[kt][2][r], acc[kt][3][r]};
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_core_gemm(CoreGemmArgs p) { core_gemm_body(p, blockIdx.x); }
+template <int KTT>
+__global__ __launch_bounds__(kGemmThreads) void k_core_gemm(CoreGemmArgs p) {
+  core_gemm_body<KTT>(p, blockIdx.x);
+}
 
-__global__ __launch_bounds__(256) void k_core_gemm_b(const CoreGemmArgs* d, const int32_t* first, int count) {
+__global__ __launch_bounds__(kGemmThreads) void k_core_gemm_b(const CoreGemmArgs* d, const int32_t* first,
+                                                              int count) {
   const int r = batch_item(first, count, blockIdx.x);
-  core_gemm_body(d[r], blockIdx.x - first[r]);
+  core_gemm_body<0>(d[r], blockIdx.x - first[r]);
+}
+
+void launch_core_gemm(const CoreGemmArgs& m, int blocks, hipStream_t s) {
+  if (m.KC <= 16) hipLaunchKernelGGL(k_core_gemm<1>, dim3(blocks), dim3(kGemmThreads), 0, s, m);
+  else hipLaunchKernelGGL(k_core_gemm<2>, dim3(blocks), dim3(kGemmThreads), 0, s, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,9 +1232,9 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
     m.R = (int32_t)p->md[mode].R;
     m.W = a.W;
     m.B = g.B;
-    m.chunk = kCoreChunk;
     m.gpart = p->sc.gpart;
     const int64_t chunks = ((int64_t)m.R + 2 * (int64_t)m.W + kCoreChunk - 1) / kCoreChunk;
+    m.nchunk = (int32_t)chunks;
     job->gemm_blocks = (int)(chunks * g.B);
     CoreRedArgs& r = job->red;
     r.gpart = p->sc.gpart;
@@ -1277,7 +1352,7 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
     void* args[] = {(void*)&job.seg};
     HOQRI_HIP_TRY(hipLaunchKernel(kern, dim3(job.seg_blocks), dim3(job.threads), args, job.shmem, s));
   }
-  if (job.key >= 1000) hipLaunchKernelGGL(k_core_gemm, dim3(job.gemm_blocks), dim3(256), 0, s, job.gemm);
+  if (job.key >= 1000) launch_core_gemm(job.gemm, job.gemm_blocks, s);
   hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
   HOQRI_HIP_TRY(hipGetLastError());
@@ -1307,12 +1382,10 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   m.W = (int32_t)W;
   m.B = g.B;
   const int64_t nv = (int64_t)m.R + 2 * W;
-  int64_t chunk = (nv + kYChunks - 1) / kYChunks;
-  chunk = (chunk + 15) / 16 * 16;
-  if (chunk < kCoreChunk) chunk = kCoreChunk;
-  m.chunk = (int32_t)chunk;
+  int64_t chunks = (nv + kCoreChunk - 1) / kCoreChunk;
+  if (chunks > kYChunks) chunks = kYChunks;
+  m.nchunk = (int32_t)chunks;
   m.gpart = p->sc.gpart;
-  const int64_t chunks = (nv + chunk - 1) / chunk;
   job->gemm_blocks = (int)(chunks * g.B);
   CoreRedArgs& r = job->red;
   r.gpart = p->sc.gpart;
@@ -1344,7 +1417,7 @@ hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipS
   YCoreJob job;
   HOQRI_TRY(prepare_ycore(p, mode, G, f_out, &job));
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
-  hipLaunchKernelGGL(k_core_gemm, dim3(job.gemm_blocks), dim3(256), 0, s, job.gemm);
+  launch_core_gemm(job.gemm, job.gemm_blocks, s);
   hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
   HOQRI_HIP_TRY(hipGetLastError());
@@ -1420,7 +1493,7 @@ bool stage_ycore_group(const YCoreJob* const* jobs, int n, Staging& st, YCoreGro
 }
 
 hoqri_status launch_ycore_group(const YCoreGroup& g, hipStream_t s) {
-  hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(256), 0, s, (const CoreGemmArgs*)g.gemm.descs,
+  hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(kGemmThreads), 0, s, (const CoreGemmArgs*)g.gemm.descs,
                      g.gemm.first, g.gemm.count);
   hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(kRedThreads), 0, s, (const CoreRedArgs*)g.red.descs,
                      g.red.first, g.red.count);
@@ -1458,7 +1531,7 @@ hoqri_status launch_core_group(const CoreGroup& g, hipStream_t s) {
   void* args[] = {(void*)&d, (void*)&first, (void*)&count};
   HOQRI_HIP_TRY(hipLaunchKernel(kern, dim3(g.seg.blocks), dim3(g.threads), args, g.shmem, s));
   if (g.key >= 1000)
-    hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(256), 0, s, (const CoreGemmArgs*)g.gemm.descs,
+    hipLaunchKernelGGL(k_core_gemm_b, dim3(g.gemm.blocks), dim3(kGemmThreads), 0, s, (const CoreGemmArgs*)g.gemm.descs,
                        g.gemm.first, g.gemm.count);
   hipLaunchKernelGGL(k_core_reduce_b, dim3(g.red.blocks), dim3(kRedThreads), 0, s, (const CoreRedArgs*)g.red.descs,
                      g.red.first, g.red.count);

@@ -20,8 +20,9 @@ relative after the same number of sweeps, with orthonormal factors (the
 orthonormalisation is float64 in every form). The 16-bit roundings move the
 trajectory, not the fixed points: on a uniformly random tensor (fit ~0.002,
 an almost flat objective) the BF16 fit after 10 sweeps of the 200^3 case
-differs by 1.6e-4 relative and by 2.3e-5 after 30, so that case is compared
-after 30 sweeps; Zipf-structured tensors stay within 6e-5 from the start.
+differs by 1.6e-4 relative and by 2.3e-5 after 30 (FP16: 1.0e-4 after 10),
+so that case is compared after 30 sweeps in both forms; Zipf-structured
+tensors stay within 6e-5 from the start.
 """
 import numpy as np
 import pytest
@@ -133,7 +134,7 @@ def run_fit(name, prec, sweeps):
     return dims, K, idx, vals32, [u.cpu().numpy().astype(np.float64) for u in Us], G.cpu().numpy(), st, Uo, h
 
 
-@pytest.mark.parametrize("prec,name,sweeps", [("bf16", "c1", 30), ("fp16", "c1", 10), ("bf16", "zipf3", 5),
+@pytest.mark.parametrize("prec,name,sweeps", [("bf16", "c1", 30), ("fp16", "c1", 30), ("bf16", "zipf3", 5),
                                               ("fp16", "zipf3", 5), ("bf16", "n4k10", 5), ("fp16", "n4k10", 5)])
 def test_16bit_run_reaches_oracle_fit(prec, name, sweeps):
     print(f"[prec-run] case={name} prec={prec} sweeps={sweeps}", flush=True)
