@@ -250,35 +250,47 @@ __global__ __launch_bounds__(kT) void k_chol_b(const CholArgs* d, const int32_t*
 // U = A M (M upper triangular), rows staged in LDS so U may alias A, then
 // rows [rows, zero_to) of U set to zero. Skipped entirely when this
 // factorisation broke down (*flag != 0): U keeps its previous contents.
-// Thread t takes column c = t mod Kp (Kp = K rounded up to a power of two)
-// and rows t / Kp + j 256 / Kp of each 64-row tile; an entry M(k, c) is read
-// once per tile for all of the thread's rows.
+// Each 64-row tile is multiplied on the float64 matrix cores: wave w takes
+// rows 16w .. 16w+15, lane (gg, q) supplies A(row q, 4s + gg) (from LDS) and
+// M(4s + gg, 16 ct + q) (kept in registers), and receives U entries
+// (4v + gg, 16 ct + q).
 __device__ inline void apply_body(const ApplyArgs& a, const int blk) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   __shared__ float tile[64][kMaxRank + 1];
-  __shared__ double Ms[kMaxRank][kMaxRank];
   const float* A = a.A;
   const int64_t rows = a.rows;
   const int K = a.K;
   const double* M = a.M;
   float* U = a.U;
-  if (*a.flag != 0) return;
-  int Kp = 1;
-  while (Kp < K) Kp <<= 1;
-  const int c = threadIdx.x % Kp, r0 = threadIdx.x / Kp;
-  const int rstep = kT / Kp;                      // rows between a thread's rows
-  const int nrt = rstep >= 64 ? 1 : 64 / rstep;   // rows per thread per tile (<= 8)
-  for (int t = threadIdx.x; t < K * K; t += kT) Ms[t / K][t % K] = M[t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gg = lane >> 4, q = lane & 15;
+  const int KT = (K + 15) >> 4;  // 16-column tiles (1 or 2)
   const int64_t last = rows * K - 1;
-  for (int64_t base = blk * (int64_t)64; base < rows; base += (int64_t)a.nblk * 64) {
-    const int nr = (int)((rows - base) < 64 ? (rows - base) : 64);
-    // the tile's loads (clamped addresses) are all issued before the LDS stores
-    float v[8];
+  // a tile's loads go to clamped (valid) addresses, all issued together; the
+  // next tile's loads are in flight while a tile is multiplied (its rows are
+  // other rows, so U may still alias A)
+  float v[8];
+  auto load_tile = [&](int64_t base) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int64_t e = base * K + threadIdx.x + i * kT;
       v[i] = A[e < last ? e : last];
     }
-    __builtin_amdgcn_sched_barrier(0);
+  };
+  const int64_t step = (int64_t)a.nblk * 64;
+  int64_t base = blk * (int64_t)64;
+  if (base < rows) load_tile(base);
+  if (*a.flag != 0) return;
+  double mb[8][2];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int kk = 4 * s + gg, cc = 16 * ct + q;
+      mb[s][ct] = (kk < K && cc < K) ? M[kk * K + cc] : 0.0;
+    }
+  for (; base < rows; base += step) {
+    const int nr = (int)((rows - base) < 64 ? (rows - base) : 64);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -286,20 +298,28 @@ __device__ inline void apply_body(const ApplyArgs& a, const int blk) {
       if (t < nr * K) tile[t / K][t % K] = v[i];
     }
     __syncthreads();
-    if (c < K && r0 < nr) {
-      double acc[8];
+    if (base + step < rows) load_tile(base + step);
+    __builtin_amdgcn_sched_barrier(0);
+    const int rw = 16 * wv;  // this wave's rows in the tile
+    if (rw < nr) {
+      d4 D[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] = 0.0;
-      for (int k = 0; k <= c; ++k) {
-        const double m = Ms[k][c];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (j < nrt && r0 + j * rstep < nr) acc[j] += (double)tile[r0 + j * rstep][k] * m;
+      for (int s = 0; s < 8; ++s) {
+        if (s >= 4 * KT) break;
+        const int kk = 4 * s + gg;
+        const double av = (rw + q < nr && kk < K) ? (double)tile[rw + q][kk] : 0.0;
+        D[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, mb[s][0], D[0], 0, 0, 0);
+        if (KT > 1) D[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, mb[s][1], D[1], 0, 0, 0);
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int r = r0 + j * rstep;
-        if (j < nrt && r < nr) U[(base + r) * K + c] = (float)acc[j];
+      for (int ct = 0; ct < 2; ++ct) {
+        if (ct >= KT) break;
+        const int cc = 16 * ct + q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rw + 4 * r + gg;
+          if (row < nr && cc < K) U[(base + row) * K + cc] = (float)D[ct][r];
+        }
       }
     }
   }

@@ -44,10 +44,12 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
 constexpr int YS = 260;                      // LDS floats per staged y_i block (256 + pad)
-// finished slices staged per stage-two product: 8 when a y_i tile is one
-// wave's (more waves fit in LDS), 16 when it spans several waves (halves the
-// cross-wave reductions)
-__host__ __device__ inline int stage_slots(int B) { return B > 1 ? 16 : 8; }
+// finished slices staged per stage-two product (LDS per wave grows with it;
+// 8 keeps several workgroups per CU also when a y_i spans several waves)
+__host__ __device__ inline int stage_slots(int B) {
+  (void)B;
+  return 8;
+}
 constexpr int KIND_COMPLETE = 0, KIND_HEAD = 1, KIND_TAIL = 2;
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
@@ -506,15 +508,18 @@ __global__ __launch_bounds__(512) void k_ttm(SegArgs a) {
   ttm_body<NM1, KN2, PREC>(a, blockIdx.x);
 }
 
-// The same pass held to 128 registers (four waves per SIMD) for the instance
-// whose allocation lands just above that without spilling when held to it
+// The same pass held to 128 registers (four waves per SIMD) for the
+// instances whose allocation lands above that: the 3-way FP32 pass fits
+// without spilling; the 4-way passes spill a few registers and still run
+// faster than at three waves per SIMD (their workgroups of up to 8 waves
+// otherwise fit only once per CU).
 template <int NM1, int KN2, int PREC>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_ttm_w4(SegArgs a) {
   ttm_body<NM1, KN2, PREC>(a, blockIdx.x);
 }
 template <int NM1, int KN2, int PREC>
 constexpr bool ttm_hold4() {
-  return NM1 == 2 && KN2 == 1 && PREC == P_FP32;
+  return (NM1 == 2 && KN2 == 1 && PREC == P_FP32) || NM1 == 3;
 }
 
 template <int NM1, int KN2, int PREC>
@@ -526,10 +531,12 @@ __global__ __launch_bounds__(512) void k_ttm_b(const SegArgs* d, const int32_t* 
 // Adds the partial rows of slices that cross range boundaries and writes them.
 // One workgroup per range; only the owner of a split slice (the range where it
 // starts, holding its tail partial) works: the head partials of the following
-// ranges w0+1..w1 are summed in float64 by 8 thread groups with a fixed
-// stride, then the groups are added in order (deterministic).
+// ranges w0+1..w1 (thousands for the heaviest slices) are summed in float64 by
+// thread groups (16 lanes per group when K_n <= 16, else 32) with a fixed
+// stride and eight loads in flight, then the groups are added in order
+// (deterministic).
 __device__ inline void fix_body(const FixArgs& f, const int32_t w) {
-  __shared__ double part[8][32];
+  __shared__ double part[16][32];
   const int32_t* meta = f.meta;
   const float* carry = f.carry;
   const int32_t* seg_row = f.seg_row;
@@ -544,28 +551,27 @@ __device__ inline void fix_body(const FixArgs& f, const int32_t w) {
   // last range holding part of slice s: the largest w1 with w1 * nnz / W <= e_last
   const int64_t e_last = (int64_t)seg_off[s + 1] - 1;
   const int32_t w1 = (int32_t)(((e_last + 1) * (int64_t)W - 1) / nnz);
-  const int kn = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int gs = Kn <= 16 ? 16 : 32;  // lanes per group
+  const int ng = 256 / gs;            // groups
+  const int kn = threadIdx.x % gs, grp = threadIdx.x / gs;
   double acc = 0.0;
   if (kn < Kn) {
-    // group grp adds ranges w+1+grp, w+9+grp, ... in order, four loads in flight
+    // group grp adds ranges w+1+grp, w+1+grp+ng, ... in order, eight loads in flight
     int32_t w2 = w + 1 + grp;
-    for (; w2 + 24 <= w1; w2 += 32) {
-      const float c0 = carry[((size_t)w2 * 2 + 0) * 32 + kn];
-      const float c1 = carry[((size_t)(w2 + 8) * 2 + 0) * 32 + kn];
-      const float c2 = carry[((size_t)(w2 + 16) * 2 + 0) * 32 + kn];
-      const float c3 = carry[((size_t)(w2 + 24) * 2 + 0) * 32 + kn];
-      acc += (double)c0;
-      acc += (double)c1;
-      acc += (double)c2;
-      acc += (double)c3;
+    for (; w2 + 7 * ng <= w1; w2 += 8 * ng) {
+      float c[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c[i] = carry[((size_t)(w2 + i * ng) * 2 + 0) * 32 + kn];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc += (double)c[i];
     }
-    for (; w2 <= w1; w2 += 8) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + kn];
+    for (; w2 <= w1; w2 += ng) acc += (double)carry[((size_t)w2 * 2 + 0) * 32 + kn];
   }
   part[grp][kn] = acc;
   __syncthreads();
-  if (threadIdx.x < 32 && kn < Kn) {
+  if (threadIdx.x < gs && kn < Kn) {
     double t = (double)carry[((size_t)w * 2 + 1) * 32 + kn];
-    for (int g2 = 0; g2 < 8; ++g2) t += part[g2][kn];
+    for (int g2 = 0; g2 < ng; ++g2) t += part[g2][kn];
     const int32_t row = out_map ? out_map[seg_row[s]] : seg_row[s];
     A[(size_t)row * Kn + kn] = (float)t;
   }
