@@ -61,7 +61,8 @@ def pass_work(dims, ranks, nnz, R, su=4):
     """Algorithmic flops and HBM bytes of one TTMcTC pass per mode (segment-first
     count: 2 nnz prod K_{-n} + 2 R_n prod K flops; indices + values streamed once,
     each needed factor row read once (su bytes per entry: 4 for float32, 2 for
-    the 16-bit copies), the output written once)."""
+    the 16-bit copies), the output written once, and the slice rows Y_(n)
+    (R_n x prod K_{-n} float32) written once for the core of the updated factor)."""
     N = len(dims)
     PK = math.prod(ranks)
     out = []
@@ -69,7 +70,7 @@ def pass_work(dims, ranks, nnz, R, su=4):
         P = PK // ranks[n]
         flops = 2 * nnz * P + 2 * R[n] * PK
         byts = nnz * (4 * (N - 1) + 4) + 8 * R[n] + sum(R[m] * ranks[m] * su for m in range(N) if m != n) \
-            + 4 * dims[n] * ranks[n]
+            + 4 * dims[n] * ranks[n] + 4 * R[n] * P
         out.append((flops, byts))
     return out
 
@@ -343,6 +344,7 @@ def main():
         "kernel_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in kt.items()},
         "fit": st.fit,
         "orth_err_max": st.orth_err_max,
+        "nonempty_slices": [int(r) for r in R],
         "plan_s": round(t_plan, 3),
         "input_gen_s": round(t_gen, 2),
         "roofline": roofline,
