@@ -237,10 +237,26 @@ __global__ void k_segments(const int32_t* modeidx, const int32_t* head, const in
   }
 }
 
-// Slice sizes (degrees) of every mode-n index; integer atomics, exact.
+// Slice sizes (degrees) of every mode-n index; integer atomics, exact. The
+// lanes of a wave that hold the same index are counted together first (one
+// atomic per distinct index per wave): a skewed mode sends a quarter of its
+// nonzeros to one index, which per-lane atomics would serialise.
 __global__ void k_degree(const int32_t* cidx_n, int64_t nnz, int32_t* deg) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&deg[cidx_n[j]], 1);
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the loop runs the same number of times on every lane of a wave
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < nnz; base += stride) {
+    const int64_t j = base + lane;
+    const int32_t v = j < nnz ? cidx_n[j] : -1;
+    uint64_t pending = __ballot(v >= 0);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int32_t lv = __builtin_amdgcn_readlane(v, leader);
+      const uint64_t same = __ballot(v == lv) & pending;
+      if (lane == leader) atomicAdd(&deg[lv], (int32_t)__popcll(same));
+      pending &= ~same;
+    }
+  }
 }
 
 // Sort keys for the relabelling: larger degree first; the stable sort keeps
