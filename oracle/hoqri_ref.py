@@ -21,7 +21,9 @@ Rank Approximation of Large and Sparse Tensors"):
 * the quantities of the convergence analysis (§5): the objective f = ||G||^2,
   the Riemannian gradient norm, the subspace distance d(U, V);
 * a HOSVD-style start (Alg. 2 allows one) by a randomized range finder of
-  every unfolding, computed as TTMcTC with random factors and a random core.
+  every unfolding, computed as TTMcTC with random factors and a random core;
+* HOOI (Alg. 1), the method HOQRI is contrasted with: each mode update takes
+  the leading left singular vectors of Y_(n) (an SVD of its nonempty rows).
 
 Readings where the paper is silent (all also listed in the design doc):
 * QR basis: the thin QR with diag(R) > 0, unique for full-rank A (the paper
@@ -75,6 +77,8 @@ __all__ = [
     "grad_norm2_direct",
     "tucker_dense",
     "sketch_start",
+    "leading_left",
+    "hooi",
 ]
 
 BREAKDOWN_REL = 1e-13
@@ -405,6 +409,53 @@ def hoqri(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: fl
         f_prev = f
     G = core(idx, vals, U)
     return U, G, hist
+
+
+# --------------------------------------------------------------------------
+# HOOI (Alg. 1), the method HOQRI is contrasted with
+# --------------------------------------------------------------------------
+
+def leading_left(idx, vals, Us: Sequence[np.ndarray], n: int, K: int):
+    """The K leading left singular vectors of Y_(n) = X_(n) (Kronecker over m != n
+    of U^(m)), the HOOI update of Alg. 1, from the SVD of its nonempty rows (rows
+    of empty slices are zero and add nothing). Returns (U_n with zero rows for
+    empty slices, the K leading singular values). Raises RankDeficient when
+    fewer than K rows are nonempty."""
+    rows, Yr = _slice_rows(idx, vals, Us, n)
+    if rows.size < K:
+        raise RankDeficient(f"mode {n}: {rows.size} nonempty slices < K = {K}")
+    W, s, _ = np.linalg.svd(Yr, full_matrices=False)
+    U = np.zeros((Us[n].shape[0], K))
+    U[rows] = W[:, :K]
+    return U, s[:K]
+
+
+def hooi(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: float | None = None):
+    """Alg. 1 (HOOI): sweeps over n = 1..N in order (Gauss-Seidel, as hoqri);
+    per mode U^(n) <- the K_n leading left singular vectors of Y_(n), which
+    maximises ||U^T Y_(n)||^2 = f over orthonormal U^(n) with the other factors
+    fixed. The basis within the subspace is free (f, the fit and the subspaces do
+    not depend on it). Stops after `sweeps` sweeps or when |f_t - f_{t-1}| <=
+    tol * f_t. Returns (U, G, history) with history["f_step"] (f after every mode
+    update), ["f_sweep"] and ["fit"]."""
+    validate(idx, dims, ranks)
+    idx, vals = coalesce(idx, vals, dims)
+    nx2 = norm_x2(vals)
+    N = len(dims)
+    U = [np.array(u, dtype=np.float64, copy=True) for u in U0]
+    hist = {"f_step": [], "f_sweep": [], "fit": [], "normx2": nx2}
+    f_prev = float(np.sum(core_segment(idx, vals, U) ** 2))
+    for t in range(sweeps):
+        for n in range(N):
+            U[n], s = leading_left(idx, vals, U, n, ranks[n])
+            hist["f_step"].append(float(np.sum(s * s)))
+        f = float(np.sum(core_segment(idx, vals, U) ** 2))
+        hist["f_sweep"].append(f)
+        hist["fit"].append(fit_from(nx2, f))
+        if tol is not None and abs(f - f_prev) <= tol * f:
+            break
+        f_prev = f
+    return U, core_segment(idx, vals, U), hist
 
 
 # --------------------------------------------------------------------------

@@ -219,3 +219,77 @@ def test_sketch_start_recovers_planted_subspaces_and_hosvd():
     n = 1
     S = O.unfold(X, n) @ O.kron_except(Om, n) @ O.unfold(Ga, n).T
     np.testing.assert_allclose(U[n], O.qr_positive(S)[0], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# HOOI (Alg. 1)
+# --------------------------------------------------------------------------
+
+def _dense_Y(idx, vals, dims, Us, n):
+    """Y_(n) = unfold(X x_{m != n} U^(m)T, n) from the dense tensor (mode products)."""
+    X = O.to_dense(idx, vals, dims)
+    for m in range(len(dims)):
+        if m != n:
+            X = O.mode_product(X, Us[m].T, m)
+    return O.unfold(X, n)
+
+
+def test_hooi_update_is_the_dense_eigen_solution_and_dominates():
+    # the update maximises ||U^T Y_(n)||^2: its value equals the sum of the K
+    # largest eigenvalues of Y Y^T from the dense tensor, its subspace is their
+    # eigenvectors', and no other orthonormal U (HOQRI's step, random ones) does better
+    dims, K = (12, 9, 10), (3, 2, 4)
+    idx, vals = synth.coo_uniform(dims, 300, seed=41)
+    U = O.orthonormal_start(synth.gaussian_start(dims, K, 42))
+    ci, cv = O.coalesce(idx, vals, dims)
+    rng = np.random.default_rng(43)
+    for n in range(3):
+        Un, s = O.leading_left(ci, cv, U, n, K[n])
+        Y = _dense_Y(ci, cv, dims, U, n)
+        w, V = np.linalg.eigh(Y @ Y.T)
+        assert np.sum(s ** 2) == pytest.approx(np.sum(w[-K[n]:]), rel=1e-12)
+        assert O.subspace_dist(Un, V[:, -K[n]:]) < 1e-10
+        assert np.allclose(Un.T @ Un, np.eye(K[n]), atol=1e-12)
+        f_hooi = np.sum((Un.T @ Y) ** 2)
+        G = O.core_segment(ci, cv, U)
+        Uq = O.qr_positive(O.ttmctc_segment(ci, cv, U, n, G))[0]
+        assert np.sum((Uq.T @ Y) ** 2) <= f_hooi * (1 + 1e-12)
+        for _ in range(5):
+            Ur = np.linalg.qr(rng.standard_normal((dims[n], K[n])))[0]
+            assert np.sum((Ur.T @ Y) ** 2) <= f_hooi * (1 + 1e-12)
+
+
+def test_hooi_planted_tucker_recovered_in_one_sweep_and_monotone():
+    dims, K = (40, 50, 60), (3, 4, 2)
+    idx, vals, U0true, G0 = _planted(dims, K, (9, 11, 9), seed=12)
+    start = O.orthonormal_start(synth.gaussian_start(dims, K, 77))
+    U, G, h = O.hooi(idx, vals, dims, K, start, sweeps=1)
+    for u, ut in zip(U, U0true):
+        assert O.subspace_dist(u, ut) < 1e-12
+    assert (h["normx2"] - h["f_sweep"][0]) / h["normx2"] < 1e-12
+    # f never decreases along the mode updates on a generic tensor
+    dims2, K2 = (30, 25, 20), (4, 3, 5)
+    idx2, vals2 = synth.coo_uniform(dims2, 2000, seed=44)
+    st2 = O.orthonormal_start(synth.gaussian_start(dims2, K2, 45))
+    _, _, h2 = O.hooi(idx2, vals2, dims2, K2, st2, sweeps=4)
+    f = np.array(h2["f_step"])
+    assert np.all(np.diff(f) >= -1e-12 * f[:-1])
+
+
+def test_hooi_matrix_case_is_the_truncated_svd():
+    # N = 2: alternating leading subspaces converge to the top-K singular pair
+    # subspaces, f* = sum of the K largest sigma^2 (Eckart-Young)
+    rng = np.random.default_rng(13)
+    I1, I2, K = 60, 50, 3
+    Ul = np.linalg.qr(rng.standard_normal((I1, I1)))[0]
+    Vr = np.linalg.qr(rng.standard_normal((I2, I2)))[0]
+    s = np.concatenate([[10.0, 8.0, 6.0], 1.0 / (1 + np.arange(I2 - 3))])
+    M = (Ul[:, :I2] * s) @ Vr.T
+    idx = np.stack(np.unravel_index(np.arange(I1 * I2), (I1, I2))).astype(np.int32)
+    start = O.orthonormal_start(synth.gaussian_start((I1, I2), (K, K), 3))
+    U, G, h = O.hooi(idx, M.ravel(), (I1, I2), (K, K), start, sweeps=20)
+    sv = np.linalg.svd(M, compute_uv=False)
+    assert h["f_sweep"][-1] == pytest.approx(np.sum(sv[:K] ** 2), rel=1e-12)
+    Ls, _, Rs = np.linalg.svd(M)
+    assert O.subspace_dist(U[0], Ls[:, :K]) < 1e-10
+    assert O.subspace_dist(U[1], Rs[:K].T) < 1e-10
