@@ -132,7 +132,19 @@ typedef struct {
                            (§5.2: grad_n = 2 (A^(n) - U^(n) G_(n) G_(n)^T), evaluated before
                            U^(n) is updated); NULL and grad_tol == 0 turn the monitor off */
   double grad_tol;      /* > 0: also stop when sqrt(sum_n ||grad_n||^2) over a sweep <= grad_tol * f_t */
+  int32_t method;       /* HOQRI_METHOD_HOQRI (0, Alg. 2) or HOQRI_METHOD_HOOI (Alg. 1) */
+  int32_t inner_iters;  /* HOOI: orthogonal-iteration steps per mode update (>= 1; 0 means 1) */
 } hoqri_run_opts;
+
+/* Methods of hoqri_run. HOOI (Alg. 1) replaces the single QR step of a mode
+ * update by the K_n leading left singular vectors of Y_(n), computed by
+ * orthogonal iteration on Y_(n) Y_(n)^T from the current U^(n):
+ * U <- orth(Y_(n) Y_(n)^T U), inner_iters times. The first product is the
+ * TTMcTC of the mode (Y_(n) G_(n)^T with G_(n) = U^T Y_(n)); the others reuse
+ * the slice rows Y_(n) that pass stored. With inner_iters == 1 a mode update
+ * is the HOQRI update. */
+#define HOQRI_METHOD_HOQRI 0
+#define HOQRI_METHOD_HOOI 1
 
 typedef struct {
   int32_t sweeps;       /* sweeps performed */
@@ -146,7 +158,8 @@ typedef struct {
 } hoqri_run_stats;
 
 /* HOQRI (Alg. 2): for each sweep, for n = 1..N: G from the current factors,
- * A^(n) = TTMcTC, U^(n) = orthonormal basis of A^(n) (Gauss-Seidel order).
+ * A^(n) = TTMcTC, U^(n) = orthonormal basis of A^(n) (Gauss-Seidel order);
+ * or HOOI (opts->method, see above) on the same passes.
  * d_U_inout: host array of N device pointers, read as the start and overwritten
  * with the result (orthonormal columns required unless orthonormalize_input).
  * d_G_out: receives G = X x {U^T} for the returned factors (last line of

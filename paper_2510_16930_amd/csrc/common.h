@@ -151,6 +151,10 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
 // G = X x {U^T} from the rows Y_(mode) stored by the last TTMcTC pass of `mode`
 // and the (updated) factor U^(mode) in the plan's scratch; ||G||^2 into *f_out.
 hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s);
+// A = Y_(mode) G_(mode)^T from the rows stored by the last TTMcTC pass of
+// `mode` (label order, rows of empty slices zeroed): one inner step of HOOI's
+// orthogonal iteration when G = U^(mode)T Y_(mode).
+hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s);
 bool segpass_supported(const hoqri_plan* p, int mode);
 // Power-of-two scales of the FP16 form for this plan (false: the values' range
 // does not allow them; use another precision).

@@ -91,6 +91,20 @@ struct CoreGemmArgs {
   float* gpart;
 };
 
+// A from stored slice rows: A(row) = y_row G_(n)^T for the rows of Y_(n) a
+// TTMcTC pass stored (complete rows into A by label, split-slice partials into
+// carry like the pass itself, for the fix-up).
+struct RowsAArgs {
+  const float* ybuf;
+  const float* ycarry;
+  const int32_t* ymeta;
+  const float* gtop;
+  int32_t R, W, B, KN2, Kn;
+  int64_t groups;  // 16-row groups over the R + 2W rows
+  float* A;
+  float* carry;
+};
+
 struct SumArgs {
   const double* part;
   int32_t n;
@@ -151,6 +165,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
 hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, CoreJob* job);
 // After the TTMcTC pass of `mode` with rows and the update of U^(mode) (float32, label order).
 hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job);
+
 
 struct GramArgs {
   const float* A;

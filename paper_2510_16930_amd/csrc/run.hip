@@ -282,6 +282,11 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   HOQRI_TRY(check_prec(opts->prec, &op));
   for (int n = 0; n < p->N; ++n)
     if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
+  if (opts->method != HOQRI_METHOD_HOQRI && opts->method != HOQRI_METHOD_HOOI) return HOQRI_ERR_ARG;
+  if (opts->inner_iters < 0 || opts->inner_iters > 1000) return HOQRI_ERR_ARG;
+  const bool hooi = opts->method == HOQRI_METHOD_HOOI;
+  const int inner = hooi && opts->inner_iters > 1 ? opts->inner_iters : 1;
+  if (hooi && !p->yfuse) return HOQRI_ERR_UNSUPPORTED;
   if (op == OP_FP16) {
     float as, ys;
     if (!fp16_scales(p, p->N - 1, &as, &ys)) return HOQRI_ERR_UNSUPPORTED;
@@ -331,15 +336,19 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       // rows R_n.. of A are zero (empty slices): orthonormalise the first R_n rows
       // and keep the remaining rows of the factor at zero
       const int64_t Rn = p->md[n].R;
-      TimerScope to(p, HOQRI_KERNEL_ORTH, stream);
-      // rows R_n.. (empty slices) of the new factor are zeroed by the same launch
-      HOQRI_TRY(launch_orth(Rn, p->K[n], p->sc.A, Up[n], nullptr, status, p->sc.orth_ws, p->sc.orth_ws_bytes,
-                            stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n]));
-      HOQRI_TRY(refresh16(p, op, n, stream));
-      if (fuse) {
-        // f after mode n: the next mode's starting point, or the sweep's end
-        double* fdst = n + 1 < N ? (d_f_hist ? d_f_hist + (size_t)t * N + n + 1 : p->sc.f_dev) : fsw + t + 1;
-        HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream));
+      // f after mode n: the next mode's starting point, or the sweep's end
+      double* fdst = n + 1 < N ? (d_f_hist ? d_f_hist + (size_t)t * N + n + 1 : p->sc.f_dev) : fsw + t + 1;
+      for (int it = 0; it < inner; ++it) {
+        {
+          TimerScope to(p, HOQRI_KERNEL_ORTH, stream);
+          // rows R_n.. (empty slices) of the new factor are zeroed by the same launch
+          HOQRI_TRY(launch_orth(Rn, p->K[n], p->sc.A, Up[n], nullptr, status, p->sc.orth_ws, p->sc.orth_ws_bytes,
+                                stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n]));
+        }
+        HOQRI_TRY(refresh16(p, op, n, stream));
+        if (fuse) HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream));
+        // HOOI: next orthogonal-iteration step A = Y_(n) (Y_(n)^T U) from the stored rows
+        if (it + 1 < inner) HOQRI_TRY(launch_rows_a(p, n, d_G_out, p->sc.A, stream));
       }
     }
     if (!fuse) HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + t + 1, stream));

@@ -837,6 +837,71 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   }
 }
 
+// A from stored rows, one wave per 16-row group: lane (g, q) takes row q of
+// the group and entries j' = 64 g + 4u + v of tile b (the stage-two operand's
+// order), so the product is the TTMcTC pass's stage two with the rows read
+// from memory: D(row 4g + v, kn = 16 kb + q) on every lane.
+__device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, q = lane & 15;
+  const int64_t grp = (int64_t)blk * 4 + wv;
+  if (grp >= p.groups) return;
+  const size_t rowf = (size_t)p.B * 256;
+  const int64_t R = p.R, NP = 2 * (int64_t)p.W;
+  // where row x of the group comes from and goes to: complete rows v < R; then
+  // the valid split-slice partials (head 0 / tail 1 of range w)
+  auto locate = [&](int64_t x, const float** src, float** dst, int ld) -> bool {
+    if (x < R) {
+      *src = p.ybuf + (size_t)x * rowf;
+      *dst = p.A + (size_t)x * ld;
+      return true;
+    }
+    if (x >= R + NP) return false;
+    const int64_t w = (x - R) >> 1;
+    const int kind = (int)((x - R) & 1);
+    const int32_t sf = p.ymeta[w * 4 + 0], sl = p.ymeta[w * 4 + 1], fl = p.ymeta[w * 4 + 2];
+    const bool head = fl & 1;
+    const bool tail = (fl & 2) && !(sf == sl && head);
+    if (kind == 0 ? !head : !tail) return false;
+    *src = p.ycarry + ((size_t)w * 2 + kind) * rowf;
+    *dst = p.carry + ((size_t)w * 2 + kind) * 32;
+    return true;
+  };
+  const float* src = p.ybuf;
+  float* dst = nullptr;
+  const bool ok = locate(grp * 16 + q, &src, &dst, p.Kn);
+  f4 d[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+  for (int b = 0; b < p.B; ++b) {
+    const float* gtl = p.gtop + (size_t)b * p.KN2 * 4096 + lane * 4;
+    const float* yr = src + b * 256 + 64 * g;
+#pragma unroll 4
+    for (int u = 0; u < 16; ++u) {
+      const f4 t = *reinterpret_cast<const f4*>(yr + 4 * u);
+      const f4 yv = ok ? t : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        if (kb >= p.KN2) break;
+        const f4 gv = *reinterpret_cast<const f4*>(gtl + (kb * 16 + u) * 256);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[kb] = mfma4(yv[v], gv[v], d[kb]);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float* s2;
+    float* out;
+    if (!locate(grp * 16 + 4 * g + v, &s2, &out, p.Kn)) continue;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int kn = 16 * kb + q;
+      if (kb < p.KN2 && kn < p.Kn) out[kn] = d[kb][v];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rows_a(RowsAArgs p) { rows_a_body(p, blockIdx.x); }
+
 template <int KTT>
 __global__ __launch_bounds__(kGemmThreads) void k_core_gemm(CoreGemmArgs p) {
   core_gemm_body<KTT>(p, blockIdx.x);
@@ -1426,6 +1491,37 @@ hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipS
   launch_core_gemm(job.gemm, job.gemm_blocks, s);
   hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
   hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s) {
+  TtmJob job;  // for the stage-two operand and the fix-up of this mode's ranges
+  const Operands op{OP_FP32, p->sc.Up, p->sc.Uh};
+  HOQRI_TRY(prepare_ttm(p, mode, op, G, A, nullptr, &job, true));
+  RowsAArgs r{};
+  r.ybuf = p->sc.ybuf;
+  r.ycarry = p->sc.ycarry;
+  r.ymeta = p->sc.meta;
+  r.gtop = p->sc.gtop;
+  r.R = job.seg.R;
+  r.W = job.seg.W;
+  r.B = job.seg.B;
+  r.KN2 = job.prep.KN2;
+  r.Kn = p->K[mode];
+  r.groups = ((int64_t)r.R + 2 * (int64_t)r.W + 15) / 16;
+  r.A = A;
+  r.carry = p->sc.carry;
+  TimerScope ts(p, HOQRI_KERNEL_CORE, s);
+  hipLaunchKernelGGL(k_prep_gtop, dim3(job.prep_blocks), dim3(256), 0, s, job.prep);
+  hipLaunchKernelGGL(k_rows_a, dim3((unsigned)((r.groups + 3) / 4)), dim3(256), 0, s, r);
+  hipLaunchKernelGGL(k_fix_split, dim3(job.fix_blocks), dim3(256), 0, s, job.fix);
+  const ModeData& md = p->md[mode];
+  if (md.E > 0) {
+    int64_t tot = md.E * p->K[mode];
+    int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, (const int32_t*)nullptr, md.R, md.E, p->K[mode], A);
+  }
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
 }

@@ -1,0 +1,108 @@
+"""HOOI (Alg. 1) on the GPU passes against the FP64 oracle.
+
+The GPU takes each mode's K_n leading left singular vectors of Y_(n) by
+orthogonal iteration on Y_(n) Y_(n)^T from the current factor (inner_iters
+steps; the first is the mode's TTMcTC, the others reuse the slice rows the pass
+stored); the oracle takes them from an SVD. On tensors with a clear gap after
+the K_n-th singular value the iteration converges to the SVD's subspace, so
+the two agree in f, fit and subspaces; with one inner step a mode update is
+the HOQRI update.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2510_16930_amd import _lib as H
+from paper_2510_16930_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def planted_noisy(dims, K, nnz_noise, seed, noise=0.05):
+    """A planted Tucker block (dense on a row subset) plus sparse uniform noise."""
+    rng = np.random.default_rng(seed)
+    rows = [np.sort(rng.choice(d, size=min(d, 6 * k), replace=False)) for d, k in zip(dims, K)]
+    Us = [np.linalg.qr(rng.standard_normal((r.size, k)))[0] for r, k in zip(rows, K)]
+    G0 = rng.standard_normal(K) * 10.0
+    block = O.tucker_dense(G0, Us)
+    grids = np.meshgrid(*rows, indexing="ij")
+    idx_b = np.stack([g.ravel() for g in grids]).astype(np.int64)
+    idx_n, v_n = synth.coo_uniform(dims, nnz_noise, seed=seed + 1)
+    idx = np.concatenate([idx_b, idx_n.astype(np.int64)], axis=1)
+    vals = np.concatenate([block.ravel(), noise * v_n])
+    ci, cv = O.coalesce(idx, vals, dims)  # planted and noise coordinates may meet: summed
+    return ci.astype(np.int32), cv.astype(np.float32)
+
+
+@pytest.mark.parametrize("dims,K", [((400, 300, 200), (4, 4, 4)), ((300, 250, 40, 30), (3, 3, 2, 2)),
+                                    ((500, 400, 300), (16, 8, 12))])
+def test_hooi_matches_oracle_svd_updates(dims, K):
+    print(f"[hooi] dims={dims} K={K}", flush=True)
+    idx, vals = planted_noisy(dims, K, 20_000, seed=sum(dims))
+    U0 = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 7))]
+    plan = H.hoqri_plan_create(dev(idx), dev(vals), dims, K)
+    Us = [dev(u) for u in U0]
+    sweeps = 3
+    G, st = H.hoqri_run(plan, Us, max_sweeps=sweeps, method="hooi", inner_iters=30)
+    torch.cuda.synchronize()
+    Uo, Go, h = O.hooi(idx, vals.astype(np.float64), dims, K, [u.astype(np.float64) for u in U0], sweeps=sweeps)
+    assert st.sweeps == sweeps
+    # f = ||G||^2 from float32 cores: relative error ~1e-7 (the fit magnifies it
+    # by f / (||X||^2 - f) on these nearly exact tensors, so f is compared)
+    assert st.f == pytest.approx(h["f_sweep"][-1], rel=1e-6)
+    assert st.orth_err_max < 1e-5
+    for n in range(len(dims)):
+        assert O.subspace_dist(Us[n].cpu().numpy().astype(np.float64), Uo[n]) < 1e-6
+    # the returned core is the core of the returned factors
+    ci, cv = O.coalesce(idx, vals.astype(np.float64), dims)
+    Gchk = O.core_segment(ci, cv, [u.cpu().numpy().astype(np.float64) for u in Us])
+    assert np.linalg.norm(G.cpu().numpy() - Gchk) / np.linalg.norm(Gchk) < 1e-5
+
+
+def test_one_inner_step_is_hoqri():
+    dims, K = (3000, 2000, 400), (8, 8, 8)
+    idx, vals = synth.coo_zipf(dims, 100_000, alpha=1.2, seed=3)
+    vals = vals.astype(np.float32)
+    U0 = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 8))]
+    plan = H.hoqri_plan_create(dev(idx), dev(vals), dims, K)
+    Ua = [dev(u) for u in U0]
+    Ub = [dev(u) for u in U0]
+    Ga, sa = H.hoqri_run(plan, Ua, max_sweeps=4, method="hoqri")
+    Gb, sb = H.hoqri_run(plan, Ub, max_sweeps=4, method="hooi", inner_iters=1)
+    torch.cuda.synchronize()
+    assert sa.f == sb.f and torch.equal(Ga, Gb)
+    for a, b in zip(Ua, Ub):
+        assert torch.equal(a, b)
+
+
+def test_hooi_objective_monotone():
+    # each HOOI mode update maximises f with the other factors fixed (and every
+    # orthogonal-iteration step on Y Y^T does not decrease it): f is
+    # non-decreasing over sweeps
+    dims, K = (2000, 1500, 300), (8, 8, 8)
+    idx, vals = synth.coo_zipf(dims, 80_000, alpha=1.1, seed=5)
+    vals = vals.astype(np.float32)
+    U0 = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 9))]
+    plan = H.hoqri_plan_create(dev(idx), dev(vals), dims, K)
+    f = []
+    Us = [dev(u) for u in U0]
+    for t in range(4):
+        G, st = H.hoqri_run(plan, Us, max_sweeps=1, method="hooi", inner_iters=20)
+        f.append(st.f)
+    torch.cuda.synchronize()
+    assert all(b >= a * (1 - 1e-6) for a, b in zip(f, f[1:])), f
+
+
+def test_bad_method_rejected():
+    dims, K = (50, 40, 30), (3, 3, 3)
+    idx, vals = synth.coo_uniform(dims, 2000, seed=1)
+    plan = H.hoqri_plan_create(dev(idx), dev(vals.astype(np.float32)), dims, K)
+    U0 = [dev(u.astype(np.float32)) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 2))]
+    with pytest.raises(H.HoqriError):
+        H.hoqri_run(plan, U0, max_sweeps=1, method="hooi", inner_iters=-1)
