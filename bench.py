@@ -56,6 +56,32 @@ CONFIGS = {
                   desc="4-way 2e5 x 2e5 x 5e3 x 1e3, nnz 100M, Zipf(1.1), uniform(0,1) values, ranks 10^4, FP32 form"),
 }
 
+# Stand-ins with the shapes of the paper's real tensors (Table 3: dims and nnz)
+# and the ranks of its convergence figures; the datasets are not available, so
+# the coordinates are Zipf(1.2) and the values lognormal(0,1), as for c2.
+TABLE3 = {
+    "last": ((2100, 18744, 12647), 186_479, ((10, 10, 10), (15, 15, 15))),
+    "delicious": ((108_035, 107_253, 52_955), 437_593, ((10, 10, 10), (20, 20, 10))),
+    "facebook": ((46_952, 46_951, 1_592), 738_079, ((10, 10, 10), (20, 20, 10))),
+    "movielens": ((610, 49_961, 8_215), 84_159, ((10, 10, 10), (15, 25, 15))),
+    "movielens10m": ((162_541, 49_994, 9_083), 20_503_478, ((10, 10, 10), (20, 20, 10))),
+}
+for _name, (_dims, _nnz, _rks) in TABLE3.items():
+    for _k in _rks:
+        CONFIGS[f"t3_{_name}_{'x'.join(map(str, _k))}"] = dict(
+            dims=_dims, ranks=_k, nnz=_nnz, dist="zipf", alpha=1.2, values="lognormal", seed=16, init_seed=116,
+            prec="fp32", desc=f"stand-in with the shape of the {_name} tensor of Table 3 "
+                              f"({'x'.join(map(str, _dims))}, nnz {_nnz}), Zipf(1.2) coordinates, lognormal(0,1) "
+                              f"values, ranks {'x'.join(map(str, _k))}, FP32")
+# Fig. 1's random tensors: 3-way I x I x I with nnz = 10 I, rank 10^3 (uniform
+# coordinates, N(0,1) values: the paper gives no distribution)
+for _e in (3, 4, 5, 6):
+    _I = 10 ** _e
+    CONFIGS[f"e1_1e{_e}"] = dict(dims=(_I, _I, _I), ranks=(10, 10, 10), nnz=10 * _I, dist="uniform", values="normal",
+                                 seed=17, init_seed=117, prec="fp32",
+                                 desc=f"3-way {_I}^3, nnz {10 * _I} uniform, N(0,1) values, ranks 10^3, FP32 "
+                                      f"(shape of Fig. 1)")
+
 
 def pass_work(dims, ranks, nnz, R, su=4):
     """Algorithmic flops and HBM bytes of one TTMcTC pass per mode (segment-first
@@ -244,6 +270,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--method", default="hoqri", choices=("hoqri", "hooi"),
+                    help="hooi: Alg. 1 on the same passes (orthogonal iteration per mode update)")
+    ap.add_argument("--inner-iters", type=int, default=10, help="hooi: orthogonal-iteration steps per mode update")
     ap.add_argument("--requests", type=int, default=None, help="serving configs: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device-to-device copy and exit (scale for HBM byte counters)")
@@ -281,15 +310,19 @@ def main():
     print(f"[bench] plan ready ({t_plan:.2f} s, nnz={nnz}, R={R}); warmup", file=sys.stderr, flush=True)
 
     Us = [u.clone() for u in U0]
+    # a numerically rank-deficient mode update is skipped (counted) rather than
+    # ending the run: very sparse random tensors reach it after a few sweeps
+    meth = dict(method=args.method, inner_iters=args.inner_iters if args.method == "hooi" else 1,
+                keep_on_breakdown=True)
     if args.warmup > 0:
-        H.hoqri_run(plan, Us, max_sweeps=args.warmup, prec=cfg["prec"], check_every=args.warmup)
+        H.hoqri_run(plan, Us, max_sweeps=args.warmup, prec=cfg["prec"], check_every=args.warmup, **meth)
     for u, u0 in zip(Us, U0):
         u.copy_(u0)
     torch.cuda.synchronize()
     H.hoqri_timing_enable(plan, True)
     print("[bench] timed region", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    G, st = H.hoqri_run(plan, Us, max_sweeps=args.steps, prec=cfg["prec"], check_every=args.steps)
+    G, st = H.hoqri_run(plan, Us, max_sweeps=args.steps, prec=cfg["prec"], check_every=args.steps, **meth)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = {k: H.hoqri_timing_read(plan, k) for k in ("ttmctc", "core", "orth", "fixup")}
@@ -325,8 +358,11 @@ def main():
         "hbm_frac_algorithmic": round(achieved_bytes / HBM_PEAK, 4),
         "mfma_frac_algorithmic": round(achieved_flops / PEAK[prec], 4),
     }
+    metric = "HOQRI iters/s & TTMcTC GFLOP/s, BF16 vs FP32 at equal fit; serve p50/p99"
+    if args.method == "hooi":
+        metric = f"HOOI iters/s ({args.inner_iters} orthogonal-iteration steps per mode update) on the HOQRI passes"
     line = {
-        "metric": "HOQRI iters/s & TTMcTC GFLOP/s, BF16 vs FP32 at equal fit; serve p50/p99",
+        "metric": metric,
         "value": round(sweeps / elapsed, 3),
         "unit": "iters/s",
         "n_gpus": 1,
@@ -339,17 +375,19 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[prec],
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "dims": list(dims), "ranks": list(ranks), "nnz": nnz,
-                   "sweeps": sweeps, "precision": prec},
+                   "sweeps": sweeps, "precision": prec, "method": args.method,
+                   **({"inner_iters": args.inner_iters} if args.method == "hooi" else {})},
         "ttmctc_gflops": round(achieved_flops / 1e9, 1),
         "kernel_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in kt.items()},
         "fit": st.fit,
         "orth_err_max": st.orth_err_max,
+        "skipped_updates": st.skipped_updates,
         "nonempty_slices": [int(r) for r in R],
         "plan_s": round(t_plan, 3),
         "input_gen_s": round(t_gen, 2),
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.method == "hoqri":
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         ncpu = min(nnz, 400_000)
         line["cpu_baseline"] = cpu_baseline(idx[:, :ncpu].cpu().numpy(), vals[:ncpu].cpu().numpy(), dims, ranks,

@@ -365,8 +365,13 @@ static void pass_sizes(int32_t N, const int32_t* K, int n, size_t* gtop, size_t*
   *gpart = (size_t)(B * 256 * 16 * KN2);
 }
 
+// Work ranges of a pass: about 3072 nonzeros each on large tensors; smaller
+// tensors are cut finer (down to 128 nonzeros) so that up to 2048 waves share
+// the work instead of a few dozen walking long ranges.
 static int32_t choose_ranges(int64_t nnz) {
   int64_t w = nnz / 3072;
+  const int64_t fine = std::min<int64_t>(nnz / 128, 2048);
+  if (w < fine) w = fine;
   if (w < 1) w = 1;
   if (w > 16384) w = 16384;
   return (int32_t)w;
@@ -470,6 +475,8 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     const int64_t ybytes = rows * Bc * 256 * 4;
     const int64_t stream = nnz * 4 * N;
     int64_t w = nnz / 4096;
+    const int64_t fine = std::min<int64_t>(nnz / 128, 2048);  // as choose_ranges
+    if (w < fine) w = fine;
     if (w < 1) w = 1;
     if (w > 8192) w = 8192;
     L->core_rows = (Bc <= 8 && ybytes <= std::max<int64_t>(2 * stream, 16 << 20)) ? 1 : 0;
