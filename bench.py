@@ -73,6 +73,12 @@ for _name, (_dims, _nnz, _rks) in TABLE3.items():
             prec="fp32", desc=f"stand-in with the shape of the {_name} tensor of Table 3 "
                               f"({'x'.join(map(str, _dims))}, nnz {_nnz}), Zipf(1.2) coordinates, lognormal(0,1) "
                               f"values, ranks {'x'.join(map(str, _k))}, FP32")
+# Fig. 5's 5-way random tensors: 80^5 with nnz = 10 I or 100 I, rank 10 per mode
+# (generic kernels: 10^4 Kronecker entries per nonzero)
+for _m in (10, 100):
+    CONFIGS[f"e4_{_m}I"] = dict(dims=(80,) * 5, ranks=(10,) * 5, nnz=_m * 80, dist="uniform", values="normal",
+                                seed=18, init_seed=118, prec="fp32",
+                                desc=f"5-way 80^5, nnz {_m * 80} uniform, N(0,1) values, ranks 10^5, FP32 (shape of Fig. 5)")
 # Fig. 1's random tensors: 3-way I x I x I with nnz = 10 I, rank 10^3 (uniform
 # coordinates, N(0,1) values: the paper gives no distribution)
 for _e in (3, 4, 5, 6):

@@ -57,7 +57,7 @@ typedef enum {
 
 /* Limits of this build: 2 <= N <= 4; 1 <= K_n <= 32; prod_{m!=n} K_m <= 2048;
  * nnz < 2^30; every I_n < 2^31 and I_n * K_n * 4 bytes < 2^32. */
-#define HOQRI_MAX_ORDER 4
+#define HOQRI_MAX_ORDER 5
 #define HOQRI_MAX_RANK 32
 
 typedef struct hoqri_plan hoqri_plan; /* opaque; host object pointing into the caller's workspace */

@@ -156,6 +156,9 @@ hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipS
 // orthogonal iteration when G = U^(mode)T Y_(mode).
 hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s);
 bool segpass_supported(const hoqri_plan* p, int mode);
+// Modes the segment passes do not take use the generic kernels (float32
+// operands; every rank <= 32).
+bool generic_supported(const hoqri_plan* p);
 // Power-of-two scales of the FP16 form for this plan (false: the values' range
 // does not allow them; use another precision).
 bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale);

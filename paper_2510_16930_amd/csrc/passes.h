@@ -53,7 +53,7 @@ struct PrepArgs {
   int32_t B, CB, KN2, krow, kcol, Kn, mode, N, nm1;
   int32_t om[3];          // other modes ascending
   int32_t Ko[3];          // their ranks
-  int64_t gstride[4];     // C-order strides of G
+  int64_t gstride[kMaxOrder];  // C-order strides of G
   int32_t nblk;           // blocks of this launch (grid-stride loop)
 };
 
@@ -71,7 +71,7 @@ struct CoreRedArgs {
   const float* gpart;
   int32_t groups, B, CB, KN2, krow, kcol, Kc, mode, nm1;
   int32_t om[3], Ko[3];
-  int64_t gstride[4];
+  int64_t gstride[kMaxOrder];
   float* G;
   double* fpart;
 };

@@ -352,6 +352,8 @@ hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, in
 
 // Stage-two operand size (floats) of the TTMcTC pass on mode n and the core
 // partial size (floats) of the core pass on mode n; see segpass_f32.hip.
+// Stage-two operand and core-partial sizes of mode n's segment pass (zero when
+// the shape is beyond the passes: then mode n takes the generic kernels).
 static void pass_sizes(int32_t N, const int32_t* K, int n, size_t* gtop, size_t* gpart) {
   int om[kMaxOrder];
   int no = other_modes(N, n, om);
@@ -361,6 +363,7 @@ static void pass_sizes(int32_t N, const int32_t* K, int n, size_t* gtop, size_t*
   int64_t RB = (krow + 15) / 16, CB = (kcol + 15) / 16;
   int64_t B = RB * CB;
   int64_t KN2 = (K[n] + 15) / 16;
+  if (B > 8 || K[n] > 32 || no > 3) B = 0;
   *gtop = (size_t)(B * KN2 * 4096);
   *gpart = (size_t)(B * 256 * 16 * KN2);
 }
@@ -442,7 +445,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     int64_t krow = 1;
     for (int q = 0; q < no - 1; ++q) krow *= K[om[q]];
     int64_t B = ((krow + 15) / 16) * ((K[om[no - 1]] + 15) / 16);
-    if (B > Bcore) Bcore = B;
+    if (B <= 8 && B > Bcore) Bcore = B;
   }
   int32_t groups = choose_core_groups(nnz, Bcore);
   int32_t rmax = 0;
@@ -506,7 +509,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
       int64_t krow = 1;
       for (int q = 0; q < no - 1; ++q) krow *= K[om[q]];
       const int64_t Bn = ((krow + 15) / 16) * ((K[om[no - 1]] + 15) / 16);
-      if (Bn > 8 || K[n] > 32) L->yfuse = 0;
+      if (Bn > 8 || K[n] > 32 || no > 3) L->yfuse = 0;
       const size_t rows = (size_t)(dims[n] < nnz ? dims[n] : nnz);
       yrows = std::max(yrows, rows);
       yrow = std::max(yrow, (size_t)Bn * 256);

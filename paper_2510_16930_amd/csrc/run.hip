@@ -57,9 +57,11 @@ __global__ void k_fill_f32(float* x, int64_t n, float v) {
 }
 
 // GG[p][q] = sum over the other indices of G(p, .) G(q, .) in mode n (float64).
-__global__ __launch_bounds__(256) void k_ggt(const float* G, int N, int mode, int32_t K0, int32_t K1, int32_t K2,
-                                             int32_t K3, double* GG) {
-  const int32_t Kd[4] = {K0, K1, K2, K3};
+struct Ranks {
+  int32_t K[kMaxOrder];
+};
+__global__ __launch_bounds__(256) void k_ggt(const float* G, int N, int mode, Ranks R, double* GG) {
+  const int32_t* Kd = R.K;
   const int Kn = Kd[mode];
   int64_t stride = 1, other = 1;
   for (int m = N - 1; m > mode; --m) stride *= Kd[m];
@@ -190,9 +192,9 @@ hoqri_status launch_grad(hoqri_plan* p, int mode, const float* A, const float* U
                          hipStream_t s) {
   double* GG = p->sc.gscr;
   double* part = p->sc.gscr + kMaxRank * kMaxRank;
-  int32_t Kd[4] = {1, 1, 1, 1};
-  for (int m = 0; m < p->N; ++m) Kd[m] = p->K[m];
-  hipLaunchKernelGGL(k_ggt, dim3(1), dim3(256), 0, s, G, p->N, mode, Kd[0], Kd[1], Kd[2], Kd[3], GG);
+  Ranks Kd{};
+  for (int m = 0; m < p->N; ++m) Kd.K[m] = p->K[m];
+  hipLaunchKernelGGL(k_ggt, dim3(1), dim3(256), 0, s, G, p->N, mode, Kd, GG);
   const int64_t total = p->dims[mode] * p->K[mode];
   int64_t nb = (total + 255) / 256;
   if (nb > kGradParts) nb = kGradParts;
@@ -247,7 +249,7 @@ extern "C" hoqri_status hoqri_sketch_start(hoqri_plan* p, const float* const* d_
   for (int n = 0; n < p->N; ++n)
     if (!d_Omega[n] || !d_U_out[n]) return HOQRI_ERR_ARG;
   for (int n = 0; n < p->N; ++n)
-    if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
+    if (!segpass_supported(p, n) && !generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
   for (int n = 0; n < p->N; ++n)
     if (p->md[n].R < p->K[n]) return HOQRI_ERR_BREAKDOWN;
   // the random factors in label order (the pass reads them there)
@@ -281,7 +283,7 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   int op = 0;
   HOQRI_TRY(check_prec(opts->prec, &op));
   for (int n = 0; n < p->N; ++n)
-    if (!segpass_supported(p, n)) return HOQRI_ERR_UNSUPPORTED;
+    if (!segpass_supported(p, n) && (op != OP_FP32 || !generic_supported(p))) return HOQRI_ERR_UNSUPPORTED;
   if (opts->method != HOQRI_METHOD_HOQRI && opts->method != HOQRI_METHOD_HOOI) return HOQRI_ERR_ARG;
   if (opts->inner_iters < 0 || opts->inner_iters > 1000) return HOQRI_ERR_ARG;
   const bool hooi = opts->method == HOQRI_METHOD_HOOI;

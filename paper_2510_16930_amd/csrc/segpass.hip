@@ -1063,10 +1063,130 @@ __global__ void k_sum_f_b(const SumArgs* d, const int32_t* first, int count) {
   sum_body(d[batch_item(first, count, blockIdx.x)]);
 }
 
+// ---------------------------------------------------------------------------
+// Generic kernels: any order N <= 5 and any ranks <= 32, for the shapes the
+// segment passes do not take (N = 5, or more than 8 16x16 tiles per y_i). They
+// read the same block records and slice tables, in float32 with float32
+// accumulation over a fixed order, and are sized for small tensors (one
+// workgroup walks one slice).
+// ---------------------------------------------------------------------------
+struct GenArgs {
+  const int32_t* rec;
+  const int32_t* seg_off;
+  const int32_t* seg_row;
+  int32_t R, N, nm1;
+  const float* U[kMaxOrder - 1];  // other modes ascending (label order)
+  int32_t Ko[kMaxOrder - 1];
+  int64_t gstride_o[kMaxOrder - 1];  // C-order strides of G along the other modes
+  int64_t gstride_n;
+  int32_t Kn;
+  int64_t P;                          // prod of the other ranks
+  const float* G;                     // TTMcTC: core
+  float* A;                           // TTMcTC: output rows by label (or out_map)
+  const int32_t* out_map;
+  const float* Uc;                    // core: factor of the pass mode
+  float* Gout;                        // core: C-order core
+};
+
+// Entry j' of a nonzero's Kronecker row (other modes ascending, last fastest):
+// x times the product of its factor-row entries.
+__device__ inline float gen_kron(const GenArgs& a, const int32_t* r, int t, int64_t jp) {
+  const int N = a.N;
+  float w = __int_as_float(r[4 * (N - 1) + t]);
+  int64_t rem = jp;
+  for (int c = a.nm1 - 1; c >= 0; --c) {
+    const int k = (int)(rem % a.Ko[c]);
+    rem /= a.Ko[c];
+    w *= a.U[c][(int64_t)r[4 * c + t] + k];  // stored offsets are label * K_m
+  }
+  return w;
+}
+
+// y_s(j') for slice s, in the order of the slice's nonzeros
+__device__ inline float gen_slice_y(const GenArgs& a, int32_t s, int64_t jp) {
+  float y = 0.f;
+  for (int32_t e = a.seg_off[s]; e < a.seg_off[s + 1]; ++e) {
+    const int32_t* r = a.rec + (int64_t)(e >> 4) * 16 * a.N + (e & 3) * 4 * a.N;
+    y += gen_kron(a, r, (e & 15) >> 2, jp);
+  }
+  return y;
+}
+
+// TTMcTC: one workgroup per slice; thread t takes j' = t, t + 256, ... and
+// keeps partial sums of A(s, kn) = sum_j' y_s(j') G_(n)(kn, j'), reduced over
+// the threads in a fixed tree.
+__global__ __launch_bounds__(256) void k_ttm_generic(GenArgs a) {
+  __shared__ float red[256];
+  const int32_t s = blockIdx.x;
+  float acc[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+  for (int64_t jp = threadIdx.x; jp < a.P; jp += 256) {
+    const float y = gen_slice_y(a, s, jp);
+    int64_t goff = 0, rem = jp;
+    for (int c = a.nm1 - 1; c >= 0; --c) {
+      goff += (rem % a.Ko[c]) * a.gstride_o[c];
+      rem /= a.Ko[c];
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if (k < a.Kn) acc[k] += y * a.G[goff + k * a.gstride_n];
+  }
+  const int32_t row = a.out_map ? a.out_map[a.seg_row[s]] : a.seg_row[s];
+  for (int k = 0; k < a.Kn; ++k) {
+    red[threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.A[(int64_t)row * a.Kn + k] = red[0];
+    __syncthreads();
+  }
+}
+
+// Core: one thread per entry j' of G_(c); it walks every slice s and adds
+// U^(c)(s, kc) y_s(j') for all kc (slices and nonzeros in stream order), so
+// every core entry has one writer and a fixed order.
+__global__ __launch_bounds__(256) void k_core_generic(GenArgs a) {
+  const int64_t jp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (jp >= a.P) return;
+  float acc[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+  for (int32_t s = 0; s < a.R; ++s) {
+    const float y = gen_slice_y(a, s, jp);
+    const float* u = a.Uc + (int64_t)a.seg_row[s] * a.Kn;
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if (k < a.Kn) acc[k] += u[k] * y;
+  }
+  int64_t goff = 0, rem = jp;
+  for (int c = a.nm1 - 1; c >= 0; --c) {
+    goff += (rem % a.Ko[c]) * a.gstride_o[c];
+    rem /= a.Ko[c];
+  }
+  for (int k = 0; k < a.Kn; ++k) a.Gout[goff + k * a.gstride_n] = acc[k];
+}
+
+// ||G||^2 in float64 by one workgroup (fixed order)
+__global__ __launch_bounds__(256) void k_sumsq(const float* G, int64_t n, double* out) {
+  __shared__ double sh[256];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) t += (double)G[i] * (double)G[i];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 struct PassGeom {
   int nm1;
-  int om[3];
-  int Ko[3];
+  int om[kMaxOrder];
+  int Ko[kMaxOrder];
   int krow, kcol, RB, CB, B;
 };
 
@@ -1179,7 +1299,7 @@ void g_strides(const hoqri_plan* p, int64_t* st) {
 
 bool segpass_supported(const hoqri_plan* p, int mode) {
   PassGeom g = geom(p, mode);
-  return g.B <= 8 && p->K[mode] <= 32;
+  return g.nm1 <= 3 && g.B <= 8 && p->K[mode] <= 32;
 }
 
 bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale) {
@@ -1381,8 +1501,59 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
   return HOQRI_OK;
 }
 
+namespace {
+GenArgs gen_args(const hoqri_plan* p, int mode) {
+  GenArgs a{};
+  const ModeData& md = p->md[mode];
+  a.rec = md.rec;
+  a.seg_off = md.seg_off;
+  a.seg_row = md.seg_row;
+  a.R = (int32_t)md.R;
+  a.N = p->N;
+  int om[kMaxOrder];
+  a.nm1 = other_modes(p->N, mode, om);
+  int64_t st[kMaxOrder];
+  g_strides(p, st);
+  a.P = 1;
+  for (int c = 0; c < a.nm1; ++c) {
+    a.U[c] = p->sc.Up[om[c]];
+    a.Ko[c] = p->K[om[c]];
+    a.gstride_o[c] = st[om[c]];
+    a.P *= p->K[om[c]];
+  }
+  a.gstride_n = st[mode];
+  a.Kn = p->K[mode];
+  return a;
+}
+}  // namespace
+
+bool generic_supported(const hoqri_plan* p) {
+  for (int n = 0; n < p->N; ++n)
+    if (p->K[n] > 32) return false;
+  return true;
+}
+
 hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
                            const int32_t* out_map, hipStream_t s, bool rows) {
+  if (!segpass_supported(p, mode)) {
+    // generic kernel: float32 operands only, no stored rows
+    if (rows || op.prec != OP_FP32 || !generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
+    GenArgs a = gen_args(p, mode);
+    a.G = G;
+    a.A = A;
+    a.out_map = out_map;
+    TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
+    if (a.R > 0) hipLaunchKernelGGL(k_ttm_generic, dim3((unsigned)a.R), dim3(256), 0, s, a);
+    const ModeData& md = p->md[mode];
+    if (md.E > 0) {
+      int64_t tot = md.E * p->K[mode];
+      int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+      hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, out_map ? md.empty_row : (const int32_t*)nullptr,
+                         md.R, md.E, p->K[mode], A);
+    }
+    HOQRI_HIP_TRY(hipGetLastError());
+    return HOQRI_OK;
+  }
   TtmJob job;
   HOQRI_TRY(prepare_ttm(p, mode, op, G, A, out_map, &job, rows));
   SegKernels k;
@@ -1412,6 +1583,19 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
 }
 
 hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, hipStream_t s) {
+  if (!segpass_supported(p, p->core_mode)) {
+    if (op.prec != OP_FP32 || !generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
+    GenArgs a = gen_args(p, p->core_mode);
+    a.Uc = op.U32[p->core_mode];
+    a.Gout = G;
+    int64_t PK = 1;
+    for (int n = 0; n < p->N; ++n) PK *= p->K[n];
+    TimerScope ts(p, HOQRI_KERNEL_CORE, s);
+    hipLaunchKernelGGL(k_core_generic, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, s, (const float*)G, PK, f_out ? f_out : p->sc.f_dev);
+    HOQRI_HIP_TRY(hipGetLastError());
+    return HOQRI_OK;
+  }
   CoreJob job;
   HOQRI_TRY(prepare_core(p, op, G, f_out, &job));
   SegKernels k;

@@ -51,7 +51,8 @@ def _ws(lib, order, dims, ranks, nnz):
 def test_argument_validation_before_device_work(lib):
     # order out of range, nnz < 1, bad dims -> ERR_ARG; bad ranks -> ERR_RANK; K > 32 -> UNSUPPORTED
     assert _ws(lib, 1, [10], [2], 5) == -1
-    assert _ws(lib, 5, [4] * 5, [2] * 5, 5) == -1
+    assert _ws(lib, 6, [4] * 6, [2] * 6, 5) == -1
+    assert _ws(lib, 5, [4] * 5, [2] * 5, 5) != -1  # order 5 is taken (generic kernels)
     assert _ws(lib, 3, [10, 10, 10], [2, 2, 2], 0) == -1
     assert _ws(lib, 3, [10, 0, 10], [2, 2, 2], 5) == -1
     assert _ws(lib, 3, [10, 10, 10], [11, 2, 2], 5) == -3     # K > I
