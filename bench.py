@@ -237,6 +237,11 @@ def bench_serve(args, cfg):
     arrivals = synth.poisson_arrivals(n, rate, cfg["seed"] + 1)
     res, lat, wall, steps = one_pass(arrivals, f"Poisson pass at {rate:.1f} requests/s")
     L = np.array([lat[i] for i in range(n)]) * 1e3
+    # a lighter load as well (half the saturated rate)
+    rate_lo = 0.5 * mu
+    _, lat_lo, wall_lo, _ = one_pass(synth.poisson_arrivals(n, rate_lo, cfg["seed"] + 2),
+                                     f"Poisson pass at {rate_lo:.1f} requests/s")
+    L_lo = np.array([lat_lo[i] for i in range(n)]) * 1e3
     sweeps = np.array([res[i].sweeps for i in range(n)])
     line = {
         "metric": "HOQRI iters/s & TTMcTC GFLOP/s, BF16 vs FP32 at equal fit; serve p50/p99",
@@ -256,6 +261,9 @@ def bench_serve(args, cfg):
         "p50_ms": round(float(np.percentile(L, 50)), 3),
         "p99_ms": round(float(np.percentile(L, 99)), 3),
         "arrival_rate_per_s": round(rate, 3),
+        "load_0.5": {"arrival_rate_per_s": round(rate_lo, 3), "tensors_per_s": round(n / wall_lo, 3),
+                     "p50_ms": round(float(np.percentile(L_lo, 50)), 3),
+                     "p99_ms": round(float(np.percentile(L_lo, 99)), 3)},
         "saturated_tensors_per_s": round(mu, 3),
         "saturated_p50_ms": round(float(np.percentile(np.array(list(lat0.values())) * 1e3, 50)), 3),
         "sweeps_mean": round(float(sweeps.mean()), 2),
