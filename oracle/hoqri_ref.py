@@ -79,6 +79,8 @@ __all__ = [
     "sketch_start",
     "leading_left",
     "hooi",
+    "core_entry",
+    "ttmctc_slice_row",
 ]
 
 BREAKDOWN_REL = 1e-13
@@ -309,6 +311,38 @@ def ttmctc_segment(idx, vals, Us: Sequence[np.ndarray], n: int, G: np.ndarray) -
     A = np.zeros((Us[n].shape[0], Us[n].shape[1]))
     A[rows] = Yr @ unfold(G, n).T
     return A
+
+
+def core_entry(idx, vals, Us: Sequence[np.ndarray], ks: Sequence[int]) -> float:
+    """One entry G(k_1, ..., k_N) = sum_e x_e prod_m U^(m)(i_m^e, k_m) of the core
+    (§2.2), as one sum over all nonzeros (for sampling large tensors)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    t = np.asarray(vals, dtype=np.float64).copy()
+    for m, k in enumerate(ks):
+        t *= Us[m][idx[m], k]
+    return float(t.sum())
+
+
+def ttmctc_slice_row(idx, vals, Us: Sequence[np.ndarray], n: int, i: int, G: np.ndarray,
+                     chunk: int = 1 << 20) -> np.ndarray:
+    """Row i of A^(n) = Y_(n) G_(n)^T (definition in §4.1) from slice i's
+    nonzeros only: y_i = sum over the slice of x_e (Kronecker over m != n of
+    U^(m)(i_m^e, :)), with the last Kronecker factor contracted by a matrix
+    product over the nonzeros (chunks of `chunk`), then y_i G_(n)^T."""
+    idx = np.asarray(idx, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    sel = np.flatnonzero(idx[n] == i)
+    others = [m for m in range(len(Us)) if m != n]
+    first, last = others[:-1], others[-1]
+    P1 = math.prod(Us[m].shape[1] for m in first)
+    y = np.zeros((P1, Us[last].shape[1]))
+    for s in range(0, sel.size, chunk):
+        e = sel[s:s + chunk]
+        W = vals[e][:, None]
+        for m in first:
+            W = (W[:, :, None] * Us[m][idx[m, e]][:, None, :]).reshape(e.size, -1)
+        y += W.T @ Us[last][idx[last, e]]
+    return y.reshape(-1) @ unfold(G, n).T
 
 
 def core_segment(idx, vals, Us: Sequence[np.ndarray], n: int = 0) -> np.ndarray:

@@ -88,6 +88,22 @@ def test_three_ttmctc_forms_match_dense_brute_force(dims, K):
         np.testing.assert_allclose(O.core_segment(idx, vals, U, n), Gd, atol=1e-13)
 
 
+@pytest.mark.parametrize("dims,K", [((5, 4, 6), (2, 3, 2)), ((3, 4, 2, 3), (2, 2, 2, 2))])
+def test_sampled_entries_match_dense_brute_force(dims, K):
+    # the one-entry core and one-row TTMcTC forms used to sample large outputs
+    idx, vals, U = _tiny(dims, K, min(30, math.prod(dims) // 2), seed=17)
+    X = O.to_dense(idx, vals, dims)
+    Gd = O.core_dense(X, U)
+    for ks in itertools.product(*[range(k) for k in K]):
+        assert O.core_entry(idx, vals, U, ks) == pytest.approx(Gd[ks], abs=1e-13)
+    for n in range(len(dims)):
+        Ad = O.ttmctc_dense(X, U, n)
+        for i in range(dims[n]):
+            for chunk in (1, 1 << 20):
+                np.testing.assert_allclose(O.ttmctc_slice_row(idx, vals, U, n, i, Gd, chunk=chunk),
+                                           Ad[i], atol=1e-13)
+
+
 def test_single_nonzero_closed_forms():
     # One nonzero x at i: G = x (x)_m U_m(i_m,:), and
     # A^(n)(i_n,:) = x^2 prod_{m!=n} ||U_m(i_m,:)||^2 U_n(i_n,:); other rows zero.
