@@ -55,6 +55,7 @@ struct PrepArgs {
   int32_t Ko[3];          // their ranks
   int64_t gstride[kMaxOrder];  // C-order strides of G
   int32_t nblk;           // blocks of this launch (grid-stride loop)
+  int32_t wide16;         // 1: bfloat16 operand of the 2 x 2-block BF16 pass (its own layout)
 };
 
 struct FixArgs {

@@ -66,6 +66,14 @@ __device__ inline i4 ld_i4(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff
   return __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0);
 }
 
+// Wave-uniform read of p[i] through the scalar cache (read-only data written
+// before the launch): it is counted apart from the vector loads in flight, so
+// waiting for it does not wait for them.
+__device__ inline int32_t scalar_ld(const int32_t* p, int32_t i) {
+  typedef const __attribute__((address_space(4))) int32_t* cptr;
+  return ((cptr)p)[__builtin_amdgcn_readfirstlane(i)];
+}
+
 // Orders this wave's LDS writes before its later LDS reads (no cross-wave sync).
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -339,11 +347,16 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   };
 
   PipeSet<NM1> S0, S1, S2;
+  // prologue in the loop's own issue order (the record of b+2 ahead of the
+  // rows of b+1), held by scheduling barriers: the wait at the loop head then
+  // covers only the loads the body needs instead of every load in flight
   load_idx(b0, S0);
   load_idx(b0 + 1, S1);
-  load_idx(b0 + 2, S2);
   gather(S0);
+  load_idx(b0 + 2, S2);
+  __builtin_amdgcn_sched_barrier(0);
   gather(S1);
+  __builtin_amdgcn_sched_barrier(0);
   for (int32_t ib = 0; ib < nblk; ib += 3) {
     step(b0 + ib, S0, S2, 0);
     if (done || ib + 1 >= nblk) break;
@@ -495,7 +508,7 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
       int kind = KIND_COMPLETE;
       if (s == s_first && head_clip) kind = KIND_HEAD;
       else if (s == s_last && tail_clip) kind = KIND_TAIL;
-      slot_row[slot] = a.out_map ? a.out_map[row] : row;
+      slot_row[slot] = a.out_map ? scalar_ld(a.out_map, row) : row;
       slot_kind[slot] = kind;
     }
     if (++slot == SLOTS) stage_two();
@@ -526,6 +539,293 @@ template <int NM1, int KN2, int PREC>
 __global__ __launch_bounds__(512) void k_ttm_b(const SegArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
   ttm_body<NM1, KN2, PREC>(d[r], blockIdx.x - first[r]);
+}
+
+// ---------------------------------------------------------------------------
+// TTMcTC pass, BF16 form, for a y_i of 2 x 2 blocks (3-way tensors whose two
+// other ranks both lie in 17..32): one wave computes all four 16x16 blocks of
+// y_i, so every nonzero's record is read and its factor rows are gathered once
+// per range instead of once per block and wave. Block (rb, cb) multiplies
+// entries 16 rb + q of the first and 16 cb + q of the second other factor;
+// lane group g holds the k-slots 4g + t as in walk_range. A finished y_i is
+// staged in LDS in bfloat16 and multiplied by G_(n)^T (bfloat16 copy) on the
+// matrix cores with float32 accumulation; the stored slice rows of Y_(n) stay
+// float32 and are written straight from the accumulators.
+// ---------------------------------------------------------------------------
+constexpr int kYs22 = 1024 + 16;  // LDS entries per staged y_i (the pad puts slots 8 banks apart)
+__host__ __device__ constexpr int ttm22_wave_bytes(int slots) { return slots * kYs22 * 2 + (2 * slots + 128) * 4; }
+
+template <typename OnSeg>
+__device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
+                                    uint32_t k2, int lane, int32_t* wlds, OnSeg&& on_seg) {
+  constexpr int NM1 = 2;
+  constexpr int GD = 4 * (NM1 + 1);
+  const int g = lane >> 4;
+  const auto rRec = make_rsrc(a.rec, (uint32_t)a.nnz_pad * 4u * (NM1 + 1));
+  const int qd = (lane & 15) < GD ? (lane & 15) : GD - 1;
+  const uint32_t goff = (uint32_t)(g * GD + qd) * 4u;
+  const auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
+  const auto rU1 = make_rsrc(a.U[1], a.Ubytes[1]);
+
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  s_first = __builtin_amdgcn_readfirstlane(s_first);
+  s_last = __builtin_amdgcn_readfirstlane(s_last);
+  const int32_t b0 = lo >> 4;
+  const int32_t nblk = ((hi - 1) >> 4) - b0 + 1;
+  const int32_t bmax = (a.nnz_pad >> 4) - 1;
+
+  // raw bfloat16 entries of k-slots t = 0..3, one per register: packing them
+  // where they are loaded would make the loop wait for loads still in flight
+  struct Set {
+    int32_t rec;
+    uint32_t ga[2][4];  // first other factor, entry 16 rb + q
+    uint32_t gb[2][4];  // second other factor, entry 16 cb + q
+  };
+  auto load_idx = [&](int32_t blk, Set& S) {
+    blk = blk <= bmax ? blk : bmax;
+    S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
+  };
+  // the record holds element offsets of the rows; entries 16..31 sit 32 bytes on
+  auto gather = [&](Set& S) {
+    struct {
+      i4 j0, j1;
+    } J{group_quad<0>(S.rec), group_quad<1>(S.rec)};
+    auto& SJ = J;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t oa = ((uint32_t)SJ.j0[t] << 1) + k2;
+      const uint32_t ob = ((uint32_t)SJ.j1[t] << 1) + k2;
+      S.ga[0][t] = ld_u16(rU0, oa);
+      S.ga[1][t] = ld_u16(rU0, oa + 32u);
+      S.gb[0][t] = ld_u16(rU1, ob);
+      S.gb[1][t] = ld_u16(rU1, ob + 32u);
+    }
+  };
+
+  SegWindow win;
+  win.off = wlds;
+  win.row = wlds + 64;
+  win.load(a, s_first, lane);
+  int32_t s = s_first;
+  int32_t seg_lo = lo;
+  int32_t seg_hi = win.get_off(s_first + 1);
+  seg_hi = __builtin_amdgcn_readfirstlane(seg_hi < hi ? seg_hi : hi);
+  f4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+  bool done = false;
+
+  auto step = [&](int32_t blk, Set& C, Set& N2) {
+    float xa[2][4];
+    const s4 xb0 = {(short)C.gb[0][0], (short)C.gb[0][1], (short)C.gb[0][2], (short)C.gb[0][3]};
+    const s4 xb1 = {(short)C.gb[1][0], (short)C.gb[1][1], (short)C.gb[1][2], (short)C.gb[1][3]};
+    const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) xa[h][t] = xq[t] * f16bits_to_f32<P_BF16>(C.ga[h][t]);
+    }
+    load_idx(blk + 3, C);
+    gather(N2);
+    const int32_t eb = blk * 16;
+    auto product = [&](float (*av)[4]) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const b4 ab = {(__bf16)av[rb][0], (__bf16)av[rb][1], (__bf16)av[rb][2], (__bf16)av[rb][3]};
+        const s4 as = __builtin_bit_cast(s4, ab);
+        acc[2 * rb + 0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as, xb0, acc[2 * rb + 0], 0, 0, 0);
+        acc[2 * rb + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as, xb1, acc[2 * rb + 1], 0, 0, 0);
+      }
+    };
+    if (__builtin_expect(seg_lo <= eb && seg_hi > eb + 16, 1)) {
+      product(xa);
+    } else {
+      while (!done && seg_lo < eb + 16) {
+        float am[2][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int32_t e = eb + 4 * t + g;
+          const bool in = e >= seg_lo && e < seg_hi;
+          am[0][t] = in ? xa[0][t] : 0.f;
+          am[1][t] = in ? xa[1][t] : 0.f;
+        }
+        product(am);
+        if (seg_hi > eb + 16) break;
+        f4 y[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          y[b] = acc[b];
+          acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+        on_seg(s, win.get_row(s), y);
+        s = __builtin_amdgcn_readfirstlane(s + 1);
+        if (s > s_last) {
+          done = true;
+        } else {
+          if (s + 1 - win.base >= 64) win.load(a, s, lane);
+          seg_lo = win.get_off(s);
+          const int32_t nx = win.get_off(s + 1);
+          seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+        }
+      }
+    }
+  };
+
+  Set S0, S1, S2;
+  // prologue in the loop's own issue order (the record of b+2 ahead of the
+  // rows of b+1), held by scheduling barriers: the wait at the loop head then
+  // covers only the loads the body needs instead of every load in flight
+  load_idx(b0, S0);
+  load_idx(b0 + 1, S1);
+  gather(S0);
+  load_idx(b0 + 2, S2);
+  __builtin_amdgcn_sched_barrier(0);
+  gather(S1);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int32_t ib = 0; ib < nblk; ib += 3) {
+    step(b0 + ib, S0, S2);
+    if (done || ib + 1 >= nblk) break;
+    step(b0 + ib + 1, S1, S0);
+    if (done || ib + 2 >= nblk) break;
+    step(b0 + ib + 2, S2, S1);
+    if (done) break;
+  }
+}
+
+// The pass itself: one wave per range, SL slices staged per stage-two product.
+// Stage two reads the bfloat16 operand gtop16[kb][64][lane][4] with
+// gtop16[kb][16 b + u][lane][t] = G_(n)^T[256 b + 16 u + 4 (lane/16) + t][16 kb + lane%16]
+// (inside block b, index c*16 + r), which k_prep_gtop writes for this pass.
+// The workgroup first copies it into LDS (KN2 x 32 KB): every stage two reads
+// all of it, and from LDS that costs a short latency instead of an L2 round
+// trip per step.
+template <int KN2, int SL>
+__device__ inline void ttm22_body(const SegArgs& a, const int wg) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int g = lane >> 4, q = lane & 15;
+  const int32_t w = wg * a.RPW + wv;
+  uint16_t* gl = reinterpret_cast<uint16_t*>(lds);
+  char* base = reinterpret_cast<char*>(lds) + KN2 * 32768 + wv * ttm22_wave_bytes(SL);
+  uint16_t* ybat = reinterpret_cast<uint16_t*>(base);
+  int32_t* slot_row = reinterpret_cast<int32_t*>(base + SL * kYs22 * 2);
+  int32_t* slot_kind = slot_row + SL;
+  int32_t* wlds = slot_kind + SL;  // slice-table window of this wave
+  {
+    const i4* src = reinterpret_cast<const i4*>(a.gtop);
+    i4* dst = reinterpret_cast<i4*>(gl);
+    for (int i = threadIdx.x; i < KN2 * 2048; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+  }
+  if (w >= a.W) return;  // past the barrier: the waves are independent from here
+
+  const int32_t lo = range_lo(w, a.W, a.nnz);
+  const int32_t hi = range_lo(w + 1, a.W, a.nnz);
+  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
+  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  const bool head_clip = a.seg_off[s_first] < lo;
+  const bool tail_clip = a.seg_off[s_last + 1] > hi;
+  if (lane == 0) {
+    a.meta[w * 4 + 0] = s_first;
+    a.meta[w * 4 + 1] = s_last;
+    a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
+    a.meta[w * 4 + 3] = 0;
+  }
+  const uint16_t* gt = gl + lane * 4;
+  constexpr uint32_t yrowf = 1024;  // floats per stored row (4 blocks)
+
+  int slot = 0;
+  auto stage_two = [&]() {
+    wave_sync();
+    f4 d[KN2];
+#pragma unroll
+    for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
+    // rows q >= SL of the product re-read staged rows and are not used
+    const uint16_t* yr = ybat + (q % SL) * kYs22 + 4 * g;
+#pragma unroll 4
+    for (int bu = 0; bu < 64; ++bu) {
+      const s4 av = *reinterpret_cast<const s4*>(yr + 16 * bu);
+#pragma unroll
+      for (int kb = 0; kb < KN2; ++kb) {
+        const s4 bv = *reinterpret_cast<const s4*>(gt + (kb * 64 + bu) * 256);
+        d[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, d[kb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int sl = 4 * g + v;
+      if (sl < slot) {
+        const int32_t row = slot_row[sl];
+        const int kind = slot_kind[sl];
+#pragma unroll
+        for (int kb = 0; kb < KN2; ++kb) {
+          const int kn = 16 * kb + q;
+          if (kn < a.Kn) {
+            const float val = d[kb][v];
+            if (kind == KIND_COMPLETE) a.A[(size_t)row * a.Kn + kn] = val;
+            else a.carry[((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
+          }
+        }
+      }
+    }
+    wave_sync();
+    slot = 0;
+  };
+
+  walk_range22(a, lo, hi, s_first, s_last, (uint32_t)q * 2u, lane, wlds,
+                       [&](int32_t s, int32_t row, const f4* y) {
+    int kind = KIND_COMPLETE;
+    if (s == s_first && head_clip) kind = KIND_HEAD;
+    else if (s == s_last && tail_clip) kind = KIND_TAIL;
+    // stage y_s in bfloat16 (nearest even), block b at 256 b + c*16 + r
+    uint16_t* ys = ybat + slot * kYs22 + q * 16 + 4 * g;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const b4 v = {(__bf16)y[b].x, (__bf16)y[b].y, (__bf16)y[b].z, (__bf16)y[b].w};
+      *reinterpret_cast<s4*>(ys + 256 * b) = __builtin_bit_cast(s4, v);
+    }
+    if (lane == 0) {
+      slot_row[slot] = a.out_map ? scalar_ld(a.out_map, row) : row;
+      slot_kind[slot] = kind;
+    }
+    if (a.yrow) {
+      // the float32 y_s for the core of the updated factor: row by label; a
+      // split slice leaves its partial per range and zeros in its own row
+      const uint32_t vo = (uint32_t)(q * 16 + 4 * g) * 4u;
+      const auto own = make_rsrc(a.yrow + (size_t)row * yrowf, yrowf * 4u);
+      if (kind == KIND_COMPLETE) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, y[b]), own, vo + 1024u * b, 0, 0);
+      } else {
+        const auto dst = make_rsrc(a.ycarry + ((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * yrowf, yrowf * 4u);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, y[b]), dst, vo + 1024u * b, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(i4{0, 0, 0, 0}, own, vo + 1024u * b, 0, 0);
+        }
+      }
+    }
+    if (++slot == SL) stage_two();
+  });
+  if (slot > 0) stage_two();
+}
+
+// One workgroup per CU: the core operand plus up to 12 waves (three per SIMD,
+// what the registers allow; holding the pass to 128 registers spills in the
+// per-slice path and runs slower on short slices), four staged slices each.
+constexpr int kSlots22 = 4;
+constexpr int kMaxRpw22 = 12;
+
+template <int KN2>
+__global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22(SegArgs a) {
+  ttm22_body<KN2, kSlots22>(a, blockIdx.x);
+}
+template <int KN2>
+__global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  ttm22_body<KN2, kSlots22>(d[r], blockIdx.x - first[r]);
 }
 
 // Adds the partial rows of slices that cross range boundaries and writes them.
@@ -603,13 +903,22 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
   const int64_t total = (int64_t)p.B * p.KN2 * 4096;
   for (int64_t idx = blk * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)p.nblk * blockDim.x) {
-    const int t = (int)(((idx >> 8) & 15) * 4 + (idx & 3));
     const int lane = (int)((idx >> 2) & 63);
-    const int64_t rest = idx >> 12;
-    const int kb = (int)(rest % p.KN2);
-    const int b = (int)(rest / p.KN2);
+    int kb, b, jp;
+    if (p.wide16) {
+      // [kb][16 b + u][lane][t]: index 16 u + 4 (lane/16) + t inside block b
+      const int bu = (int)((idx >> 8) & 63);
+      kb = (int)(idx >> 14);
+      b = bu >> 4;
+      jp = 16 * (bu & 15) + 4 * (lane >> 4) + (int)(idx & 3);
+    } else {
+      const int t = (int)(((idx >> 8) & 15) * 4 + (idx & 3));
+      const int64_t rest = idx >> 12;
+      kb = (int)(rest % p.KN2);
+      b = (int)(rest / p.KN2);
+      jp = 64 * (lane >> 4) + t;
+    }
     const int rb = b / p.CB, cb = b % p.CB;
-    const int jp = 64 * (lane >> 4) + t;
     const int c = jp >> 4, r = jp & 15;
     const int rg = 16 * rb + r, cg = 16 * cb + c;
     const int kn = 16 * kb + (lane & 15);
@@ -624,7 +933,8 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
       }
       v = p.G[off];
     }
-    p.gtop[idx] = v;
+    if (p.wide16) reinterpret_cast<uint16_t*>(p.gtop)[idx] = __builtin_bit_cast(uint16_t, (__bf16)v);
+    else p.gtop[idx] = v;
   }
 }
 
@@ -1227,6 +1537,9 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   return true;
 }
 
+// Key offset of the 2 x 2-block BF16 TTMcTC pass (core keys add 1000).
+constexpr int kWideKey = 2000;
+
 // Kernel instances: one single-plan and one batched launch per
 // (order, rank blocks, precision).
 struct SegKernels {
@@ -1262,12 +1575,42 @@ bool seg_kernels_p(int nm1, int kn2, SegKernels* k) {
 }
 
 bool seg_kernels(int key, SegKernels* k) {
+  const bool wide = key >= kWideKey;
+  if (wide) key -= kWideKey;
   key %= 1000;
   const int nm1 = key / 100, kn2 = (key / 10) % 10, prec = key % 10;
-  if (prec == P_FP32) return seg_kernels_p<P_FP32>(nm1, kn2, k);
-  if (prec == P_BF16) return seg_kernels_p<P_BF16>(nm1, kn2, k);
-  if (prec == P_FP16) return seg_kernels_p<P_FP16>(nm1, kn2, k);
-  return false;
+  bool ok = false;
+  if (prec == P_FP32) ok = seg_kernels_p<P_FP32>(nm1, kn2, k);
+  else if (prec == P_BF16) ok = seg_kernels_p<P_BF16>(nm1, kn2, k);
+  else if (prec == P_FP16) ok = seg_kernels_p<P_FP16>(nm1, kn2, k);
+  if (!ok || !wide) return ok;
+  if (nm1 != 2 || prec != P_BF16) return false;
+  if (kn2 == 1) {
+    k->ttm = (const void*)k_ttm22<1>;
+    k->ttm_b = (const void*)k_ttm22_b<1>;
+  } else {
+    k->ttm = (const void*)k_ttm22<2>;
+    k->ttm_b = (const void*)k_ttm22_b<2>;
+  }
+  return true;
+}
+
+// The 2 x 2-block pass takes the BF16 form of 3-way tensors whose two other
+// ranks both lie in 17..32.
+bool ttm_wide(const PassGeom& g, int prec) { return prec == OP_BF16 && g.nm1 == 2 && g.RB == 2 && g.CB == 2; }
+
+// Waves (ranges) per workgroup of that pass: as many as the LDS of one
+// workgroup holds next to the core operand, at most kMaxRpw22.
+int rpw22(int KN2) {
+  static int lds_max = 0;
+  if (lds_max == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    lds_max = v;
+  }
+  int r = (lds_max - KN2 * 32768) / ttm22_wave_bytes(kSlots22);
+  return r > kMaxRpw22 ? kMaxRpw22 : (r < 1 ? 1 : r);
 }
 
 hipError_t set_shmem(const void* k, size_t shmem) {
@@ -1334,9 +1677,11 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   const int KN2 = (p->K[mode] + 15) / 16;
   const ModeData& md = p->md[mode];
   *job = TtmJob{};
-  job->key = seg_key(g.nm1, KN2, op.prec);
+  const bool wide = ttm_wide(g, op.prec);
+  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0);
   // stage-two operand
   PrepArgs& pa = job->prep;
+  pa.wide16 = wide ? 1 : 0;
   pa.G = G;
   pa.gtop = p->sc.gtop;
   pa.B = g.B;
@@ -1362,7 +1707,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   int64_t W = md.ranges;
   if (W > p->nnz) W = p->nnz;
   a.W = (int32_t)W;
-  a.RPW = g.B == 1 ? 4 : 1;
+  a.RPW = wide ? rpw22(KN2) : (g.B == 1 ? 4 : 1);
   a.gtop = p->sc.gtop;
   a.A = A;
   a.Kn = p->K[mode];
@@ -1371,8 +1716,9 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   a.out_map = out_map;
   a.yrow = rows ? p->sc.ybuf : nullptr;
   a.ycarry = rows ? p->sc.ycarry : nullptr;
-  job->threads = 64 * g.B * a.RPW;
-  job->shmem = (size_t)ttm_lds_floats(a, KN2) * 4;
+  job->threads = wide ? 64 * a.RPW : 64 * g.B * a.RPW;
+  job->shmem = wide ? (size_t)KN2 * 32768 + (size_t)a.RPW * ttm22_wave_bytes(kSlots22)
+                    : (size_t)ttm_lds_floats(a, KN2) * 4;
   job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
   // split slices
   FixArgs& f = job->fix;

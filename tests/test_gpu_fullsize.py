@@ -13,7 +13,9 @@ factors orthonormal with f = ||G||^2 of the returned core.
 
 Tolerances: FP32 accumulation over up to 4M terms per slice row: 1e-5
 relative (Frobenius over the sampled outputs); BF16 form: the rounding bound of
-test_gpu_prec (|A_gpu - A| <= (N 2^-8 + 2e-5) |.|-instance) on the sampled rows.
+test_gpu_prec on the sampled values (core: N 2^-8 + 2e-5 times the
+|.|-instance; TTMcTC rows at ranks 32^3: (N + 2) 2^-8 + 2e-5, since y_i and the
+core are rounded to bfloat16 for their product).
 """
 import numpy as np
 import pytest
@@ -89,7 +91,8 @@ def test_fullsize_core_entries_and_slice_rows(tensor, K, prec):
                 assert rel(row, want) < 1e-5, (n, i)
             else:
                 wabs = O.ttmctc_slice_row(ih, np.abs(vh), Uabs, n, i, np.abs(G64))
-                lim = (3 * 2.0 ** -8 + 2e-5) * wabs + 1e-9 * wabs.max()
+                # y_i and the core are rounded to bfloat16 for their product too
+                lim = (5 * 2.0 ** -8 + 2e-5) * wabs + 1e-9 * wabs.max()
                 assert np.all(np.abs(row - want) <= lim), (n, i)
     plan.destroy()
 
