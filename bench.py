@@ -89,6 +89,17 @@ for _e in (3, 4, 5, 6):
                                       f"(shape of Fig. 1)")
 
 
+def ttm_kernel_name(dims, ranks, prec):
+    """The TTMcTC kernel the library picks: one wave for all of y_i in the BF16
+    form of 3-way tensors whose other ranks lie in 17..32, else one wave per
+    16x16 block of y_i."""
+    N = len(dims)
+    wide = prec == "bf16" and N == 3 and all(16 < ranks[m] <= 32 for m in range(N))
+    if wide:
+        return "k_ttm22<bf16> (TTMcTC segment pass, 2x2 blocks of y_i per wave)"
+    return f"k_ttm<{prec}> (TTMcTC segment pass)"
+
+
 def pass_work(dims, ranks, nnz, R, su=4):
     """Algorithmic flops and HBM bytes of one TTMcTC pass per mode (segment-first
     count: 2 nnz prod K_{-n} + 2 R_n prod K flops; indices + values streamed once,
@@ -363,7 +374,7 @@ def main():
         **rl,
         "traffic": measured_traffic(args.config, prec),
         "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
-        "kernel": f"k_ttm<{prec}> (TTMcTC segment pass)",
+        "kernel": ttm_kernel_name(dims, ranks, prec),
         "launches": ttm_launch,
         "avg_launch_ms": round(ttm_ms / max(ttm_launch, 1), 4),
         "algorithmic_flops_per_launch": int(ttm_flops / max(ttm_launch, 1)),
