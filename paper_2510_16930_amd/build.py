@@ -2,7 +2,10 @@
 
 Each csrc/*.hip file is compiled separately with hipcc and linked into
 paper_2510_16930_amd/libhoqri.so. Packed float32 instructions are disabled
-(-packed-fp32-ops) for every HIP translation unit.
+(-packed-fp32-ops) for every HIP translation unit, and matrix-core
+accumulators are kept in ordinary vector registers (-amdgpu-mfma-vgpr-form):
+in the segment passes, whose accumulators are reset at slice ends, the
+accumulator-register form copies every accumulator out and back in each step.
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
     "-Wno-unused-function", "-Wno-unused-variable",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
 ]
 

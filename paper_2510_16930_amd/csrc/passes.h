@@ -32,6 +32,7 @@ struct SegArgs {
   float ascale;             // FP16: power of two applied to x * (row factors) before rounding
   float yscale;             // 16-bit forms: exact unscale of y
   int32_t K1;               // rank of the second other mode (row split for N = 4)
+  int32_t K0, K2;           // ranks of the first and third other modes (N = 4, c-tile 16-bit pass)
   // TTMcTC
   const float* gtop;        // stage-two operand [B][KN2][64][64]
   float* A;
@@ -55,7 +56,7 @@ struct PrepArgs {
   int32_t Ko[3];          // their ranks
   int64_t gstride[kMaxOrder];  // C-order strides of G
   int32_t nblk;           // blocks of this launch (grid-stride loop)
-  int32_t wide16;         // 1: bfloat16 operand of the 2 x 2-block BF16 pass (its own layout)
+  int32_t wide16;         // 1: bfloat16 operand of the one-wave 16-bit passes (their own layout)
 };
 
 struct FixArgs {

@@ -34,6 +34,7 @@
 #include "passes.h"
 
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace hoqri {
@@ -99,6 +100,18 @@ template <int PREC>
 __device__ inline float f16bits_to_f32(uint32_t b) {
   if constexpr (PREC == P_BF16) return __builtin_bit_cast(float, b << 16);
   else return (float)__builtin_bit_cast(_Float16, (unsigned short)b);
+}
+// one 16x16x16 product: a[t] (float32, rounded to nearest even here) against
+// the packed 16-bit operand b
+template <int PREC>
+__device__ inline f4 mfma16v(const float* a, s4 b, f4 c) {
+  if constexpr (PREC == P_BF16) {
+    const b4 av = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, av), b, c, 0, 0, 0);
+  } else {
+    const h4 av = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, __builtin_bit_cast(h4, b), c, 0, 0, 0);
+  }
 }
 // one 16x16x16 product: a[t] (float32, rounded to nearest even here) against
 // b[t] (16-bit raw bits), k-slot 4g + t of lane group g
@@ -198,7 +211,15 @@ struct PipeSet {
 // Lane n of each 16-lane row, broadcast to the whole row (DPP row_newbcast).
 template <int N>
 __device__ inline int32_t row_bcast(int32_t v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, false);
+}
+// f(integral_constant<int, C>) for C = I .. N-1 (compile-time lane indices)
+template <int I, int N, typename F>
+__device__ inline void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
 }
 // Dwords 4A .. 4A+3 of this row's group record.
 template <int A>
@@ -828,6 +849,313 @@ __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, co
   ttm22_body<KN2, kSlots22>(d[r], blockIdx.x - first[r]);
 }
 
+// ---------------------------------------------------------------------------
+// TTMcTC pass, 16-bit forms, 4-way tensors whose three other ranks are at most
+// 16: y_i (K_a x K_b x K_c) is computed as accumulator tiles over (a, b), one
+// per index c of the third other mode, four tiles per wave and ceil(K_c / 4)
+// waves per range. Per k-slot a lane gathers one entry of each other factor's
+// row (a = q, b = q, c = c0 + q for the wave's first tile c0); tile c
+// multiplies x * U_a(., a) * U_c(., c) (the c entry broadcast from a lane of
+// the lane group) by U_b(., b). A nonzero thus costs three gathers per lane
+// and wave for four tiles of y_i, instead of three per 16x16 block of the
+// (a K_b + b, c) layout. The waves of a range stage their tiles of finished
+// y_i in LDS in float32, in the block layout of the other passes (blocks of
+// 16 rows r = a K_b + b, columns c), store them from there as rows of Y_(n),
+// and multiply them by G_(n)^T in bfloat16 on the matrix cores (float32
+// accumulation; bfloat16 keeps the range of y_i in both forms), each wave
+// over its own columns c, partial products added in LDS in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kTiles4c = 4;   // c-tiles per wave
+
+template <int PREC, typename OnSeg>
+__device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
+                                    uint32_t k2, uint32_t k2c, int lane, int32_t* wlds, OnSeg&& on_seg) {
+  constexpr int NM1 = 3;
+  constexpr int NC = kTiles4c;
+  constexpr int GD = 4 * (NM1 + 1);
+  const int g = lane >> 4;
+  const auto rRec = make_rsrc(a.rec, (uint32_t)a.nnz_pad * 4u * (NM1 + 1));
+  const uint32_t goff = (uint32_t)(g * GD + (lane & 15)) * 4u;
+  const auto rU0 = make_rsrc(a.U[0], a.Ubytes[0]);
+  const auto rU1 = make_rsrc(a.U[1], a.Ubytes[1]);
+  const auto rU2 = make_rsrc(a.U[2], a.Ubytes[2]);
+
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  s_first = __builtin_amdgcn_readfirstlane(s_first);
+  s_last = __builtin_amdgcn_readfirstlane(s_last);
+  const int32_t b0 = lo >> 4;
+  const int32_t nblk = ((hi - 1) >> 4) - b0 + 1;
+  const int32_t bmax = (a.nnz_pad >> 4) - 1;
+
+  // raw 16-bit entries of k-slots t = 0..3, one per register (see walk_range22)
+  struct Set {
+    int32_t rec;
+    uint32_t u0[4], u1[4], u2[4];
+  };
+  auto load_idx = [&](int32_t blk, Set& S) {
+    blk = blk <= bmax ? blk : bmax;
+    S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
+  };
+  auto gather = [&](Set& S) {
+    struct {
+      i4 j0, j1, j2;
+    } J{group_quad<0>(S.rec), group_quad<1>(S.rec), group_quad<2>(S.rec)};
+    auto& SJ = J;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      S.u0[t] = ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + k2);
+      S.u1[t] = ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + k2);
+      S.u2[t] = ld_u16(rU2, ((uint32_t)SJ.j2[t] << 1) + k2c);
+    }
+  };
+
+  SegWindow win;
+  win.off = wlds;
+  win.row = wlds + 64;
+  win.load(a, s_first, lane);
+  int32_t s = s_first;
+  int32_t seg_lo = lo;
+  int32_t seg_hi = win.get_off(s_first + 1);
+  seg_hi = __builtin_amdgcn_readfirstlane(seg_hi < hi ? seg_hi : hi);
+  f4 acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+  bool done = false;
+
+  auto step = [&](int32_t blk, Set& C, Set& N2) {
+    float xa[4], uc[4];
+    const s4 bv = {(short)C.u1[0], (short)C.u1[1], (short)C.u1[2], (short)C.u1[3]};
+    const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      // FP16: the scale goes first, so no intermediate can exceed the bound
+      const float xv = (PREC == P_FP16) ? xq[t] * a.ascale : xq[t];
+      xa[t] = xv * f16bits_to_f32<PREC>(C.u0[t]);
+      uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
+    }
+    load_idx(blk + 3, C);
+    gather(N2);
+    const int32_t eb = blk * 16;
+    auto product = [&](const float* av) {
+      static_for<0, NC>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        float ac[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) ac[t] = av[t] * __builtin_bit_cast(float, row_bcast<c>(__builtin_bit_cast(int32_t, uc[t])));
+        acc[c] = mfma16v<PREC>(ac, bv, acc[c]);
+      });
+    };
+    if (__builtin_expect(seg_lo <= eb && seg_hi > eb + 16, 1)) {
+      product(xa);
+    } else {
+      while (!done && seg_lo < eb + 16) {
+        float am[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int32_t e = eb + 4 * t + g;
+          am[t] = (e >= seg_lo && e < seg_hi) ? xa[t] : 0.f;
+        }
+        product(am);
+        if (seg_hi > eb + 16) break;
+        f4 y[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          y[c] = acc[c];
+          acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+        on_seg(s, win.get_row(s), y);
+        s = __builtin_amdgcn_readfirstlane(s + 1);
+        if (s > s_last) {
+          done = true;
+        } else {
+          if (s + 1 - win.base >= 64) win.load(a, s, lane);
+          seg_lo = win.get_off(s);
+          const int32_t nx = win.get_off(s + 1);
+          seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+        }
+      }
+    }
+  };
+
+  Set S0, S1, S2;
+  load_idx(b0, S0);
+  load_idx(b0 + 1, S1);
+  gather(S0);
+  load_idx(b0 + 2, S2);
+  __builtin_amdgcn_sched_barrier(0);
+  gather(S1);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int32_t ib = 0; ib < nblk; ib += 3) {
+    step(b0 + ib, S0, S2);
+    if (done || ib + 1 >= nblk) break;
+    step(b0 + ib + 1, S1, S0);
+    if (done || ib + 2 >= nblk) break;
+    step(b0 + ib + 2, S2, S1);
+    if (done) break;
+  }
+}
+
+constexpr int kSlots4c = 4;  // staged slices per stage-two product
+__host__ __device__ constexpr int ttm4c_ys(int B) { return B * 256 + 4; }
+// LDS of one range (workgroup of nw waves): staged slices, partial products
+// of stage two, slot table, one slice-table window per wave.
+__host__ __device__ constexpr int ttm4c_bytes(int B, int nw, int KN2) {
+  return kSlots4c * ttm4c_ys(B) * 4 + nw * KN2 * 256 * 4 + 2 * kSlots4c * 4 + nw * 128 * 4;
+}
+
+// The pass: one workgroup of ceil(K_c / 4) waves per range. Stage two reads
+// gtop16 in the layout of the 2 x 2-block pass generalised to B blocks
+// ([kb][16 b + u][lane][t], u the column c inside block b), from memory:
+// slices are long where this pass is used, so stage two is rare.
+template <int PREC, int KN2>
+__device__ inline void ttm4c_body(const SegArgs& a, const int w) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int g = lane >> 4, q = lane & 15;
+  const int B = a.B;
+  const int YSB = ttm4c_ys(B);
+  float* ybat = lds;
+  float* red = lds + kSlots4c * YSB;
+  int32_t* slot_row = reinterpret_cast<int32_t*>(red + nw * KN2 * 256);
+  int32_t* slot_kind = slot_row + kSlots4c;
+  int32_t* wlds = slot_kind + kSlots4c + wv * 128;
+  // padded entries of the staged blocks are never written: zero them once
+  for (int i = threadIdx.x; i < kSlots4c * YSB; i += blockDim.x) ybat[i] = 0.f;
+  __syncthreads();
+
+  const int32_t lo = range_lo(w, a.W, a.nnz);
+  const int32_t hi = range_lo(w + 1, a.W, a.nnz);
+  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
+  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  const bool head_clip = a.seg_off[s_first] < lo;
+  const bool tail_clip = a.seg_off[s_last + 1] > hi;
+  if (wv == 0 && lane == 0) {
+    a.meta[w * 4 + 0] = s_first;
+    a.meta[w * 4 + 1] = s_last;
+    a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
+    a.meta[w * 4 + 3] = 0;
+  }
+  const int c0 = kTiles4c * wv;  // this wave's first column c
+  const uint16_t* gt = reinterpret_cast<const uint16_t*>(a.gtop) + lane * 4;
+  const uint32_t yrowf = (uint32_t)B * 256;
+  const int K0 = a.K0, K1 = a.K1;
+  const int cw = a.K2 - c0 < kTiles4c ? a.K2 - c0 : kTiles4c;  // columns of this wave
+
+  int slot = 0;
+  auto stage_two = [&]() {
+    __syncthreads();  // every wave's tiles of the staged slices are in LDS
+    f4 d[KN2];
+#pragma unroll
+    for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
+    const float* yr = ybat + (q % kSlots4c) * YSB + 4 * g;
+    for (int b = 0; b < B; ++b) {
+      for (int u = c0; u < c0 + cw; ++u) {
+        const int bu = 16 * b + u;
+        const f4 yv = *reinterpret_cast<const f4*>(yr + 16 * bu);
+        const b4 yb = {(__bf16)yv.x, (__bf16)yv.y, (__bf16)yv.z, (__bf16)yv.w};
+        const s4 av = __builtin_bit_cast(s4, yb);
+#pragma unroll
+        for (int kb = 0; kb < KN2; ++kb) {
+          const s4 gv = *reinterpret_cast<const s4*>(gt + ((size_t)kb * 16 * B + bu) * 256);
+          d[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, gv, d[kb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < KN2; ++kb) *reinterpret_cast<f4*>(red + (wv * KN2 + kb) * 256 + lane * 4) = d[kb];
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int kb = 0; kb < KN2; ++kb) {
+        f4 t = d[kb];
+        for (int w2 = 1; w2 < nw; ++w2) t += *reinterpret_cast<const f4*>(red + (w2 * KN2 + kb) * 256 + lane * 4);
+        d[kb] = t;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int sl = 4 * g + v;
+        if (sl < slot) {
+          const int32_t row = slot_row[sl];
+          const int kind = slot_kind[sl];
+#pragma unroll
+          for (int kb = 0; kb < KN2; ++kb) {
+            const int kn = 16 * kb + q;
+            if (kn < a.Kn) {
+              const float val = d[kb][v];
+              if (kind == KIND_COMPLETE) a.A[(size_t)row * a.Kn + kn] = val;
+              else a.carry[((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
+            }
+          }
+        }
+      }
+    }
+    if (a.yrow) {
+      // the float32 y_s for the core of the updated factor (row by label; a
+      // split slice leaves its partial per range and zeros in its own row);
+      // the waves take the blocks in turn
+      for (int sl = 0; sl < slot; ++sl) {
+        const int32_t row = __builtin_amdgcn_readfirstlane(slot_row[sl]);
+        const int kind = __builtin_amdgcn_readfirstlane(slot_kind[sl]);
+        const auto own = make_rsrc(a.yrow + (size_t)row * yrowf, yrowf * 4u);
+        const auto dst = make_rsrc(a.ycarry + ((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * yrowf, yrowf * 4u);
+        for (int b = wv; b < B; b += nw) {
+          const uint32_t vo = (uint32_t)(b * 256 + 4 * lane) * 4u;
+          const i4 yv = __builtin_bit_cast(i4, *reinterpret_cast<const f4*>(ybat + sl * YSB + b * 256 + 4 * lane));
+          if (kind == KIND_COMPLETE) {
+            __builtin_amdgcn_raw_buffer_store_b128(yv, own, vo, 0, 0);
+          } else {
+            __builtin_amdgcn_raw_buffer_store_b128(yv, dst, vo, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(i4{0, 0, 0, 0}, own, vo, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();  // staged slices and the slot table are reused
+    slot = 0;
+  };
+
+  walk_range4c<PREC>(a, lo, hi, s_first, s_last, (uint32_t)q * 2u, (uint32_t)(c0 + q) * 2u, lane, wlds,
+                     [&](int32_t s, int32_t row, const f4* y) {
+    // tile c0 + c, lane (g, q): y[a = 4g + v][b = q][c0 + c]; block row r = a K1 + b
+    float* ys = ybat + slot * YSB;
+    if (q < K1) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int av = 4 * g + v;
+        if (av < K0) {
+          const int r = av * K1 + q;
+          float* yp = ys + (r >> 4) * 256 + (r & 15) + c0 * 16;
+#pragma unroll
+          for (int c = 0; c < kTiles4c; ++c)
+            if (c < cw) yp[c * 16] = y[c][v] * a.yscale;
+        }
+      }
+    }
+    if (wv == 0 && lane == 0) {
+      int kind = KIND_COMPLETE;
+      if (s == s_first && head_clip) kind = KIND_HEAD;
+      else if (s == s_last && tail_clip) kind = KIND_TAIL;
+      slot_row[slot] = a.out_map ? scalar_ld(a.out_map, row) : row;
+      slot_kind[slot] = kind;
+    }
+    if (++slot == kSlots4c) stage_two();
+  });
+  if (slot > 0) stage_two();
+}
+
+template <int PREC, int KN2>
+__global__ __launch_bounds__(256) void k_ttm4c(SegArgs a) {
+  ttm4c_body<PREC, KN2>(a, blockIdx.x);
+}
+template <int PREC, int KN2>
+__global__ __launch_bounds__(256) void k_ttm4c_b(const SegArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  ttm4c_body<PREC, KN2>(d[r], blockIdx.x - first[r]);
+}
+
 // Adds the partial rows of slices that cross range boundaries and writes them.
 // One workgroup per range; only the owner of a split slice (the range where it
 // starts, holding its tail partial) works: the head partials of the following
@@ -907,8 +1235,8 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
     int kb, b, jp;
     if (p.wide16) {
       // [kb][16 b + u][lane][t]: index 16 u + 4 (lane/16) + t inside block b
-      const int bu = (int)((idx >> 8) & 63);
-      kb = (int)(idx >> 14);
+      const int bu = (int)((idx >> 8) % (16 * p.B));
+      kb = (int)(idx / (4096 * p.B));
       b = bu >> 4;
       jp = 16 * (bu & 15) + 4 * (lane >> 4) + (int)(idx & 3);
     } else {
@@ -1534,11 +1862,15 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   a.RB = g.RB;
   a.CB = g.CB;
   a.K1 = g.nm1 >= 2 ? g.Ko[1] : 1;
+  a.K0 = g.Ko[0];
+  a.K2 = g.nm1 >= 3 ? g.Ko[2] : 1;
   return true;
 }
 
-// Key offset of the 2 x 2-block BF16 TTMcTC pass (core keys add 1000).
+// Key offset of the 2 x 2-block BF16 TTMcTC pass (core keys add 1000), and of
+// the 4-way 16-bit pass with c-tiles.
 constexpr int kWideKey = 2000;
+constexpr int kWide4Key = 10000;
 
 // Kernel instances: one single-plan and one batched launch per
 // (order, rank blocks, precision).
@@ -1574,7 +1906,21 @@ bool seg_kernels_p(int nm1, int kn2, SegKernels* k) {
   }
 }
 
+template <int PREC>
+bool seg_kernels_4c(int kn2, SegKernels* k) {
+  if (kn2 == 1) {
+    k->ttm = (const void*)k_ttm4c<PREC, 1>;
+    k->ttm_b = (const void*)k_ttm4c_b<PREC, 1>;
+  } else {
+    k->ttm = (const void*)k_ttm4c<PREC, 2>;
+    k->ttm_b = (const void*)k_ttm4c_b<PREC, 2>;
+  }
+  return true;
+}
+
 bool seg_kernels(int key, SegKernels* k) {
+  const bool wide4 = key >= kWide4Key;
+  if (wide4) key -= kWide4Key;
   const bool wide = key >= kWideKey;
   if (wide) key -= kWideKey;
   key %= 1000;
@@ -1583,6 +1929,12 @@ bool seg_kernels(int key, SegKernels* k) {
   if (prec == P_FP32) ok = seg_kernels_p<P_FP32>(nm1, kn2, k);
   else if (prec == P_BF16) ok = seg_kernels_p<P_BF16>(nm1, kn2, k);
   else if (prec == P_FP16) ok = seg_kernels_p<P_FP16>(nm1, kn2, k);
+  if (ok && wide4) {
+    if (nm1 != 3 || kn2 > 2) return false;
+    if (prec == P_BF16) return seg_kernels_4c<P_BF16>(kn2, k);
+    if (prec == P_FP16) return seg_kernels_4c<P_FP16>(kn2, k);
+    return false;
+  }
   if (!ok || !wide) return ok;
   if (nm1 != 2 || prec != P_BF16) return false;
   if (kn2 == 1) {
@@ -1598,6 +1950,12 @@ bool seg_kernels(int key, SegKernels* k) {
 // The 2 x 2-block pass takes the BF16 form of 3-way tensors whose two other
 // ranks both lie in 17..32.
 bool ttm_wide(const PassGeom& g, int prec) { return prec == OP_BF16 && g.nm1 == 2 && g.RB == 2 && g.CB == 2; }
+
+// The 4-way c-tile pass takes the 16-bit forms when all three other ranks are
+// at most 16 (every y_i then fits the staging of one range).
+bool ttm_wide4(const PassGeom& g, int prec) {
+  return prec != OP_FP32 && g.nm1 == 3 && g.Ko[0] <= 16 && g.Ko[1] <= 16 && g.Ko[2] <= 16;
+}
 
 // Waves (ranges) per workgroup of that pass: as many as the LDS of one
 // workgroup holds next to the core operand, at most kMaxRpw22.
@@ -1678,10 +2036,12 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   const ModeData& md = p->md[mode];
   *job = TtmJob{};
   const bool wide = ttm_wide(g, op.prec);
-  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0);
+  const bool nc4 = ttm_wide4(g, op.prec);
+  const int nw4 = (g.Ko[2] + kTiles4c - 1) / kTiles4c;  // waves per range of the c-tile pass
+  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (nc4 ? kWide4Key : 0);
   // stage-two operand
   PrepArgs& pa = job->prep;
-  pa.wide16 = wide ? 1 : 0;
+  pa.wide16 = (wide || nc4) ? 1 : 0;
   pa.G = G;
   pa.gtop = p->sc.gtop;
   pa.B = g.B;
@@ -1707,7 +2067,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   int64_t W = md.ranges;
   if (W > p->nnz) W = p->nnz;
   a.W = (int32_t)W;
-  a.RPW = wide ? rpw22(KN2) : (g.B == 1 ? 4 : 1);
+  a.RPW = wide ? rpw22(KN2) : nc4 ? 1 : (g.B == 1 ? 4 : 1);
   a.gtop = p->sc.gtop;
   a.A = A;
   a.Kn = p->K[mode];
@@ -1716,9 +2076,10 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   a.out_map = out_map;
   a.yrow = rows ? p->sc.ybuf : nullptr;
   a.ycarry = rows ? p->sc.ycarry : nullptr;
-  job->threads = wide ? 64 * a.RPW : 64 * g.B * a.RPW;
-  job->shmem = wide ? (size_t)KN2 * 32768 + (size_t)a.RPW * ttm22_wave_bytes(kSlots22)
-                    : (size_t)ttm_lds_floats(a, KN2) * 4;
+  job->threads = wide ? 64 * a.RPW : nc4 ? 64 * nw4 : 64 * g.B * a.RPW;
+  job->shmem = wide  ? (size_t)KN2 * 32768 + (size_t)a.RPW * ttm22_wave_bytes(kSlots22)
+               : nc4 ? (size_t)ttm4c_bytes(g.B, nw4, KN2)
+                     : (size_t)ttm_lds_floats(a, KN2) * 4;
   job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
   // split slices
   FixArgs& f = job->fix;

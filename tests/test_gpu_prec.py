@@ -9,9 +9,11 @@ significand) or 2^-11 (float16, 11-bit significand). Summing terms and
 multiplying by the float32 core cannot raise that relative error above the
 same factor times the result of the same computation on absolute values:
     |A_gpu - A| <= (N u16 + eps32) * TTMcTC(|X|, {|U|}, |G|)   elementwise,
-and likewise for the core. Where the BF16 pass also rounds y_i and the core
-to bfloat16 before their product (y_i of 2 x 2 blocks: 3-way tensors with both
-other ranks in 17..32), two more roundings enter every term: (N + 2) u16.
+and likewise for the core. Where a pass also rounds y_i and the core to
+bfloat16 before their product (BF16 with y_i of 2 x 2 blocks: 3-way tensors
+with both other ranks in 17..32; BF16 and FP16 on 4-way tensors with all
+other ranks at most 16), two more bfloat16 roundings enter every term:
+N u16 + 2 * 2^-8.
 The oracle evaluates the right-hand side (the
 operation is multilinear, so its absolute-value instance is the same
 definition). Float16 gradual underflow adds an absolute error far below
@@ -62,6 +64,10 @@ def make(name):
     elif name == "n4k10":
         dims, K = (4000, 4000, 100, 20), (10, 10, 10, 10)
         idx, vals = synth.coo_zipf(dims, 100_000, alpha=1.1, seed=6, values="uniform")
+    elif name == "n4rag":
+        # ragged 4-way ranks: c-tile waves with 4, 4 and 1 (or 4 x 4) columns
+        dims, K = (3000, 2500, 200, 40), (6, 12, 9, 16)
+        idx, vals = synth.coo_zipf(dims, 80_000, alpha=1.1, seed=8, values="uniform")
     elif name == "n2":
         dims, K = (3000, 2000), (8, 8)
         idx, vals = synth.coo_uniform(dims, 40_000, seed=7)
@@ -79,12 +85,15 @@ def make(name):
 
 
 def ttmctc_tol(prec, K, n):
-    """Relative bound of a TTMcTC pass: N u16 + eps32, and (N + 2) u16 + eps32
-    where the BF16 pass also rounds y_i and the core to bfloat16 for their
-    product (3-way, both other ranks in 17..32)."""
+    """Relative bound of a TTMcTC pass: N u16 + eps32, plus 2 u_bf16 where the
+    pass also rounds y_i and the core to bfloat16 for their product (BF16,
+    3-way with both other ranks in 17..32; BF16 and FP16, 4-way with all other
+    ranks at most 16)."""
     N = len(K)
-    wide = prec == "bf16" and N == 3 and all(16 < K[m] <= 32 for m in range(N) if m != n)
-    return (N + 2 if wide else N) * U16[prec] + EPS32
+    others = [K[m] for m in range(N) if m != n]
+    bf16_core = (prec == "bf16" and N == 3 and all(16 < k <= 32 for k in others)) or \
+        (prec in ("bf16", "fp16") and N == 4 and all(k <= 16 for k in others))
+    return N * U16[prec] + (2 * U16["bf16"] if bf16_core else 0.0) + EPS32
 
 
 def bound_check(got, ref, absref, tol_rel, what):
@@ -97,7 +106,7 @@ def bound_check(got, ref, absref, tol_rel, what):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("name", ["c1", "n2", "zipf3", "n3k32", "n3rag", "n4k10", "wide"])
+@pytest.mark.parametrize("name", ["c1", "n2", "zipf3", "n3k32", "n3rag", "n4k10", "n4rag", "wide"])
 def test_16bit_passes_within_rounding_bound(name, prec):
     print(f"[prec] case={name} prec={prec}", flush=True)
     dims, K, idx, vals32, U = make(name)
