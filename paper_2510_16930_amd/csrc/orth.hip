@@ -22,6 +22,11 @@ namespace hoqri {
 namespace {
 
 constexpr int kT = 256;
+static_assert(kMaxRank == 32, "rank blocks are at most 32 wide");
+// Element loops of the Cholesky step run over (i, j) = (e >> sh, e & (2^sh - 1))
+// for e < K 2^sh, with 2^sh the power of two >= K (16 or 32): shifts, not
+// divisions by K.
+__device__ inline int rank_shift(int K) { return K <= 16 ? 4 : 5; }
 constexpr int kChunk = 32;    // rows staged per step
 constexpr double kBreakRel = 1e-13;
 
@@ -138,6 +143,7 @@ __global__ __launch_bounds__(kT) void k_gram_reduce_b(const GRedArgs* d, const i
 // <= 1e-13 * tr or not finite.
 __device__ inline void chol_inv(double (*L)[kMaxRank + 1], double (*Ri)[kMaxRank + 1], int K, double tr, int* bad) {
   const int t = threadIdx.x;
+  const int sh = rank_shift(K);
   for (int k = 0; k < K; ++k) {
     if (t == 0) {
       const double piv = L[k][k];
@@ -148,13 +154,13 @@ __device__ inline void chol_inv(double (*L)[kMaxRank + 1], double (*Ri)[kMaxRank
     const double d = L[k][k];
     for (int j = k + 1 + t; j < K; j += kT) L[k][j] /= d;
     __syncthreads();
-    for (int e = t; e < K * K; e += kT) {
-      const int i = e / K, j = e % K;
-      if (i > k && j >= i) L[i][j] -= L[k][i] * L[k][j];
+    for (int e = t; e < (K << sh); e += kT) {
+      const int i = e >> sh, j = e & ((1 << sh) - 1);
+      if (i > k && j >= i && j < K) L[i][j] -= L[k][i] * L[k][j];
     }
     __syncthreads();
   }
-  for (int e = t; e < K * K; e += kT) Ri[e / K][e % K] = 0.0;
+  for (int e = t; e < (K << sh); e += kT) Ri[e >> sh][e & ((1 << sh) - 1)] = 0.0;
   __syncthreads();
   for (int j = t; j < K; j += kT) {
     for (int i = j; i >= 0; --i) {
@@ -181,9 +187,14 @@ __device__ inline void chol_body(const CholArgs& c) {
   __shared__ int bad;
   const int K = c.K;
   const int t = threadIdx.x;
-  for (int e = t; e < K * K; e += kT) {
-    L[e / K][e % K] = c.W[e];
-    W[e / K][e % K] = c.W[e];
+  const int sh = rank_shift(K);
+  for (int e = t; e < (K << sh); e += kT) {
+    const int i = e >> sh, j = e & ((1 << sh) - 1);
+    if (i < K && j < K) {
+      const double w = c.W[i * K + j];
+      L[i][j] = w;
+      W[i][j] = w;
+    }
   }
   if (t == 0) {
     double s = 0.0;
@@ -194,24 +205,27 @@ __device__ inline void chol_body(const CholArgs& c) {
   __syncthreads();
   chol_inv(L, Ri, K, tr, &bad);  // L: R1, Ri: R1^-1
   // T = W1 R1^-1, then W2 = R1^-T T (kept in L after saving R1)
-  for (int e = t; e < K * K; e += kT) {
-    const int i = e / K, j = e % K;
+  for (int e = t; e < (K << sh); e += kT) {
+    const int i = e >> sh, j = e & ((1 << sh) - 1);
+    if (j >= K) continue;
     double s = 0.0;
     for (int k = 0; k <= j; ++k) s += W[i][k] * Ri[k][j];
     T[i][j] = s;
     R1[i][j] = (j >= i) ? L[i][j] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < K * K; e += kT) {
-    const int i = e / K, j = e % K;
+  for (int e = t; e < (K << sh); e += kT) {
+    const int i = e >> sh, j = e & ((1 << sh) - 1);
+    if (j >= K) continue;
     double s = 0.0;
     for (int k = 0; k <= i; ++k) s += Ri[k][i] * T[k][j];
     W[i][j] = s;  // W2
   }
   __syncthreads();
-  for (int e = t; e < K * K; e += kT) {
-    L[e / K][e % K] = W[e / K][e % K];
-    T[e / K][e % K] = Ri[e / K][e % K];  // keep R1^-1
+  for (int e = t; e < (K << sh); e += kT) {
+    const int i = e >> sh, j = e & ((1 << sh) - 1);
+    L[i][j] = W[i][j];
+    T[i][j] = Ri[i][j];  // keep R1^-1
   }
   if (t == 0) {
     double s = 0.0;
@@ -220,15 +234,16 @@ __device__ inline void chol_body(const CholArgs& c) {
   }
   __syncthreads();
   chol_inv(L, Ri, K, tr, &bad);  // L: R2, Ri: R2^-1
-  for (int e = t; e < K * K; e += kT) {
-    const int i = e / K, j = e % K;
+  for (int e = t; e < (K << sh); e += kT) {
+    const int i = e >> sh, j = e & ((1 << sh) - 1);
+    if (j >= K) continue;
     double m = 0.0, r = 0.0;
     if (j >= i) {
       for (int k = i; k <= j; ++k) m += T[i][k] * Ri[k][j];  // R1^-1 R2^-1
       for (int k = i; k <= j; ++k) r += L[i][k] * R1[k][j];  // R2 R1
     }
-    c.Mout[e] = m;
-    if (c.Rout) c.Rout[e] = r;
+    c.Mout[i * K + j] = m;
+    if (c.Rout) c.Rout[i * K + j] = r;
   }
   if (t == 0) {
     *c.flag = bad;

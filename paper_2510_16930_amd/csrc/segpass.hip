@@ -673,13 +673,9 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
         }
         product(am);
         if (seg_hi > eb + 16) break;
-        f4 y[4];
+        on_seg(s, win.get_row(s), acc);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          y[b] = acc[b];
-          acc[b] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-        on_seg(s, win.get_row(s), y);
+        for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
         s = __builtin_amdgcn_readfirstlane(s + 1);
         if (s > s_last) {
           done = true;
@@ -765,7 +761,8 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
     for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
     // rows q >= SL of the product re-read staged rows and are not used
     const uint16_t* yr = ybat + (q % SL) * kYs22 + 4 * g;
-#pragma unroll 4
+    // fully unrolled: every LDS address is a base register plus an immediate
+#pragma unroll
     for (int bu = 0; bu < 64; ++bu) {
       const s4 av = *reinterpret_cast<const s4*>(yr + 16 * bu);
 #pragma unroll
@@ -958,13 +955,9 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
         }
         product(am);
         if (seg_hi > eb + 16) break;
-        f4 y[NC];
+        on_seg(s, win.get_row(s), acc);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          y[c] = acc[c];
-          acc[c] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-        on_seg(s, win.get_row(s), y);
+        for (int c = 0; c < NC; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
         s = __builtin_amdgcn_readfirstlane(s + 1);
         if (s > s_last) {
           done = true;
