@@ -862,13 +862,19 @@ __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, co
 // accumulation; bfloat16 keeps the range of y_i in both forms), each wave
 // over its own columns c, partial products added in LDS in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kTiles4c = 4;   // c-tiles per wave
+// c-tiles per wave: waves per range nw = ceil(K_c / 6), tiles per wave
+// NC = ceil(K_c / nw) (4 to 6; fewer tiles than that still run 4)
+constexpr int kMaxTiles4c = 6;
+inline int tiles4c(int Kc, int* nw) {
+  *nw = (Kc + kMaxTiles4c - 1) / kMaxTiles4c;
+  const int nc = (Kc + *nw - 1) / *nw;
+  return nc < 4 ? 4 : nc;
+}
 
-template <int PREC, typename OnSeg>
+template <int PREC, int NC, typename OnSeg>
 __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
                                     uint32_t k2, uint32_t k2c, int lane, int32_t* wlds, OnSeg&& on_seg) {
   constexpr int NM1 = 3;
-  constexpr int NC = kTiles4c;
   constexpr int GD = 4 * (NM1 + 1);
   const int g = lane >> 4;
   const auto rRec = make_rsrc(a.rec, (uint32_t)a.nnz_pad * 4u * (NM1 + 1));
@@ -989,7 +995,7 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
   }
 }
 
-constexpr int kSlots4c = 4;  // staged slices per stage-two product
+constexpr int kSlots4c = 3;  // staged slices per stage-two product (six workgroups of two waves fit a CU)
 __host__ __device__ constexpr int ttm4c_ys(int B) { return B * 256 + 4; }
 // LDS of one range (workgroup of nw waves): staged slices, partial products
 // of stage two, slot table, one slice-table window per wave.
@@ -997,11 +1003,11 @@ __host__ __device__ constexpr int ttm4c_bytes(int B, int nw, int KN2) {
   return kSlots4c * ttm4c_ys(B) * 4 + nw * KN2 * 256 * 4 + 2 * kSlots4c * 4 + nw * 128 * 4;
 }
 
-// The pass: one workgroup of ceil(K_c / 4) waves per range. Stage two reads
+// The pass: one workgroup of nw waves per range, NC c-tiles each. Stage two reads
 // gtop16 in the layout of the 2 x 2-block pass generalised to B blocks
 // ([kb][16 b + u][lane][t], u the column c inside block b), from memory:
 // slices are long where this pass is used, so stage two is rare.
-template <int PREC, int KN2>
+template <int PREC, int NC, int KN2>
 __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
@@ -1031,11 +1037,11 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
     a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
     a.meta[w * 4 + 3] = 0;
   }
-  const int c0 = kTiles4c * wv;  // this wave's first column c
+  const int c0 = NC * wv;  // this wave's first column c
   const uint16_t* gt = reinterpret_cast<const uint16_t*>(a.gtop) + lane * 4;
   const uint32_t yrowf = (uint32_t)B * 256;
   const int K0 = a.K0, K1 = a.K1;
-  const int cw = a.K2 - c0 < kTiles4c ? a.K2 - c0 : kTiles4c;  // columns of this wave
+  const int cw = a.K2 - c0 < NC ? a.K2 - c0 : NC;  // columns of this wave
 
   int slot = 0;
   auto stage_two = [&]() {
@@ -1110,7 +1116,7 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
     slot = 0;
   };
 
-  walk_range4c<PREC>(a, lo, hi, s_first, s_last, (uint32_t)q * 2u, (uint32_t)(c0 + q) * 2u, lane, wlds,
+  walk_range4c<PREC, NC>(a, lo, hi, s_first, s_last, (uint32_t)q * 2u, (uint32_t)(c0 + q) * 2u, lane, wlds,
                      [&](int32_t s, int32_t row, const f4* y) {
     // tile c0 + c, lane (g, q): y[a = 4g + v][b = q][c0 + c]; block row r = a K1 + b
     float* ys = ybat + slot * YSB;
@@ -1122,7 +1128,7 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
           const int r = av * K1 + q;
           float* yp = ys + (r >> 4) * 256 + (r & 15) + c0 * 16;
 #pragma unroll
-          for (int c = 0; c < kTiles4c; ++c)
+          for (int c = 0; c < NC; ++c)
             if (c < cw) yp[c * 16] = y[c][v] * a.yscale;
         }
       }
@@ -1139,14 +1145,14 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
   if (slot > 0) stage_two();
 }
 
-template <int PREC, int KN2>
+template <int PREC, int NC, int KN2>
 __global__ __launch_bounds__(256) void k_ttm4c(SegArgs a) {
-  ttm4c_body<PREC, KN2>(a, blockIdx.x);
+  ttm4c_body<PREC, NC, KN2>(a, blockIdx.x);
 }
-template <int PREC, int KN2>
+template <int PREC, int NC, int KN2>
 __global__ __launch_bounds__(256) void k_ttm4c_b(const SegArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
-  ttm4c_body<PREC, KN2>(d[r], blockIdx.x - first[r]);
+  ttm4c_body<PREC, NC, KN2>(d[r], blockIdx.x - first[r]);
 }
 
 // Adds the partial rows of slices that cross range boundaries and writes them.
@@ -1861,7 +1867,7 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
 }
 
 // Key offset of the 2 x 2-block BF16 TTMcTC pass (core keys add 1000), and of
-// the 4-way 16-bit pass with c-tiles.
+// the 4-way 16-bit pass with c-tiles (plus 1000 x the tiles per wave).
 constexpr int kWideKey = 2000;
 constexpr int kWide4Key = 10000;
 
@@ -1899,21 +1905,32 @@ bool seg_kernels_p(int nm1, int kn2, SegKernels* k) {
   }
 }
 
-template <int PREC>
-bool seg_kernels_4c(int kn2, SegKernels* k) {
+template <int PREC, int NC>
+bool seg_kernels_4c_n(int kn2, SegKernels* k) {
   if (kn2 == 1) {
-    k->ttm = (const void*)k_ttm4c<PREC, 1>;
-    k->ttm_b = (const void*)k_ttm4c_b<PREC, 1>;
+    k->ttm = (const void*)k_ttm4c<PREC, NC, 1>;
+    k->ttm_b = (const void*)k_ttm4c_b<PREC, NC, 1>;
   } else {
-    k->ttm = (const void*)k_ttm4c<PREC, 2>;
-    k->ttm_b = (const void*)k_ttm4c_b<PREC, 2>;
+    k->ttm = (const void*)k_ttm4c<PREC, NC, 2>;
+    k->ttm_b = (const void*)k_ttm4c_b<PREC, NC, 2>;
   }
   return true;
 }
 
+template <int PREC>
+bool seg_kernels_4c(int nc, int kn2, SegKernels* k) {
+  if (nc == 4) return seg_kernels_4c_n<PREC, 4>(kn2, k);
+  if (nc == 5) return seg_kernels_4c_n<PREC, 5>(kn2, k);
+  if (nc == 6) return seg_kernels_4c_n<PREC, 6>(kn2, k);
+  return false;
+}
+
 bool seg_kernels(int key, SegKernels* k) {
-  const bool wide4 = key >= kWide4Key;
-  if (wide4) key -= kWide4Key;
+  int nc4 = 0;  // c-tiles per wave of the 4-way c-tile pass
+  if (key >= kWide4Key) {
+    nc4 = (key - kWide4Key) / 1000;
+    key %= 1000;
+  }
   const bool wide = key >= kWideKey;
   if (wide) key -= kWideKey;
   key %= 1000;
@@ -1922,10 +1939,10 @@ bool seg_kernels(int key, SegKernels* k) {
   if (prec == P_FP32) ok = seg_kernels_p<P_FP32>(nm1, kn2, k);
   else if (prec == P_BF16) ok = seg_kernels_p<P_BF16>(nm1, kn2, k);
   else if (prec == P_FP16) ok = seg_kernels_p<P_FP16>(nm1, kn2, k);
-  if (ok && wide4) {
+  if (ok && nc4 > 0) {
     if (nm1 != 3 || kn2 > 2) return false;
-    if (prec == P_BF16) return seg_kernels_4c<P_BF16>(kn2, k);
-    if (prec == P_FP16) return seg_kernels_4c<P_FP16>(kn2, k);
+    if (prec == P_BF16) return seg_kernels_4c<P_BF16>(nc4, kn2, k);
+    if (prec == P_FP16) return seg_kernels_4c<P_FP16>(nc4, kn2, k);
     return false;
   }
   if (!ok || !wide) return ok;
@@ -2030,8 +2047,9 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   *job = TtmJob{};
   const bool wide = ttm_wide(g, op.prec);
   const bool nc4 = ttm_wide4(g, op.prec);
-  const int nw4 = (g.Ko[2] + kTiles4c - 1) / kTiles4c;  // waves per range of the c-tile pass
-  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (nc4 ? kWide4Key : 0);
+  int nw4 = 1;  // waves per range of the c-tile pass
+  const int tiles4 = nc4 ? tiles4c(g.Ko[2], &nw4) : 0;
+  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (nc4 ? kWide4Key + 1000 * tiles4 : 0);
   // stage-two operand
   PrepArgs& pa = job->prep;
   pa.wide16 = (wide || nc4) ? 1 : 0;
