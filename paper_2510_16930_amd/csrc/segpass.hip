@@ -88,6 +88,7 @@ __device__ inline f4 mfma4(float a, float b, f4 c) {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
 
 constexpr int P_FP32 = 0, P_BF16 = 1, P_FP16 = 2;
@@ -941,13 +942,27 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
     gather(N2);
     const int32_t eb = blk * 16;
     auto product = [&](const float* av) {
-      static_for<0, NC>([&](auto ci) {
-        constexpr int c = decltype(ci)::value;
-        float ac[4];
+      if constexpr (PREC == P_FP16) {
+        // packed half precision: x U_a(., a) rounded to float16 once, then one
+        // packed product per pair of k-slots with the broadcast c entries
+        const h2 xp0 = {(_Float16)av[0], (_Float16)av[1]}, xp1 = {(_Float16)av[2], (_Float16)av[3]};
+        const int32_t up0 = (int32_t)(C.u2[0] | (C.u2[1] << 16)), up1 = (int32_t)(C.u2[2] | (C.u2[3] << 16));
+        static_for<0, NC>([&](auto ci) {
+          constexpr int c = decltype(ci)::value;
+          const h2 a0 = xp0 * __builtin_bit_cast(h2, row_bcast<c>(up0));
+          const h2 a1 = xp1 * __builtin_bit_cast(h2, row_bcast<c>(up1));
+          const h4 ah = {a0.x, a0.y, a1.x, a1.y};
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, __builtin_bit_cast(h4, bv), acc[c], 0, 0, 0);
+        });
+      } else {
+        static_for<0, NC>([&](auto ci) {
+          constexpr int c = decltype(ci)::value;
+          float ac[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ac[t] = av[t] * __builtin_bit_cast(float, row_bcast<c>(__builtin_bit_cast(int32_t, uc[t])));
-        acc[c] = mfma16v<PREC>(ac, bv, acc[c]);
-      });
+          for (int t = 0; t < 4; ++t) ac[t] = av[t] * __builtin_bit_cast(float, row_bcast<c>(__builtin_bit_cast(int32_t, uc[t])));
+          acc[c] = mfma16v<PREC>(ac, bv, acc[c]);
+        });
+      }
     };
     if (__builtin_expect(seg_lo <= eb && seg_hi > eb + 16, 1)) {
       product(xa);

@@ -13,7 +13,8 @@ and likewise for the core. Where a pass also rounds y_i and the core to
 bfloat16 before their product (BF16 with y_i of 2 x 2 blocks: 3-way tensors
 with both other ranks in 17..32; BF16 and FP16 on 4-way tensors with all
 other ranks at most 16), two more bfloat16 roundings enter every term:
-N u16 + 2 * 2^-8.
+N u16 + 2 * 2^-8; the FP16 form of that 4-way pass rounds its A operand in two
+steps (x U_a, then the packed product with U_c): (N + 1) u16 + 2 * 2^-8.
 The oracle evaluates the right-hand side (the
 operation is multilinear, so its absolute-value instance is the same
 definition). Float16 gradual underflow adds an absolute error far below
@@ -91,9 +92,11 @@ def ttmctc_tol(prec, K, n):
     ranks at most 16)."""
     N = len(K)
     others = [K[m] for m in range(N) if m != n]
-    bf16_core = (prec == "bf16" and N == 3 and all(16 < k <= 32 for k in others)) or \
-        (prec in ("bf16", "fp16") and N == 4 and all(k <= 16 for k in others))
-    return N * U16[prec] + (2 * U16["bf16"] if bf16_core else 0.0) + EPS32
+    ctile = prec in ("bf16", "fp16") and N == 4 and all(k <= 16 for k in others)
+    bf16_core = (prec == "bf16" and N == 3 and all(16 < k <= 32 for k in others)) or ctile
+    # the FP16 c-tile pass rounds x U_a to float16 before the packed product with U_c
+    n_round = N + 1 if (ctile and prec == "fp16") else N
+    return n_round * U16[prec] + (2 * U16["bf16"] if bf16_core else 0.0) + EPS32
 
 
 def bound_check(got, ref, absref, tol_rel, what):
