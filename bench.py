@@ -120,7 +120,9 @@ def pass_work(dims, ranks, nnz, R, su=4):
     return out
 
 
-TRAFFIC_PROFILES = {("c2", "fp32"): "profiles/ttmctc_fp32_c2_traffic.txt"}
+TRAFFIC_PROFILES = {("c2", "fp32"): "profiles/ttmctc_fp32_c2_traffic.txt",
+                    ("c3", "bf16"): "profiles/ttmctc_bf16_c3_traffic.txt",
+                    ("c4", "fp16"): "profiles/ttmctc_fp16_c4_traffic.txt"}
 KERNEL_SOURCES = ("paper_2510_16930_amd/csrc/segpass.hip", "paper_2510_16930_amd/csrc/common.h",
                   "paper_2510_16930_amd/csrc/passes.h")
 
