@@ -150,7 +150,7 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
                            const int32_t* out_map, hipStream_t s, bool rows = false);
 // G = X x {U^T} from the rows Y_(mode) stored by the last TTMcTC pass of `mode`
 // and the (updated) factor U^(mode) in the plan's scratch; ||G||^2 into *f_out.
-hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s);
+hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s, bool split = false);
 // A = Y_(mode) G_(mode)^T from the rows stored by the last TTMcTC pass of
 // `mode` (label order, rows of empty slices zeroed): one inner step of HOOI's
 // orthogonal iteration when G = U^(mode)T Y_(mode).

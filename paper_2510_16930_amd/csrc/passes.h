@@ -90,6 +90,7 @@ struct CoreGemmArgs {
   const float* Uc;
   int32_t Kc, KC, R, W, B;
   int32_t nchunk;  // partials: chunk c takes the 16-row groups c, c + nchunk, ...
+  int32_t split;   // 1: products in split bfloat16 (hi + lo, three per product; 16-bit forms)
   float* gpart;
 };
 
@@ -166,7 +167,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
                          const int32_t* out_map, TtmJob* job, bool rows = false);
 hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, CoreJob* job);
 // After the TTMcTC pass of `mode` with rows and the update of U^(mode) (float32, label order).
-hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job);
+hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split = false);
 
 
 struct GramArgs {

@@ -348,7 +348,8 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
                                 stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n]));
         }
         HOQRI_TRY(refresh16(p, op, n, stream));
-        if (fuse) HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream));
+        // the 16-bit forms take the core from the stored rows in split bfloat16
+        if (fuse) HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream, op != OP_FP32));
         // HOOI: next orthogonal-iteration step A = Y_(n) (Y_(n)^T U) from the stored rows
         if (it + 1 < inner) HOQRI_TRY(launch_rows_a(p, n, d_G_out, p->sc.A, stream));
       }

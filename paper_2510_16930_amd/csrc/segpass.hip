@@ -1357,8 +1357,23 @@ __global__ __launch_bounds__(512) void k_core_rows_b(const SegArgs* d, const int
 // of a group as one vector, and product c of a step takes component c, so its
 // output column q stands for j' = 64 cq + 4q + c. The four row lanes' sums are
 // added in order rl = 0, 1, 2, 3 (fixed order throughout).
+// SPLIT (the 16-bit forms): each float32 operand is the sum of two bfloat16
+// numbers (hi = nearest, lo = nearest of the rest, about 2^-16 relative) and a
+// product of 16 rows takes three v_mfma_f32_16x16x16_bf16 (hi hi, hi lo,
+// lo hi), k-slot 4g + t standing for row 4t + g, instead of four float32
+// products of 4 rows.
 constexpr int kGemmThreads = 1024;
-template <int KTT>
+__device__ inline void split_bf16(const float* x, s4* hi, s4* lo) {
+  const b4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+  const s4 hs = __builtin_bit_cast(s4, h);
+  float r[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) r[t] = x[t] - __builtin_bit_cast(float, (uint32_t)(uint16_t)hs[t] << 16);
+  const b4 l = {(__bf16)r[0], (__bf16)r[1], (__bf16)r[2], (__bf16)r[3]};
+  *hi = hs;
+  *lo = __builtin_bit_cast(s4, l);
+}
+template <int KTT, bool SPLIT>
 __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   constexpr int KTM = KTT == 0 ? 2 : KTT;
   __shared__ f4 red[3][4][KTM * 4][64];  // row lanes 1..3, column quarter, accumulator, lane
@@ -1377,16 +1392,38 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   const int64_t R = p.R;
   const int col = b * 256 + 64 * cq + 4 * q;
   auto product = [&](const f4* yv, float (*ua)[KTM]) {
+    if constexpr (SPLIT) {
+      s4 yh[4], yl[4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
+      for (int c = 0; c < 4; ++c) {
+        const float yc[4] = {yv[0][c], yv[1][c], yv[2][c], yv[3][c]};
+        split_bf16(yc, &yh[c], &yl[c]);
+      }
 #pragma unroll
       for (int kt = 0; kt < KTM; ++kt) {
         if (kt >= KT) continue;
-        acc[kt][0] = mfma4(ua[st][kt], yv[st].x, acc[kt][0]);
-        acc[kt][1] = mfma4(ua[st][kt], yv[st].y, acc[kt][1]);
-        acc[kt][2] = mfma4(ua[st][kt], yv[st].z, acc[kt][2]);
-        acc[kt][3] = mfma4(ua[st][kt], yv[st].w, acc[kt][3]);
+        const float uc[4] = {ua[0][kt], ua[1][kt], ua[2][kt], ua[3][kt]};
+        s4 uh, ul;
+        split_bf16(uc, &uh, &ul);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[kt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(uh, yh[c], acc[kt][c], 0, 0, 0);
+          acc[kt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(uh, yl[c], acc[kt][c], 0, 0, 0);
+          acc[kt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ul, yh[c], acc[kt][c], 0, 0, 0);
+        }
       }
+    } else {
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int kt = 0; kt < KTM; ++kt) {
+          if (kt >= KT) continue;
+          acc[kt][0] = mfma4(ua[st][kt], yv[st].x, acc[kt][0]);
+          acc[kt][1] = mfma4(ua[st][kt], yv[st].y, acc[kt][1]);
+          acc[kt][2] = mfma4(ua[st][kt], yv[st].z, acc[kt][2]);
+          acc[kt][3] = mfma4(ua[st][kt], yv[st].w, acc[kt][3]);
+        }
+    }
   };
   // complete slice rows v < R (label v), groups j = chunk + NC (rl + 4i).
   // Loads go to clamped (valid) addresses and rows past R are masked only
@@ -1554,20 +1591,25 @@ __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
 
 __global__ __launch_bounds__(256) void k_rows_a(RowsAArgs p) { rows_a_body(p, blockIdx.x); }
 
-template <int KTT>
+template <int KTT, bool SPLIT>
 __global__ __launch_bounds__(kGemmThreads) void k_core_gemm(CoreGemmArgs p) {
-  core_gemm_body<KTT>(p, blockIdx.x);
+  core_gemm_body<KTT, SPLIT>(p, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kGemmThreads) void k_core_gemm_b(const CoreGemmArgs* d, const int32_t* first,
                                                               int count) {
   const int r = batch_item(first, count, blockIdx.x);
-  core_gemm_body<0>(d[r], blockIdx.x - first[r]);
+  core_gemm_body<0, false>(d[r], blockIdx.x - first[r]);
 }
 
 void launch_core_gemm(const CoreGemmArgs& m, int blocks, hipStream_t s) {
-  if (m.KC <= 16) hipLaunchKernelGGL(k_core_gemm<1>, dim3(blocks), dim3(kGemmThreads), 0, s, m);
-  else hipLaunchKernelGGL(k_core_gemm<2>, dim3(blocks), dim3(kGemmThreads), 0, s, m);
+  if (m.split) {
+    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, true>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+    else hipLaunchKernelGGL((k_core_gemm<2, true>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+  } else {
+    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+    else hipLaunchKernelGGL((k_core_gemm<2, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2351,7 +2393,7 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
 // the updated factor U^(mode): G_(mode) = U^(mode)T Y_(mode). The rows (nonempty
 // slices, then the split-slice partials) are cut into at most kYChunks chunks
 // of equal length; partials are reduced in chunk order.
-hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job) {
+hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split) {
   if (!p->yfuse || !segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
@@ -2373,6 +2415,7 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   int64_t chunks = (nv + kCoreChunk - 1) / kCoreChunk;
   if (chunks > kYChunks) chunks = kYChunks;
   m.nchunk = (int32_t)chunks;
+  m.split = split ? 1 : 0;
   m.gpart = p->sc.gpart;
   job->gemm_blocks = (int)(chunks * g.B);
   CoreRedArgs& r = job->red;
@@ -2401,9 +2444,9 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   return HOQRI_OK;
 }
 
-hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s) {
+hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s, bool split) {
   YCoreJob job;
-  HOQRI_TRY(prepare_ycore(p, mode, G, f_out, &job));
+  HOQRI_TRY(prepare_ycore(p, mode, G, f_out, &job, split));
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
   launch_core_gemm(job.gemm, job.gemm_blocks, s);
   hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
