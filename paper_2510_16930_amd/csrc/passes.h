@@ -56,7 +56,7 @@ struct PrepArgs {
   int32_t Ko[3];          // their ranks
   int64_t gstride[kMaxOrder];  // C-order strides of G
   int32_t nblk;           // blocks of this launch (grid-stride loop)
-  int32_t wide16;         // 1: bfloat16 operand of the one-wave 16-bit passes (their own layout)
+  int32_t wide16;         // bfloat16 operand of the one-wave 16-bit passes: 1 c-tile layout, 2 2x2-block layout
 };
 
 struct FixArgs {

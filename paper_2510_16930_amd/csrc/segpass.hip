@@ -90,6 +90,7 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 constexpr int P_FP32 = 0, P_BF16 = 1, P_FP16 = 2;
 
@@ -712,8 +713,8 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
 }
 
 // The pass itself: one wave per range, SL slices staged per stage-two product.
-// Stage two reads the bfloat16 operand gtop16[kb][64][lane][4] with
-// gtop16[kb][16 b + u][lane][t] = G_(n)^T[256 b + 16 u + 4 (lane/16) + t][16 kb + lane%16]
+// Stage two reads the bfloat16 operand gtop16[kb][32][lane][8] with
+// gtop16[kb][8 b + u][lane][t] = G_(n)^T[256 b + 32 u + 8 (lane/16) + t][16 kb + lane%16]
 // (inside block b, index c*16 + r), which k_prep_gtop writes for this pass.
 // The workgroup first copies it into LDS (KN2 x 32 KB): every stage two reads
 // all of it, and from LDS that costs a short latency instead of an L2 round
@@ -751,7 +752,7 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
     a.meta[w * 4 + 2] = (head_clip ? 1 : 0) | (tail_clip ? 2 : 0);
     a.meta[w * 4 + 3] = 0;
   }
-  const uint16_t* gt = gl + lane * 4;
+  const uint16_t* gt = gl + lane * 8;
   constexpr uint32_t yrowf = 1024;  // floats per stored row (4 blocks)
 
   int slot = 0;
@@ -760,16 +761,19 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
     f4 d[KN2];
 #pragma unroll
     for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
-    // rows q >= SL of the product re-read staged rows and are not used
-    const uint16_t* yr = ybat + (q % SL) * kYs22 + 4 * g;
+    // rows q >= SL of the product re-read staged rows and are not used; lane
+    // group g takes the 8 consecutive indices 32 u + 8 g .. of each 32-wide
+    // step u (v_mfma_f32_16x16x32_bf16 contracts a lane group's 8 entries of
+    // A with the same group's 8 of B)
+    const uint16_t* yr = ybat + (q % SL) * kYs22 + 8 * g;
     // fully unrolled: every LDS address is a base register plus an immediate
 #pragma unroll
-    for (int bu = 0; bu < 64; ++bu) {
-      const s4 av = *reinterpret_cast<const s4*>(yr + 16 * bu);
+    for (int bu = 0; bu < 32; ++bu) {
+      const b8 av = *reinterpret_cast<const b8*>(yr + 32 * bu);
 #pragma unroll
       for (int kb = 0; kb < KN2; ++kb) {
-        const s4 bv = *reinterpret_cast<const s4*>(gt + (kb * 64 + bu) * 256);
-        d[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, d[kb], 0, 0, 0);
+        const b8 bv = *reinterpret_cast<const b8*>(gt + (kb * 32 + bu) * 512);
+        d[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, d[kb], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -1245,9 +1249,16 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
   const int64_t total = (int64_t)p.B * p.KN2 * 4096;
   for (int64_t idx = blk * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)p.nblk * blockDim.x) {
-    const int lane = (int)((idx >> 2) & 63);
+    int lane = (int)((idx >> 2) & 63);
     int kb, b, jp;
-    if (p.wide16) {
+    if (p.wide16 == 2) {
+      // [kb][8 b + u][lane][t] (t < 8): index 32 u + 8 (lane/16) + t inside block b
+      lane = (int)((idx >> 3) & 63);
+      const int bu = (int)((idx >> 9) % (8 * p.B));
+      kb = (int)(idx / (4096 * p.B));
+      b = bu >> 3;
+      jp = 32 * (bu & 7) + 8 * (lane >> 4) + (int)(idx & 7);
+    } else if (p.wide16) {
       // [kb][16 b + u][lane][t]: index 16 u + 4 (lane/16) + t inside block b
       const int bu = (int)((idx >> 8) % (16 * p.B));
       kb = (int)(idx / (4096 * p.B));
@@ -2109,7 +2120,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (nc4 ? kWide4Key + 1000 * tiles4 : 0);
   // stage-two operand
   PrepArgs& pa = job->prep;
-  pa.wide16 = (wide || nc4) ? 1 : 0;
+  pa.wide16 = wide ? 2 : (nc4 ? 1 : 0);
   pa.G = G;
   pa.gtop = p->sc.gtop;
   pa.B = g.B;
