@@ -69,6 +69,13 @@ def make(name):
         # ragged 4-way ranks: c-tile waves with 4, 4 and 1 (or 4 x 4) columns
         dims, K = (3000, 2500, 200, 40), (6, 12, 9, 16)
         idx, vals = synth.coo_zipf(dims, 80_000, alpha=1.1, seed=8, values="uniform")
+    elif name == "tiny3":
+        # fewer nonzeros than one 16-nonzero block; y_i of 2 x 2 blocks in mode 2
+        dims, K = (30, 40, 50), (20, 24, 12)
+        idx, vals = synth.coo_uniform(dims, 7, seed=21)
+    elif name == "tiny4":
+        dims, K = (12, 11, 10, 9), (6, 7, 8, 9)
+        idx, vals = synth.coo_uniform(dims, 5, seed=22)
     elif name == "n2":
         dims, K = (3000, 2000), (8, 8)
         idx, vals = synth.coo_uniform(dims, 40_000, seed=7)
@@ -109,7 +116,7 @@ def bound_check(got, ref, absref, tol_rel, what):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("name", ["c1", "n2", "zipf3", "n3k32", "n3rag", "n4k10", "n4rag", "wide"])
+@pytest.mark.parametrize("name", ["c1", "n2", "zipf3", "n3k32", "n3rag", "n4k10", "n4rag", "tiny3", "tiny4", "wide"])
 def test_16bit_passes_within_rounding_bound(name, prec):
     print(f"[prec] case={name} prec={prec}", flush=True)
     dims, K, idx, vals32, U = make(name)
