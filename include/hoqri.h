@@ -89,7 +89,7 @@ hoqri_status hoqri_plan_info(const hoqri_plan* plan, int64_t* nnz_coalesced, dou
 /* Releases the host object. Frees nothing the caller owns. */
 void hoqri_plan_destroy(hoqri_plan* plan);
 
-/* Core G = X x {U^T} (§2.2; first line of Alg. 3): G(k) = sum over nonzeros of
+/* Core G = X x {U^T} (§2.2; the core Alg. 3 forms before its loop): G(k) = sum over nonzeros of
  * x(i) prod_m U^(m)(i_m, k_m). d_U is a HOST array of N device pointers (factor
  * m row-major I_m x K_m). Writes all prod K_m entries of d_G (C order). If
  * d_f is not NULL, writes f = ||G||^2 (float64, device) there. */

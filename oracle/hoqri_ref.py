@@ -207,7 +207,7 @@ def _letters(N: int):
 
 def core_elementwise(idx, vals, Us: Sequence[np.ndarray], chunk: int = 65536) -> np.ndarray:
     """G(k_1..k_N) = sum over nonzeros x(i) prod_m U^(m)(i_m, k_m): the core of §2.2
-    written out over the nonzero set I(X) of Table 1 (first line of Alg. 3)."""
+    written out over the nonzero set I(X) of Table 1 (the core Alg. 3 forms first)."""
     idx = np.asarray(idx, dtype=np.int64)
     vals = np.asarray(vals, dtype=np.float64)
     N = len(Us)
@@ -386,8 +386,8 @@ def hoqri(idx, vals, dims, ranks, U0: Sequence[np.ndarray], sweeps: int, tol: fl
           stop: str = "rel_f", impl: str = "segment", record_A: bool = False, on_breakdown: str = "raise"):
     """Alg. 2 (HOQRI). Sweeps over n = 1..N in order (Gauss-Seidel: the update of
     mode n sees the already-updated factors of modes < n, as in the single-mode
-    update rule of §5). Per mode: G from the current factors (first line of
-    Alg. 3), A^(n) = TTMcTC, U^(n) = orthonormal basis of A^(n) by QR.
+    update rule of §5). Per mode: G from the current factors (the core
+    Alg. 3 forms first), A^(n) = TTMcTC, U^(n) = orthonormal basis of A^(n) by QR.
 
     U0 must be orthonormal. Stops after `sweeps` sweeps, or earlier when
     stop == "rel_f" and |f_t - f_{t-1}| <= tol * f_t, or stop == "err" and the

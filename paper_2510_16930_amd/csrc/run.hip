@@ -1,7 +1,7 @@
 // Public entry points for the core, TTMcTC and the HOQRI loop (Alg. 2).
 //
 // One sweep = one HOQRI iteration: for n = 1..N, the core G from the current
-// factors (first line of Alg. 3), A^(n) = TTMcTC(X, {U}, n), U^(n) = an
+// factors (the core Alg. 3 forms first), A^(n) = TTMcTC(X, {U}, n), U^(n) = an
 // orthonormal basis of A^(n). Factors updated earlier in the sweep are used by
 // later modes (the single-mode update rule of §5). The core computed after the
 // last mode of a sweep is reused as the first core of the next sweep, so f
