@@ -309,7 +309,7 @@ def main():
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the multi-GPU design is documented, not run",
+        print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU design is documented, not run",
                           "n_gpus": args.gpus}))
         return 2
 
