@@ -69,6 +69,10 @@ def make(name):
         # ragged 4-way ranks: c-tile waves with 4, 4 and 1 (or 4 x 4) columns
         dims, K = (3000, 2500, 200, 40), (6, 12, 9, 16)
         idx, vals = synth.coo_zipf(dims, 80_000, alpha=1.1, seed=8, values="uniform")
+    elif name == "n4kn2":
+        # mode 0 of rank 20 (two 16-column blocks of A) through the c-tile pass
+        dims, K = (3000, 200, 150, 100), (20, 4, 4, 4)
+        idx, vals = synth.coo_zipf(dims, 60_000, alpha=1.1, seed=23, values="uniform")
     elif name == "tiny3":
         # fewer nonzeros than one 16-nonzero block; y_i of 2 x 2 blocks in mode 2
         dims, K = (30, 40, 50), (20, 24, 12)
@@ -116,7 +120,7 @@ def bound_check(got, ref, absref, tol_rel, what):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("name", ["c1", "n2", "zipf3", "n3k32", "n3rag", "n4k10", "n4rag", "tiny3", "tiny4", "wide"])
+@pytest.mark.parametrize("name", ["c1", "n2", "zipf3", "n3k32", "n3rag", "n4k10", "n4rag", "n4kn2", "tiny3", "tiny4", "wide"])
 def test_16bit_passes_within_rounding_bound(name, prec):
     print(f"[prec] case={name} prec={prec}", flush=True)
     dims, K, idx, vals32, U = make(name)
