@@ -139,7 +139,7 @@ struct TtmJob {
 };
 
 struct CoreJob {
-  int key, threads;  // key + 1000: row-writing core pass
+  int key, threads;  // key >= 1000: row-writing core pass (+ 1000, or the c-tile key)
   size_t shmem;
   SegArgs seg;
   int seg_blocks;

@@ -1026,7 +1026,9 @@ __host__ __device__ constexpr int ttm4c_bytes(int B, int nw, int KN2) {
 // gtop16 in the layout of the 2 x 2-block pass generalised to B blocks
 // ([kb][16 b + u][lane][t], u the column c inside block b), from memory:
 // slices are long where this pass is used, so stage two is rare.
-template <int PREC, int NC, int KN2>
+// CORE: the row-writing core pass of the same walk (the core mode's slice
+// rows to a.yrow / a.ycarry for U^(c)T Y_(c); no product with a core).
+template <int PREC, int NC, int KN2, bool CORE = false>
 __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
@@ -1065,6 +1067,7 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
   int slot = 0;
   auto stage_two = [&]() {
     __syncthreads();  // every wave's tiles of the staged slices are in LDS
+    if constexpr (!CORE) {
     f4 d[KN2];
 #pragma unroll
     for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
@@ -1110,6 +1113,7 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
         }
       }
     }
+    }  // !CORE
     if (a.yrow) {
       // the float32 y_s for the core of the updated factor (row by label; a
       // split slice leaves its partial per range and zeros in its own row);
@@ -1172,6 +1176,15 @@ template <int PREC, int NC, int KN2>
 __global__ __launch_bounds__(256) void k_ttm4c_b(const SegArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
   ttm4c_body<PREC, NC, KN2>(d[r], blockIdx.x - first[r]);
+}
+template <int PREC, int NC>
+__global__ __launch_bounds__(256) void k_core4c(SegArgs a) {
+  ttm4c_body<PREC, NC, 1, true>(a, blockIdx.x);
+}
+template <int PREC, int NC>
+__global__ __launch_bounds__(256) void k_core4c_b(const SegArgs* d, const int32_t* first, int count) {
+  const int r = batch_item(first, count, blockIdx.x);
+  ttm4c_body<PREC, NC, 1, true>(d[r], blockIdx.x - first[r]);
 }
 
 // Adds the partial rows of slices that cross range boundaries and writes them.
@@ -1975,6 +1988,8 @@ bool seg_kernels_p(int nm1, int kn2, SegKernels* k) {
 
 template <int PREC, int NC>
 bool seg_kernels_4c_n(int kn2, SegKernels* k) {
+  k->rows = (const void*)k_core4c<PREC, NC>;
+  k->rows_b = (const void*)k_core4c_b<PREC, NC>;
   if (kn2 == 1) {
     k->ttm = (const void*)k_ttm4c<PREC, NC, 1>;
     k->ttm_b = (const void*)k_ttm4c_b<PREC, NC, 1>;
@@ -2187,16 +2202,29 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
   SegArgs& a = job->seg;
   if (!fill_common(a, p, mode, g, op)) return HOQRI_ERR_UNSUPPORTED;
   if (p->core_rows) {
-    job->key += 1000;
     int64_t W = p->core_w;
     if (W > p->nnz) W = p->nnz;
     a.W = (int32_t)W;
-    a.RPW = g.B == 1 ? 4 : 1;
-    a.A = p->sc.ybuf;
-    a.carry = p->sc.ycarry;
-    a.meta = p->sc.ymeta;
-    job->threads = 64 * g.B * a.RPW;
-    job->shmem = (size_t)g.B * a.RPW * 128 * 4;
+    if (ttm_wide4(g, op.prec)) {
+      // 16-bit forms of 4-way tensors: the c-tile walk writes the rows
+      int nw4 = 1;
+      const int tiles4 = tiles4c(g.Ko[2], &nw4);
+      job->key += kWide4Key + 1000 * tiles4;
+      a.RPW = 1;
+      a.yrow = p->sc.ybuf;
+      a.ycarry = p->sc.ycarry;
+      a.meta = p->sc.ymeta;
+      job->threads = 64 * nw4;
+      job->shmem = (size_t)ttm4c_bytes(g.B, nw4, 1);
+    } else {
+      job->key += 1000;
+      a.RPW = g.B == 1 ? 4 : 1;
+      a.A = p->sc.ybuf;
+      a.carry = p->sc.ycarry;
+      a.meta = p->sc.ymeta;
+      job->threads = 64 * g.B * a.RPW;
+      job->shmem = (size_t)g.B * a.RPW * 128 * 4;
+    }
     job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
     CoreGemmArgs& m = job->gemm;
     m.ybuf = p->sc.ybuf;
