@@ -852,8 +852,8 @@ __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, co
 }
 
 // ---------------------------------------------------------------------------
-// TTMcTC pass, 16-bit forms, 4-way tensors whose three other ranks are at most
-// 16: y_i (K_a x K_b x K_c) is computed as accumulator tiles over (a, b), one
+// TTMcTC pass, 4-way tensors whose three other ranks are at most 16 (every
+// operand form): y_i (K_a x K_b x K_c) is computed as accumulator tiles over (a, b), one
 // per index c of the third other mode, four tiles per wave and ceil(K_c / 4)
 // waves per range. Per k-slot a lane gathers one entry of each other factor's
 // row (a = q, b = q, c = c0 + q for the wave's first tile c0); tile c
@@ -863,9 +863,10 @@ __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, co
 // (a K_b + b, c) layout. The waves of a range stage their tiles of finished
 // y_i in LDS in float32, in the block layout of the other passes (blocks of
 // 16 rows r = a K_b + b, columns c), store them from there as rows of Y_(n),
-// and multiply them by G_(n)^T in bfloat16 on the matrix cores (float32
-// accumulation; bfloat16 keeps the range of y_i in both forms), each wave
-// over its own columns c, partial products added in LDS in a fixed order.
+// and multiply them by G_(n)^T on the matrix cores, in bfloat16 in the 16-bit
+// forms (float32 accumulation; bfloat16 keeps the range of y_i) and in
+// float32 in the FP32 form, each wave over its own columns c, partial
+// products added in LDS in a fixed order.
 // ---------------------------------------------------------------------------
 // c-tiles per wave: waves per range nw = ceil(K_c / 6), tiles per wave
 // NC = ceil(K_c / nw) (4 to 6; fewer tiles than that still run 4)
@@ -912,9 +913,15 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
     auto& SJ = J;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      S.u0[t] = ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + k2);
-      S.u1[t] = ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + k2);
-      S.u2[t] = ld_u16(rU2, ((uint32_t)SJ.j2[t] << 1) + k2c);
+      if constexpr (PREC == P_FP32) {
+        S.u0[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, ((uint32_t)SJ.j0[t] << 2) + k2, 0, 0);
+        S.u1[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, ((uint32_t)SJ.j1[t] << 2) + k2, 0, 0);
+        S.u2[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU2, ((uint32_t)SJ.j2[t] << 2) + k2c, 0, 0);
+      } else {
+        S.u0[t] = ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + k2);
+        S.u1[t] = ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + k2);
+        S.u2[t] = ld_u16(rU2, ((uint32_t)SJ.j2[t] << 1) + k2c);
+      }
     }
   };
 
@@ -939,8 +946,13 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
     for (int t = 0; t < 4; ++t) {
       // FP16: the scale goes first, so no intermediate can exceed the bound
       const float xv = (PREC == P_FP16) ? xq[t] * a.ascale : xq[t];
-      xa[t] = xv * f16bits_to_f32<PREC>(C.u0[t]);
-      uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
+      if constexpr (PREC == P_FP32) {
+        xa[t] = xv * __builtin_bit_cast(float, C.u0[t]);
+        uc[t] = __builtin_bit_cast(float, C.u2[t]);
+      } else {
+        xa[t] = xv * f16bits_to_f32<PREC>(C.u0[t]);
+        uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
+      }
     }
     load_idx(blk + 3, C);
     gather(N2);
@@ -957,6 +969,15 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
           const h2 a1 = xp1 * __builtin_bit_cast(h2, row_bcast<c>(up1));
           const h4 ah = {a0.x, a0.y, a1.x, a1.y};
           acc[c] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, __builtin_bit_cast(h4, bv), acc[c], 0, 0, 0);
+        });
+      } else if constexpr (PREC == P_FP32) {
+        // float32: one v_mfma_f32_16x16x4f32 per k-slot t (k = lane group)
+        static_for<0, NC>([&](auto ci) {
+          constexpr int c = decltype(ci)::value;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[c] = mfma4(av[t] * __builtin_bit_cast(float, row_bcast<c>(__builtin_bit_cast(int32_t, uc[t]))),
+                           __builtin_bit_cast(float, C.u1[t]), acc[c]);
         });
       } else {
         static_for<0, NC>([&](auto ci) {
@@ -1060,6 +1081,7 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
   }
   const int c0 = NC * wv;  // this wave's first column c
   const uint16_t* gt = reinterpret_cast<const uint16_t*>(a.gtop) + lane * 4;
+  const float* gt32 = a.gtop + lane * 4;
   const uint32_t yrowf = (uint32_t)B * 256;
   const int K0 = a.K0, K1 = a.K1;
   const int cw = a.K2 - c0 < NC ? a.K2 - c0 : NC;  // columns of this wave
@@ -1076,12 +1098,23 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
       for (int u = c0; u < c0 + cw; ++u) {
         const int bu = 16 * b + u;
         const f4 yv = *reinterpret_cast<const f4*>(yr + 16 * bu);
-        const b4 yb = {(__bf16)yv.x, (__bf16)yv.y, (__bf16)yv.z, (__bf16)yv.w};
-        const s4 av = __builtin_bit_cast(s4, yb);
+        if constexpr (PREC == P_FP32) {
+          // float32 operand in the same order ([kb][16 b + u][lane][t]), one
+          // v_mfma_f32_16x16x4f32 per t
 #pragma unroll
-        for (int kb = 0; kb < KN2; ++kb) {
-          const s4 gv = *reinterpret_cast<const s4*>(gt + ((size_t)kb * 16 * B + bu) * 256);
-          d[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, gv, d[kb], 0, 0, 0);
+          for (int kb = 0; kb < KN2; ++kb) {
+            const f4 gv = *reinterpret_cast<const f4*>(gt32 + ((size_t)kb * 16 * B + bu) * 256);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) d[kb] = mfma4(yv[t], gv[t], d[kb]);
+          }
+        } else {
+          const b4 yb = {(__bf16)yv.x, (__bf16)yv.y, (__bf16)yv.z, (__bf16)yv.w};
+          const s4 av = __builtin_bit_cast(s4, yb);
+#pragma unroll
+          for (int kb = 0; kb < KN2; ++kb) {
+            const s4 gv = *reinterpret_cast<const s4*>(gt + ((size_t)kb * 16 * B + bu) * 256);
+            d[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, gv, d[kb], 0, 0, 0);
+          }
         }
       }
     }
@@ -1139,7 +1172,8 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
     slot = 0;
   };
 
-  walk_range4c<PREC, NC>(a, lo, hi, s_first, s_last, (uint32_t)q * 2u, (uint32_t)(c0 + q) * 2u, lane, wlds,
+  constexpr uint32_t es = PREC == P_FP32 ? 4u : 2u;  // bytes per factor entry
+  walk_range4c<PREC, NC>(a, lo, hi, s_first, s_last, (uint32_t)q * es, (uint32_t)(c0 + q) * es, lane, wlds,
                      [&](int32_t s, int32_t row, const f4* y) {
     // tile c0 + c, lane (g, q): y[a = 4g + v][b = q][c0 + c]; block row r = a K1 + b
     float* ys = ybat + slot * YSB;
@@ -1273,6 +1307,7 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
       jp = 32 * (bu & 7) + 8 * (lane >> 4) + (int)(idx & 7);
     } else if (p.wide16) {
       // [kb][16 b + u][lane][t]: index 16 u + 4 (lane/16) + t inside block b
+      // (bfloat16; wide16 == 3: the same order in float32)
       const int bu = (int)((idx >> 8) % (16 * p.B));
       kb = (int)(idx / (4096 * p.B));
       b = bu >> 4;
@@ -1299,7 +1334,7 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
       }
       v = p.G[off];
     }
-    if (p.wide16) reinterpret_cast<uint16_t*>(p.gtop)[idx] = __builtin_bit_cast(uint16_t, (__bf16)v);
+    if (p.wide16 == 1 || p.wide16 == 2) reinterpret_cast<uint16_t*>(p.gtop)[idx] = __builtin_bit_cast(uint16_t, (__bf16)v);
     else p.gtop[idx] = v;
   }
 }
@@ -2026,6 +2061,7 @@ bool seg_kernels(int key, SegKernels* k) {
     if (nm1 != 3 || kn2 > 2) return false;
     if (prec == P_BF16) return seg_kernels_4c<P_BF16>(nc4, kn2, k);
     if (prec == P_FP16) return seg_kernels_4c<P_FP16>(nc4, kn2, k);
+    if (prec == P_FP32) return seg_kernels_4c<P_FP32>(nc4, kn2, k);
     return false;
   }
   if (!ok || !wide) return ok;
@@ -2044,10 +2080,11 @@ bool seg_kernels(int key, SegKernels* k) {
 // ranks both lie in 17..32.
 bool ttm_wide(const PassGeom& g, int prec) { return prec == OP_BF16 && g.nm1 == 2 && g.RB == 2 && g.CB == 2; }
 
-// The 4-way c-tile pass takes the 16-bit forms when all three other ranks are
-// at most 16 (every y_i then fits the staging of one range).
+// The 4-way c-tile pass takes every operand form when all three other ranks
+// are at most 16 (every y_i then fits the staging of one range).
 bool ttm_wide4(const PassGeom& g, int prec) {
-  return prec != OP_FP32 && g.nm1 == 3 && g.Ko[0] <= 16 && g.Ko[1] <= 16 && g.Ko[2] <= 16;
+  (void)prec;
+  return g.nm1 == 3 && g.Ko[0] <= 16 && g.Ko[1] <= 16 && g.Ko[2] <= 16;
 }
 
 // Waves (ranges) per workgroup of that pass: as many as the LDS of one
@@ -2135,7 +2172,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (nc4 ? kWide4Key + 1000 * tiles4 : 0);
   // stage-two operand
   PrepArgs& pa = job->prep;
-  pa.wide16 = wide ? 2 : (nc4 ? 1 : 0);
+  pa.wide16 = wide ? 2 : (nc4 ? (op.prec == OP_FP32 ? 3 : 1) : 0);
   pa.G = G;
   pa.gtop = p->sc.gtop;
   pa.B = g.B;
@@ -2511,6 +2548,9 @@ hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hi
   r.groups = ((int64_t)r.R + 2 * (int64_t)r.W + 15) / 16;
   r.A = A;
   r.carry = p->sc.carry;
+  // k_rows_a reads the operand in the classic float32 order, whatever order
+  // this mode's TTMcTC pass uses
+  job.prep.wide16 = 0;
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
   hipLaunchKernelGGL(k_prep_gtop, dim3(job.prep_blocks), dim3(256), 0, s, job.prep);
   hipLaunchKernelGGL(k_rows_a, dim3((unsigned)((r.groups + 3) / 4)), dim3(256), 0, s, r);
