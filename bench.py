@@ -91,14 +91,14 @@ for _e in (3, 4, 5, 6):
 
 def ttm_kernel_name(dims, ranks, prec):
     """The TTMcTC kernel the library picks: one wave for all of y_i in the BF16
-    form of 3-way tensors whose other ranks lie in 17..32; four c-tiles per
-    wave in the 16-bit forms of 4-way tensors with ranks up to 16; else one
-    wave per 16x16 block of y_i."""
+    form of 3-way tensors whose other ranks lie in 17..32; c-tiles of y_i per
+    wave for 4-way tensors with ranks up to 16; else one wave per 16x16 block
+    of y_i."""
     N = len(dims)
     if prec == "bf16" and N == 3 and all(16 < ranks[m] <= 32 for m in range(N)):
         return "k_ttm22<bf16> (TTMcTC segment pass, 2x2 blocks of y_i per wave)"
-    if prec != "fp32" and N == 4 and all(k <= 16 for k in ranks):
-        return f"k_ttm4c<{prec}> (TTMcTC segment pass, 4 c-tiles of y_i per wave)"
+    if N == 4 and all(k <= 16 for k in ranks):
+        return f"k_ttm4c<{prec}> (TTMcTC segment pass, c-tiles of y_i per wave)"
     return f"k_ttm<{prec}> (TTMcTC segment pass)"
 
 
