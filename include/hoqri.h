@@ -55,11 +55,15 @@ typedef enum {
   HOQRI_FP16 = 3   /* float16 operands with a power-of-two scale per factor, float32 accumulate */
 } hoqri_prec;
 
-/* Limits: 2 <= N <= 5; 1 <= K_n <= 32; nnz < 2^30; every I_n < 2^31 and
- * I_n * K_n * 4 bytes < 2^32. Modes with N <= 4 and prod_{m!=n} K_m within 8
- * blocks of 16 x 16 take the segment passes (every operand form, stored slice
- * rows, HOOI, the server); other modes (N = 5, wider Kronecker rows) take the
- * generic kernels, float32 operands only (HOQRI_ERR_UNSUPPORTED otherwise). */
+/* Limits: 2 <= N <= 5; 1 <= K_n <= 32; nnz < 2^30 and 4 N ceil16(nnz) bytes
+ * < 2^32 (one mode's block records: nnz below about 268M at N = 4, 358M at
+ * N = 3); every I_n < 2^31, I_1 * ... * I_N <= 2^63 (C-order linear keys in
+ * 64 bits) and I_n * K_n * 4 bytes < 2^32. Shapes beyond these return
+ * HOQRI_ERR_UNSUPPORTED (HOQRI_ERR_ARG for nnz or I_n out of range). Modes
+ * with N <= 4 and prod_{m!=n} K_m within 8 blocks of 16 x 16 take the segment
+ * passes (every operand form, stored slice rows, HOOI, the server); other
+ * modes (N = 5, wider Kronecker rows) take the generic kernels, float32
+ * operands only (HOQRI_ERR_UNSUPPORTED otherwise). */
 #define HOQRI_MAX_ORDER 5
 #define HOQRI_MAX_RANK 32
 

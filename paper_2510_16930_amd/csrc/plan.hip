@@ -338,6 +338,16 @@ hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, in
   if (nnz < 1 || nnz >= (int64_t(1) << 30)) return HOQRI_ERR_ARG;
   for (int n = 0; n < N; ++n)
     if (dims[n] < 1 || dims[n] >= (int64_t(1) << 31)) return HOQRI_ERR_ARG;
+  // Duplicates are found by sorting C-order linear keys (uint64): the product
+  // of the dims must not exceed 2^63, or distinct coordinates could share a key.
+  unsigned __int128 cells = 1;
+  for (int n = 0; n < N; ++n) {
+    cells *= (unsigned __int128)dims[n];
+    if (cells > ((unsigned __int128)1 << 63)) return HOQRI_ERR_UNSUPPORTED;
+  }
+  // A mode's block records (4 N bytes per nonzero, padded to 16 nonzeros) are
+  // read through buffer descriptors with 32-bit byte offsets.
+  if ((nnz + 15) / 16 * 16 * 4 * (int64_t)N >= (int64_t(1) << 32)) return HOQRI_ERR_UNSUPPORTED;
   for (int n = 0; n < N; ++n) {
     if (K[n] < 1 || K[n] > dims[n]) return HOQRI_ERR_RANK;
     int64_t other = 1;

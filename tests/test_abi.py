@@ -76,3 +76,26 @@ def test_orth_argument_validation(lib):
     assert lib.hoqri_orth(3, 4, None, None, None, None, None, 0, None) == -1
     assert lib.hoqri_orth(100, 40, None, None, None, None, None, 0, None) == -1
     assert lib.hoqri_orth_workspace_size(1000, 16) > 0
+
+
+def test_record_stream_limit(lib):
+    # one mode's block records take 4 N bytes per nonzero (padded to 16) and are
+    # addressed with 32-bit byte offsets: 4 N ceil16(nnz) must stay below 2^32
+    dims4, K4 = [200_000, 200_000, 5_000, 1_000], [10, 10, 10, 10]
+    assert _ws(lib, 4, dims4, K4, 300_000_000) == -7
+    assert _ws(lib, 4, dims4, K4, (1 << 32) // 16) == -7          # exactly 2^32 bytes
+    assert _ws(lib, 3, [1_000_000, 500_000, 20_000], [16] * 3, 358_000_000) == -7
+    # just below the limit the shape passes validation (the device query that
+    # follows needs a GPU, so only "not UNSUPPORTED / not ARG" is checked here)
+    ok = _ws(lib, 4, dims4, K4, (1 << 32) // 16 - 16)
+    assert ok not in (-1, -3, -7)
+
+
+def test_linear_key_limit(lib):
+    # duplicates are merged by sorting C-order linear keys in 64 bits: the
+    # product of the dims must not exceed 2^63 (2^22 per mode of a 3-way tensor
+    # is 2^66 and used to wrap the key stride to zero)
+    assert _ws(lib, 3, [1 << 22] * 3, [4] * 3, 1000) == -7
+    assert _ws(lib, 5, [(1 << 31) - 1] * 5, [2] * 5, 1000) == -7
+    assert _ws(lib, 3, [1 << 21, 1 << 21, 1 << 21], [4] * 3, 1000) not in (-1, -3, -7)  # 2^63 exactly
+    assert _ws(lib, 3, [(1 << 21) + 1, 1 << 21, 1 << 21], [4] * 3, 1000) == -7

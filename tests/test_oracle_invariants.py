@@ -176,8 +176,37 @@ def test_stopping_rules():
     _, _, h = O.hoqri(idx, vals, dims, K, start, sweeps=200, tol=1e-6, stop="rel_f")
     f = h["f_sweep"]
     assert len(f) < 200 and abs(f[-1] - f[-2]) <= 1e-6 * f[-1]
-    _, _, h2 = O.hoqri(idx, vals, dims, K, start, sweeps=200, tol=1e-12, stop="err")
-    assert len(h2["f_sweep"]) <= 200
+
+
+def test_error_change_stop_rule_replayed_by_hand():
+    # §6.1 stops when the change of the relative approximation error
+    # eps_t = ||X - G x {U}||_F / ||X||_F = sqrt((||X||^2 - f_t) / ||X||^2)
+    # between consecutive iterations is below tol. Replay it from an unstopped
+    # run: the stopped run must end at the first sweep t with
+    # |eps_t - eps_{t-1}| < tol (eps_0 from the starting factors), and the
+    # fixture is chosen so that comparing squared errors, or not advancing
+    # eps_{t-1}, would stop elsewhere.
+    dims, K = (30, 30, 30), (2, 2, 2)
+    idx, vals = synth.coo_uniform(dims, 300, seed=15)
+    start = O.orthonormal_start(synth.gaussian_start(dims, K, 9))
+    _, _, full = O.hoqri(idx, vals, dims, K, start, sweeps=40)
+    nx2 = float(np.sum(np.asarray(vals, np.float64) ** 2))
+    assert full["normx2"] == pytest.approx(nx2, rel=1e-14)
+    fs = [full["f_step"][0]] + full["f_sweep"]          # f before sweep 1, after each sweep
+    eps = np.sqrt(np.maximum(nx2 - np.array(fs), 0.0) / nx2)
+    tol = 9e-6
+    d = np.abs(np.diff(eps))                            # d[t-1] = |eps_t - eps_{t-1}|
+    k = int(np.argmax(d < tol)) + 1
+    assert d[k - 1] < tol and np.all(d[:k - 1] >= tol) and 1 < k < 40
+    k_sq = int(np.argmax(np.abs(np.diff(eps ** 2)) < tol)) + 1
+    stale = np.abs(eps[1:] - eps[0]) < tol
+    assert k_sq != k and not stale.any()                # the plausible mistakes differ
+    _, _, h = O.hoqri(idx, vals, dims, K, start, sweeps=40, tol=tol, stop="err")
+    assert len(h["f_sweep"]) == k
+    np.testing.assert_allclose(h["f_sweep"], full["f_sweep"][:k], rtol=0, atol=0)
+    # a tolerance no change reaches runs every sweep
+    _, _, h0 = O.hoqri(idx, vals, dims, K, start, sweeps=12, tol=1e-300, stop="err")
+    assert len(h0["f_sweep"]) == 12
 
 
 def test_rank_deficient_mode_is_kept_on_request():
