@@ -7,10 +7,14 @@ ABI of libhoqri.so. Inputs are generated on the device from a seed and are
 resident in HBM before the timed region; the plan (sorted copies, slice
 tables) is built once, outside the timed region, and reported separately.
 
-Prints one JSON line. `roofline` describes the dominant kernel (the TTMcTC
-segment pass) from HIP events recorded around its launches during the timed
-region; `cpu_baseline` times the FP64 numpy oracle on a bounded sample of the
-same tensor on the host cores.
+Prints one JSON line. The default workload is the 50M-nonzero 3-way tensor at
+ranks 32^3 in the BF16 form (`value`), with the plain FP32 form run after it
+on the same plan from the same start for the same sweeps (`compare`, the fit
+gap and whether the fits are equal within 1e-4). `roofline` describes the
+dominant kernel (the TTMcTC segment pass) from HIP events recorded around its
+launches during the timed region, against the algorithmic bytes and flops of
+the segment-first count; `cpu_baseline` times the FP64 numpy oracle on a
+bounded sample of the same tensor on the host cores (and on one thread).
 """
 from __future__ import annotations
 
@@ -39,11 +43,12 @@ CONFIGS = {
                   values="lognormal", seed=12, init_seed=113, prec="fp32",
                   desc="c2 tensor at ranks 32^3, FP32 form"),
     "c3": dict(dims=(1_000_000, 500_000, 20_000), ranks=(32, 32, 32), nnz=50_000_000, dist="zipf", alpha=1.2,
-               values="lognormal", seed=12, init_seed=113, prec="bf16",
-               desc="c2 tensor at ranks 32^3, Kronecker x core products in BF16 on MFMA, FP32 accumulation, "
-                    "FP64 CholeskyQR2"),
+               values="lognormal", seed=12, init_seed=113, prec="bf16", compare="fp32",
+               desc="3-way 1e6 x 5e5 x 2e4, nnz 50M, Zipf(1.2) indices (duplicates merged), lognormal(0,1) values, "
+                    "int32 COO, ranks 32^3: Kronecker x core products in BF16 on MFMA with FP32 accumulation, "
+                    "FP64 CholeskyQR2, against the plain FP32 form from the same start at 20 sweeps"),
     "c4": dict(dims=(200_000, 200_000, 5_000, 1_000), ranks=(10, 10, 10, 10), nnz=100_000_000, dist="zipf",
-               alpha=1.1, values="uniform", seed=14, init_seed=114, prec="fp16",
+               alpha=1.1, values="uniform", seed=14, init_seed=114, prec="fp16", compare="fp32",
                desc="4-way 2e5 x 2e5 x 5e3 x 1e3, nnz 100M, Zipf(1.1), uniform(0,1) values, ranks 10^4, "
                     "FP16 MFMA form (power-of-two scaled), FP32 accumulation"),
     "c5": dict(serve=True, n_requests=2000, seed=15, arena_gib=8.0, max_slots=64, max_sweeps=30, tol=1e-6,
@@ -104,10 +109,13 @@ def ttm_kernel_name(dims, ranks, prec):
 
 def pass_work(dims, ranks, nnz, R, su=4):
     """Algorithmic flops and HBM bytes of one TTMcTC pass per mode (segment-first
-    count: 2 nnz prod K_{-n} + 2 R_n prod K flops; indices + values streamed once,
-    each needed factor row read once (su bytes per entry: 4 for float32, 2 for
-    the 16-bit copies), the output written once, and the slice rows Y_(n)
-    (R_n x prod K_{-n} float32) written once for the core of the updated factor)."""
+    count of the paper's second complexity: 2 nnz prod K_{-n} + 2 R_n prod K
+    flops; bytes: indices + values streamed once, the slice table, each needed
+    factor row read once (su bytes per entry: 4 for float32, 2 for the 16-bit
+    copies) and the output A^(n) written once). Returns (flops, bytes,
+    design_bytes) per mode, design_bytes being what this library's pass also
+    writes by design: the slice rows Y_(n) (R_n x prod K_{-n} float32) kept for
+    the core of the updated factor."""
     N = len(dims)
     PK = math.prod(ranks)
     out = []
@@ -115,8 +123,8 @@ def pass_work(dims, ranks, nnz, R, su=4):
         P = PK // ranks[n]
         flops = 2 * nnz * P + 2 * R[n] * PK
         byts = nnz * (4 * (N - 1) + 4) + 8 * R[n] + sum(R[m] * ranks[m] * su for m in range(N) if m != n) \
-            + 4 * dims[n] * ranks[n] + 4 * R[n] * P
-        out.append((flops, byts))
+            + 4 * dims[n] * ranks[n]
+        out.append((flops, byts, 4 * R[n] * P))
     return out
 
 
@@ -158,23 +166,14 @@ def make_input(cfg, dev):
     return synth.coo_uniform_torch(cfg["dims"], cfg["nnz"], cfg["seed"], cfg["values"], device=dev)
 
 
-def cpu_baseline(idx_cpu, vals_cpu, dims, ranks, U0_cpu, nnz_full, budget_s=20.0):
-    """Times one FP64 oracle sweep on a prefix sample of the nonzeros; scales the
-    pass time linearly in nnz and adds the (nnz-independent) QR time."""
+def _oracle_sweep(idx, vals, ranks, U0_cpu):
+    """One FP64 oracle sweep (per mode: core, TTMcTC slice pass, QR) on the given
+    nonzeros; returns (pass seconds, QR seconds)."""
     import numpy as np
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    N = len(dims)
-    S = min(nnz_full, 400_000)
-    idx = idx_cpu[:, :S].astype(np.int64)
-    vals = vals_cpu[:S].astype(np.float64)
     U = [u.astype(np.float64) for u in U0_cpu]
     t_pass = t_qr = 0.0
-    for n in range(N):
+    for n in range(len(ranks)):
         t0 = time.perf_counter()
         G = O.core_segment(idx, vals, U)
         A = O.ttmctc_segment(idx, vals, U, n, G)
@@ -186,10 +185,35 @@ def cpu_baseline(idx_cpu, vals_cpu, dims, ranks, U0_cpu, nnz_full, budget_s=20.0
         t2 = time.perf_counter()
         t_pass += t1 - t0
         t_qr += t2 - t1
+    return t_pass, t_qr
+
+
+def cpu_baseline(idx_cpu, vals_cpu, dims, ranks, U0_cpu, nnz_full, budget_s=12.0):
+    """Times one FP64 oracle sweep on a prefix sample of the nonzeros, on all the
+    host threads BLAS uses and on one thread; scales the pass time linearly in
+    nnz (the passes are linear in the nonzeros) and adds the nnz-independent QR
+    time. The sample is sized from a small probe to take about budget_s."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    n_avail = idx_cpu.shape[1]
+    S0 = min(n_avail, 20_000)
+    tp, tq = _oracle_sweep(idx_cpu[:, :S0].astype(np.int64), vals_cpu[:S0].astype(np.float64), ranks, U0_cpu)
+    S = int(min(n_avail, max(S0, S0 * max(budget_s - tq, 1.0) / max(tp, 1e-3))))
+    idx = idx_cpu[:, :S].astype(np.int64)
+    vals = vals_cpu[:S].astype(np.float64)
+    t_pass, t_qr = _oracle_sweep(idx, vals, ranks, U0_cpu)
     t_sweep = t_pass * (nnz_full / S) + t_qr
+    S1 = max(S0, S // 4)
+    with threadpool_limits(limits=1):
+        tp1, tq1 = _oracle_sweep(idx[:, :S1], vals[:S1], ranks, U0_cpu)
+    t_sweep1 = tp1 * (nnz_full / S1) + tq1
     return {"value": 1.0 / t_sweep, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
             "sample": f"one FP64 numpy sweep (N core + N TTMcTC slice passes + N QR) on the first {S} of "
-                      f"{nnz_full} nonzeros: passes {t_pass:.2f} s scaled x{nnz_full / S:.1f}, QR {t_qr:.2f} s"}
+                      f"{nnz_full} nonzeros: passes {t_pass:.2f} s scaled x{nnz_full / S:.1f}, QR {t_qr:.2f} s",
+            "single_thread": {"value": 1.0 / t_sweep1, "unit": "iters/s", "cores": 1,
+                              "sample": f"the first {S1} nonzeros: passes {tp1:.2f} s scaled x{nnz_full / S1:.1f}, "
+                                        f"QR {tq1:.2f} s"}}
 
 
 def copy_calibration():
@@ -297,7 +321,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--method", default="hoqri", choices=("hoqri", "hooi"),
                     help="hooi: Alg. 1 on the same passes (orthogonal iteration per mode update)")
@@ -338,34 +362,43 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] plan ready ({t_plan:.2f} s, nnz={nnz}, R={R}); warmup", file=sys.stderr, flush=True)
 
-    Us = [u.clone() for u in U0]
     # a numerically rank-deficient mode update is skipped (counted) rather than
     # ending the run: very sparse random tensors reach it after a few sweeps
     meth = dict(method=args.method, inner_iters=args.inner_iters if args.method == "hooi" else 1,
                 keep_on_breakdown=True)
-    if args.warmup > 0:
-        H.hoqri_run(plan, Us, max_sweeps=args.warmup, prec=cfg["prec"], check_every=args.warmup, **meth)
-    for u, u0 in zip(Us, U0):
-        u.copy_(u0)
-    torch.cuda.synchronize()
-    H.hoqri_timing_enable(plan, True)
-    print("[bench] timed region", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    G, st = H.hoqri_run(plan, Us, max_sweeps=args.steps, prec=cfg["prec"], check_every=args.steps, **meth)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kt = {k: H.hoqri_timing_read(plan, k) for k in ("ttmctc", "core", "orth", "fixup")}
-    H.hoqri_timing_enable(plan, False)
 
-    work = pass_work(dims, ranks, nnz, R, 4 if cfg["prec"] == "fp32" else 2)
+    def run_form(prec, label):
+        """Warm-up sweeps, then the timed sweeps from U0 (barrier + synchronise on
+        both sides); HIP events around the kernels of this plan."""
+        Us = [u.clone() for u in U0]
+        if args.warmup > 0:
+            H.hoqri_run(plan, Us, max_sweeps=args.warmup, prec=prec, check_every=args.warmup, **meth)
+        for u, u0 in zip(Us, U0):
+            u.copy_(u0)
+        torch.cuda.synchronize()
+        H.hoqri_timing_enable(plan, True)
+        print(f"[bench] timed region ({label})", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        G, st = H.hoqri_run(plan, Us, max_sweeps=args.steps, prec=prec, check_every=args.steps, **meth)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kt = {k: H.hoqri_timing_read(plan, k) for k in ("ttmctc", "core", "orth", "fixup")}
+        H.hoqri_timing_enable(plan, False)
+        return st, elapsed, kt, Us
+
+    prec = cfg["prec"]
+    st, elapsed, kt, _ = run_form(prec, prec)
     sweeps = st.sweeps
+
+    work = pass_work(dims, ranks, nnz, R, 4 if prec == "fp32" else 2)
     ttm_launch, ttm_ms = kt["ttmctc"]
     ttm_flops = sweeps * sum(w[0] for w in work)
     ttm_bytes = sweeps * sum(w[1] for w in work)
+    ttm_design = sweeps * sum(w[2] for w in work)
     ttm_s = ttm_ms / 1e3
     achieved_flops = ttm_flops / ttm_s
     achieved_bytes = ttm_bytes / ttm_s
-    prec = cfg["prec"]
+    per = max(ttm_launch, 1)
     # the binding roof is the one whose peak needs more time for the algorithmic work
     mfma_bound = ttm_flops / PEAK[prec] >= ttm_bytes / HBM_PEAK
     if mfma_bound:
@@ -374,15 +407,20 @@ def main():
     else:
         rl = dict(bound="hbm", achieved=round(achieved_bytes / 1e9, 1), peak=HBM_PEAK / 1e9, unit="GB/s",
                   frac=round(achieved_bytes / HBM_PEAK, 4))
+    traffic = measured_traffic(args.config, prec)
     roofline = {
         **rl,
-        "traffic": measured_traffic(args.config, prec),
+        "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
+        "traffic_over_algorithmic": round(traffic / (ttm_bytes / per), 2) if traffic else None,
         "kernel": ttm_kernel_name(dims, ranks, prec),
         "launches": ttm_launch,
-        "avg_launch_ms": round(ttm_ms / max(ttm_launch, 1), 4),
-        "algorithmic_flops_per_launch": int(ttm_flops / max(ttm_launch, 1)),
-        "algorithmic_bytes_per_launch": int(ttm_bytes / max(ttm_launch, 1)),
+        "avg_launch_ms": round(ttm_ms / per, 4),
+        "algorithmic_flops_per_launch": int(ttm_flops / per),
+        "algorithmic_bytes_per_launch": int(ttm_bytes / per),
+        "design_bytes_per_launch": int(ttm_design / per),
+        "design_bytes_note": "slice rows Y_(n) the pass also stores (float32) for the core of the updated factor; "
+                             "not part of the algorithmic bytes",
         "hbm_GBps_algorithmic": round(achieved_bytes / 1e9, 1),
         "hbm_frac_algorithmic": round(achieved_bytes / HBM_PEAK, 4),
         "mfma_frac_algorithmic": round(achieved_flops / PEAK[prec], 4),
@@ -416,6 +454,34 @@ def main():
         "input_gen_s": round(t_gen, 2),
         "roofline": roofline,
     }
+    cmp_prec = cfg.get("compare")
+    if cmp_prec and args.method == "hoqri":
+        # the plain FP32 form on the same plan, from the same U0, same sweeps;
+        # equal fit: the 16-bit form's fit within 1e-4 relative of the FP32
+        # form's (which matches the FP64 oracle to float32 accuracy at test sizes)
+        st2, el2, kt2, _ = run_form(cmp_prec, cmp_prec)
+        gap = abs(st.fit - st2.fit) / abs(st2.fit)
+        cmp = {"form": cmp_prec, "iters_per_s": round(st2.sweeps / el2, 3), "ms_per_step": round(1e3 * el2 / st2.sweeps, 4),
+               "fit": st2.fit, "ttmctc_avg_launch_ms": round(kt2["ttmctc"][1] / max(kt2["ttmctc"][0], 1), 4),
+               "kernel_ms": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in kt2.items()}}
+        line["compare"] = cmp
+        line["fit_gap_rel"] = gap
+        line["equal_fit"] = bool(gap <= 1e-4)
+        line["speedup_vs_" + cmp_prec] = round((sweeps / elapsed) / (st2.sweeps / el2), 3)
+        if gap > 1e-4:
+            # not qualifying: sweeps of this form until its fit reaches (1 - 1e-4) x the FP32 form's
+            target = (1.0 - 1e-4) * st2.fit
+            for t in range(sweeps + 1, 4 * sweeps + 1):
+                Us = [u.clone() for u in U0]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, s3 = H.hoqri_run(plan, Us, max_sweeps=t, prec=prec, check_every=t, **meth)
+                torch.cuda.synchronize()
+                if s3.fit >= target:
+                    line["time_to_fit"] = {"sweeps": t, "ms": round(1e3 * (time.perf_counter() - t0), 3)}
+                    break
+            else:
+                line["time_to_fit"] = None
     if not args.no_cpu_baseline and args.method == "hoqri":
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         ncpu = min(nnz, 400_000)

@@ -52,7 +52,11 @@ typedef enum {
 typedef enum {
   HOQRI_FP32 = 1,  /* float32 operands on the float32 matrix cores */
   HOQRI_BF16 = 2,  /* bfloat16 operands (round to nearest even), float32 accumulate */
-  HOQRI_FP16 = 3   /* float16 operands with a power-of-two scale per factor, float32 accumulate */
+  HOQRI_FP16 = 3   /* float16 operands, float32 accumulate: factor copies scaled by 2^15 and the
+                      value x row-entries operand by a power of two chosen from max|x|, both
+                      removed exactly. Factor entries must have magnitude below 1.5 (orthonormal
+                      columns give at most 1): hoqri_core, hoqri_ttmctc and hoqri_run check this
+                      with one synchronisation before any pass and return HOQRI_ERR_ARG otherwise */
 } hoqri_prec;
 
 /* Limits: 2 <= N <= 5; 1 <= K_n <= 32; nnz < 2^30 and 4 N ceil16(nnz) bytes
@@ -128,7 +132,7 @@ hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A, float* d_U
 
 typedef struct {
   int32_t max_sweeps;   /* sweeps over all N modes (one sweep = one HOQRI iteration) */
-  double tol;           /* stop when |f_t - f_{t-1}| <= tol * f_t (0 disables) */
+  double tol;           /* stop rule threshold (0 disables); the rule is chosen by stop_rule */
   hoqri_prec prec;      /* operand precision of the segment passes */
   int32_t check_every;  /* read f back every this many sweeps (>= 1) */
   int32_t orthonormalize_input; /* nonzero: first replace each U^(n) by its orthonormal basis */
@@ -141,7 +145,16 @@ typedef struct {
   double grad_tol;      /* > 0: also stop when sqrt(sum_n ||grad_n||^2) over a sweep <= grad_tol * f_t */
   int32_t method;       /* HOQRI_METHOD_HOQRI (0, Alg. 2) or HOQRI_METHOD_HOOI (Alg. 1) */
   int32_t inner_iters;  /* HOOI: orthogonal-iteration steps per mode update (>= 1; 0 means 1) */
+  int32_t stop_rule;    /* HOQRI_STOP_REL_F (0): stop when |f_t - f_{t-1}| <= tol * f_t;
+                           HOQRI_STOP_ERR_CHANGE (1): stop when the relative approximation error
+                           eps_t = sqrt(max(||X||^2 - f_t, 0) / ||X||^2) changes by less than tol,
+                           |eps_t - eps_{t-1}| < tol (the rule of the experiments in §6.1).
+                           Both rules compare the last two sweeps (f_0: the starting factors)
+                           at every check (every check_every sweeps) */
 } hoqri_run_opts;
+
+#define HOQRI_STOP_REL_F 0
+#define HOQRI_STOP_ERR_CHANGE 1
 
 /* Methods of hoqri_run. HOOI (Alg. 1) replaces the single QR step of a mode
  * update by the K_n leading left singular vectors of Y_(n), computed by

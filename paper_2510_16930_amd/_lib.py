@@ -45,10 +45,12 @@ class RunOpts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("prec", ctypes.c_int),
                 ("check_every", ctypes.c_int32), ("orthonormalize_input", ctypes.c_int32),
                 ("keep_on_breakdown", ctypes.c_int32), ("d_grad_hist", ctypes.c_void_p),
-                ("grad_tol", ctypes.c_double), ("method", ctypes.c_int32), ("inner_iters", ctypes.c_int32)]
+                ("grad_tol", ctypes.c_double), ("method", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("stop_rule", ctypes.c_int32)]
 
 
 METHOD = {"hoqri": 0, "hooi": 1}
+STOP = {"rel_f": 0, "err": 1}
 
 
 class RunStats(ctypes.Structure):
@@ -292,9 +294,12 @@ class Stats:
 
 def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp32", check_every: int = 1,
               orthonormalize_input: bool = False, G=None, f_hist=None, stream=None, keep_on_breakdown: bool = False,
-              grad_hist=None, grad_tol: float = 0.0, method: str = "hoqri", inner_iters: int = 1):
+              grad_hist=None, grad_tol: float = 0.0, method: str = "hoqri", inner_iters: int = 1,
+              stop: str = "rel_f"):
     """Runs HOQRI (or HOOI with `inner_iters` orthogonal-iteration steps per mode
-    update) in place on Us. Returns (G, Stats)."""
+    update) in place on Us. `stop` picks the rule `tol` applies to: "rel_f"
+    (|f_t - f_{t-1}| <= tol f_t) or "err" (change of the relative approximation
+    error below tol). Returns (G, Stats)."""
     import torch
     L = load()
     for U in Us:
@@ -305,7 +310,7 @@ def hoqri_run(plan: Plan, Us, max_sweeps: int, tol: float = 0.0, prec: str = "fp
         _need_cuda(grad_hist, torch.float64, "grad_hist")
     opts = RunOpts(int(max_sweeps), float(tol), PREC[prec], int(check_every), int(bool(orthonormalize_input)),
                    int(bool(keep_on_breakdown)), ctypes.c_void_p(grad_hist.data_ptr()) if grad_hist is not None else None,
-                   float(grad_tol), METHOD[method], int(inner_iters))
+                   float(grad_tol), METHOD[method], int(inner_iters), STOP[stop])
     st = RunStats()
     _check(L.hoqri_run(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f_hist) if f_hist is not None else None,
                        ctypes.byref(opts), ctypes.byref(st), _stream(stream)), "hoqri_run")

@@ -59,7 +59,7 @@ struct Scratch {
   float* carry;        // ranges_max * 2 * 32 floats: partial rows of split slices
   int32_t* meta;       // ranges_max * 4 ints
   double* orth_ws;     // CholeskyQR2 workspace (Gram partials, factors)
-  int32_t* status;     // device status flags [4]
+  int32_t* status;     // device status flags [4]: breakdown, skipped updates, FP16 range, spare
   double* f_dev;       // scalars [64]
   double* fsweep;      // f after each sweep inside hoqri_run [kMaxSweeps + 1]
   double* gscr;        // gradient monitor: G_(n) G_(n)^T [32*32], block partials [4096], history
@@ -163,7 +163,8 @@ bool generic_supported(const hoqri_plan* p);
 // does not allow them; use another precision).
 bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale);
 // Rounds rows [0, rows) of a float32 factor (K columns) to the 16-bit copy.
-hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s);
+hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s,
+                           int32_t* range_flag = nullptr);
 
 // Factor rows between the caller's order and the plan's label order (run.hip).
 hoqri_status to_labels(hoqri_plan* p, const float* const* U, hipStream_t s);

@@ -1,19 +1,21 @@
 // QR step of HOQRI (Alg. 2): an orthonormal basis of A (I x K, K <= 32) by
-// Cholesky QR in float64, refined once (the second step of CholeskyQR2):
-//   W1 = A^T A, R1 = chol(W1), W2 = R1^-T W1 R1^-1, R2 = chol(W2),
+// CholeskyQR2 in float64:
+//   W1 = A^T A, R1 = chol(W1), Q1 = A R1^-1, W2 = Q1^T Q1, R2 = chol(W2),
 //   U = A (R2 R1)^-1 = A M with M = R1^-1 R2^-1.
 // W1 is formed from the float32 A with float64 products on the float64
-// matrix cores (v_mfma_f64_16x16x4_f64), so its error is ~1e-16 relative;
-// the second factorisation then removes the rounding of the first one, which
-// is what forming Q1 = A R1^-1 explicitly and taking its Gram would do, up
-// to float64 rounding (Q1 is never formed). Both Cholesky factors have a
+// matrix cores (v_mfma_f64_16x16x4_f64). Q1 is never stored: a second pass
+// over A forms each 16-row tile of A R1^-1 on the same matrix cores and adds
+// its Gram to W2 at once, so W2 is the Gram of the float64 Q1 itself and the
+// loss of orthonormality of U is that of CholeskyQR2 (about u64 times a
+// modest factor while kappa(A)^2 u64 < 1, then the float32 rounding of U),
+// not kappa(A)^2 times the rounding of W1. Both Cholesky factors have a
 // positive diagonal, so U is the thin QR factor with diag(R) > 0 (the basis
 // the paper leaves free, made unique).
-// A Cholesky pivot <= 1e-13 * trace(W) (or not finite) flags breakdown: A is
-// numerically rank deficient; U is then left untouched.
+// A Cholesky pivot <= 1e-13 * trace(W) (or not finite) in either step flags
+// breakdown: A is numerically rank deficient; U is then left untouched.
 //
-// Memory traffic: one read of A for the Gram and one read + one write for
-// the final product; the K x K work runs in a single workgroup.
+// Memory traffic: two reads of A for the Gram matrices and one read + one
+// write for the final product; the K x K work runs in single workgroups.
 #include "passes.h"
 
 #include <vector>
@@ -37,13 +39,38 @@ int gram_blocks(int64_t rows) {
   return (int)nb;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Adds the 4 waves' Gram tiles in wave order and stores the block's partial:
+// tile (pb, qb) holds entry (16 pb + 4 v + gg, 16 qb + q) in D[pb][qb][v]
+// (the float64 16x16 result layout); part[e * nb + blk] for entry e = p*K + q.
+__device__ inline void gram_store(const d4 (&D)[2][2], const GramArgs& g, const int blk) {
+  __shared__ double red[kT / 64][kMaxRank * kMaxRank];
+  const int K = g.K;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane & 15, gg = lane >> 4;
+#pragma unroll
+  for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pr = 16 * pb + 4 * v + gg, pc = 16 * qb + q;
+        if (pr < K && pc < K) red[wv][pr * K + pc] = D[pb][qb][v];
+      }
+  __syncthreads();
+  for (int e = threadIdx.x; e < K * K; e += kT) {
+    double t = red[0][e];
+    for (int w = 1; w < kT / 64; ++w) t += red[w][e];
+    g.part[(size_t)e * g.nb + blk] = t;
+  }
+}
+
 // Partial Gram of the rows [r0, r1) of block blk, on the float64 matrix cores:
 // each wave takes 4 rows at a time (lane group g: row 4s + g, lane q: columns
 // 16 pb + q), W tile (pb, qb) += A_rows^T A_rows; the 4 waves' tiles are added
 // in order. part[e * nb + blk] for entry e = p*K + q.
 __device__ inline void gram_body(const GramArgs& g, const int blk) {
-  typedef double d4 __attribute__((ext_vector_type(4)));
-  __shared__ double red[kT / 64][kMaxRank * kMaxRank];
   const float* A = g.A;
   const int64_t rows = g.rows;
   const int K = g.K;
@@ -88,30 +115,90 @@ __device__ inline void gram_body(const GramArgs& g, const int blk) {
       }
     }
   }
-  // float64 16x16 result layout: tile (pb, qb) holds entry (16 pb + 4 v + gg,
-  // 16 qb + q) in D[pb][qb][v]
+  gram_store(D, g, blk);
+}
+
+
+// Partial Gram of Q1 = A M (M = R1^-1, upper triangular) over the rows
+// [r0, r1) of block blk. Each wave takes 16-row tiles of A (staged in its
+// own LDS rows), forms the tile of Q1 on the float64 matrix cores (lane
+// (gg, q) supplies A(row q, 4s + gg) and M(4s + gg, 16 ct + q), and receives
+// Q1(4 r + gg, 16 ct + q) in D[ct][r]), and multiplies it into its Gram
+// tiles at once: that output layout is the operand layout of the Gram
+// product (step r: rows 4 r + gg of the tile, lane column q). Rows past r1
+// and columns past K are zero and add nothing.
+__device__ inline void gramq_body(const GramArgs& g, const int blk) {
+  __shared__ float tile[kT / 64][16][kMaxRank + 1];
+  const float* A = g.A;
+  const int64_t rows = g.rows;
+  const int K = g.K;
+  const int nb = g.nb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane & 15, gg = lane >> 4;
+  const int KT = (K + 15) >> 4;
+  const int64_t per = (rows + nb - 1) / nb;
+  const int64_t r0 = blk * per;
+  int64_t r1 = r0 + per;
+  if (r1 > rows) r1 = rows;
+  double mb[8][2];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int kk = 4 * s + gg, cc = 16 * ct + q;
+      mb[s][ct] = (kk < K && cc < K) ? g.M[kk * K + cc] : 0.0;
+    }
+  d4 W[2][2];
 #pragma unroll
   for (int pb = 0; pb < 2; ++pb)
 #pragma unroll
-    for (int qb = 0; qb < 2; ++qb)
+    for (int qb = 0; qb < 2; ++qb) W[pb][qb] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = r0 + 16 * wv; base < r1; base += 16 * (kT / 64)) {
+    const int nr = (int)((r1 - base) < 16 ? (r1 - base) : 16);
+    // the tile's nr * K floats are contiguous in A
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pr = 16 * pb + 4 * v + gg, pc = 16 * qb + q;
-        if (pr < K && pc < K) red[wv][pr * K + pc] = D[pb][qb][v];
+    for (int i = 0; i < 8; ++i) {
+      const int t = lane + 64 * i;
+      if (t < nr * K) tile[wv][t / K][t % K] = A[base * K + t];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    d4 D[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (s >= 4 * KT) break;
+      const int kk = 4 * s + gg;
+      const double av = (q < nr && kk < K) ? (double)tile[wv][q][kk] : 0.0;
+      D[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, mb[s][0], D[0], 0, 0, 0);
+      if (KT > 1) D[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, mb[s][1], D[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      W[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[0][r], D[0][r], W[0][0], 0, 0, 0);
+      if (KT > 1) {
+        W[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[0][r], D[1][r], W[0][1], 0, 0, 0);
+        W[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[1][r], D[0][r], W[1][0], 0, 0, 0);
+        W[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[1][r], D[1][r], W[1][1], 0, 0, 0);
       }
-  __syncthreads();
-  for (int e = threadIdx.x; e < K * K; e += kT) {
-    double t = red[0][e];
-    for (int w = 1; w < kT / 64; ++w) t += red[w][e];
-    g.part[(size_t)e * nb + blk] = t;
+    }
+    // the next tile overwrites this wave's LDS rows after every lane read them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  gram_store(W, g, blk);
 }
 
-__global__ __launch_bounds__(kT) void k_gram(GramArgs g) { gram_body(g, blockIdx.x); }
+__global__ __launch_bounds__(kT) void k_gram(GramArgs g) {
+  if (g.M) gramq_body(g, blockIdx.x);
+  else gram_body(g, blockIdx.x);
+}
 
 __global__ __launch_bounds__(kT) void k_gram_b(const GramArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
-  gram_body(d[r], blockIdx.x - first[r]);
+  if (d[r].M) gramq_body(d[r], blockIdx.x - first[r]);
+  else gram_body(d[r], blockIdx.x - first[r]);
 }
 
 // W[e] = sum over blocks of part[e * nb + b], fixed tree order.
@@ -172,75 +259,61 @@ __device__ inline void chol_inv(double (*L)[kMaxRank + 1], double (*Ri)[kMaxRank
   __syncthreads();
 }
 
-// W1 -> R1 = chol(W1), W2 = R1^-T W1 R1^-1, R2 = chol(W2); Mout = R1^-1 R2^-1,
-// Rout = R2 R1 (optional). On breakdown either *skipped += 1 (when a counter
-// is given: the factor is left as it was) or *status = HOQRI_ERR_BREAKDOWN;
-// without breakdown *status = 0 unless `sticky` (then an earlier breakdown
-// recorded in *status is kept). *flag = breakdown (read by the apply kernel).
+// The two Cholesky steps, each in one workgroup.
+// Stage 1 (c.M1 == null): R1 = chol(W1); Mout = R1^-1, Rout = R1;
+//   *flag = breakdown.
+// Stage 2: R2 = chol(W2) with W2 the Gram of Q1 = A R1^-1; Mout = M1 R2^-1
+//   (= R1^-1 R2^-1), Rout = R2 R1 (optional). Breakdown in either stage:
+//   *skipped += 1 when a counter is given (the factor is left as it was), else
+//   *status = HOQRI_ERR_BREAKDOWN; without breakdown *status = 0 unless
+//   `sticky` (then an earlier breakdown recorded in *status is kept).
+//   *flag = breakdown (read by the apply kernel).
 __device__ inline void chol_body(const CholArgs& c) {
   __shared__ double L[kMaxRank][kMaxRank + 1];
   __shared__ double Ri[kMaxRank][kMaxRank + 1];
-  __shared__ double W[kMaxRank][kMaxRank + 1];
-  __shared__ double T[kMaxRank][kMaxRank + 1];
+  __shared__ double M1[kMaxRank][kMaxRank + 1];
   __shared__ double R1[kMaxRank][kMaxRank + 1];
   __shared__ double tr;
   __shared__ int bad;
   const int K = c.K;
   const int t = threadIdx.x;
   const int sh = rank_shift(K);
+  const bool second = c.M1 != nullptr;
   for (int e = t; e < (K << sh); e += kT) {
     const int i = e >> sh, j = e & ((1 << sh) - 1);
     if (i < K && j < K) {
-      const double w = c.W[i * K + j];
-      L[i][j] = w;
-      W[i][j] = w;
+      L[i][j] = c.W[i * K + j];
+      if (second) {
+        M1[i][j] = c.M1[i * K + j];
+        R1[i][j] = c.R1[i * K + j];
+      }
     }
   }
   if (t == 0) {
     double s = 0.0;
     for (int k = 0; k < K; ++k) s += c.W[k * K + k];
     tr = s;
-    bad = 0;
+    bad = second ? *c.flag : 0;
   }
   __syncthreads();
-  chol_inv(L, Ri, K, tr, &bad);  // L: R1, Ri: R1^-1
-  // T = W1 R1^-1, then W2 = R1^-T T (kept in L after saving R1)
-  for (int e = t; e < (K << sh); e += kT) {
-    const int i = e >> sh, j = e & ((1 << sh) - 1);
-    if (j >= K) continue;
-    double s = 0.0;
-    for (int k = 0; k <= j; ++k) s += W[i][k] * Ri[k][j];
-    T[i][j] = s;
-    R1[i][j] = (j >= i) ? L[i][j] : 0.0;
+  chol_inv(L, Ri, K, tr, &bad);  // L: the factor (upper), Ri: its inverse
+  if (!second) {
+    for (int e = t; e < (K << sh); e += kT) {
+      const int i = e >> sh, j = e & ((1 << sh) - 1);
+      if (j >= K) continue;
+      c.Mout[i * K + j] = Ri[i][j];
+      c.Rout[i * K + j] = (j >= i) ? L[i][j] : 0.0;
+    }
+    if (t == 0) *c.flag = bad;
+    return;
   }
-  __syncthreads();
-  for (int e = t; e < (K << sh); e += kT) {
-    const int i = e >> sh, j = e & ((1 << sh) - 1);
-    if (j >= K) continue;
-    double s = 0.0;
-    for (int k = 0; k <= i; ++k) s += Ri[k][i] * T[k][j];
-    W[i][j] = s;  // W2
-  }
-  __syncthreads();
-  for (int e = t; e < (K << sh); e += kT) {
-    const int i = e >> sh, j = e & ((1 << sh) - 1);
-    L[i][j] = W[i][j];
-    T[i][j] = Ri[i][j];  // keep R1^-1
-  }
-  if (t == 0) {
-    double s = 0.0;
-    for (int k = 0; k < K; ++k) s += W[k][k];
-    tr = s;
-  }
-  __syncthreads();
-  chol_inv(L, Ri, K, tr, &bad);  // L: R2, Ri: R2^-1
   for (int e = t; e < (K << sh); e += kT) {
     const int i = e >> sh, j = e & ((1 << sh) - 1);
     if (j >= K) continue;
     double m = 0.0, r = 0.0;
     if (j >= i) {
-      for (int k = i; k <= j; ++k) m += T[i][k] * Ri[k][j];  // R1^-1 R2^-1
-      for (int k = i; k <= j; ++k) r += L[i][k] * R1[k][j];  // R2 R1
+      for (int k = i; k <= j; ++k) m += M1[i][k] * Ri[k][j];  // R1^-1 R2^-1
+      for (int k = i; k <= j; ++k) r += L[i][k] * R1[k][j];   // R2 R1
     }
     c.Mout[i * K + j] = m;
     if (c.Rout) c.Rout[i * K + j] = r;
@@ -414,7 +487,10 @@ hoqri_status prepare_orth(int64_t rows, int32_t K, const float* A, float* U, dou
   *job = OrthJob{};
   job->g1 = GramArgs{A, rows, K, nullptr, o.part, nb};
   job->r1 = GRedArgs{o.part, nb, o.W};
-  job->c = CholArgs{o.W, K, nullptr, nullptr, o.M, R ? R : o.R, o.flag, status, (int32_t)sticky, skipped};
+  job->c1 = CholArgs{o.W, K, nullptr, nullptr, o.M1, o.R1, o.flag, status, (int32_t)sticky, skipped};
+  job->g2 = GramArgs{A, rows, K, o.M1, o.part, nb};
+  job->r2 = GRedArgs{o.part, nb, o.W};
+  job->c = CholArgs{o.W, K, o.M1, o.R1, o.M, R ? R : o.R, o.flag, status, (int32_t)sticky, skipped};
   int64_t ab = (rows + 63) / 64;
   if (ab > 4096) ab = 4096;
   job->ap = ApplyArgs{A, rows, K, o.M, U, o.flag, (int32_t)ab, zero_to > rows ? zero_to : rows};
@@ -430,6 +506,9 @@ hoqri_status launch_orth(int64_t rows, int32_t K, const float* A, float* U, doub
   HOQRI_TRY(prepare_orth(rows, K, A, U, R, status, ws, ws_bytes, sticky, &j, skipped, zero_to));
   hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g1);
   hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r1);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c1);
+  hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g2);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r2);
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c);
   hipLaunchKernelGGL(k_apply, dim3(j.apply_blocks), dim3(kT), 0, s, j.ap);
   HOQRI_HIP_TRY(hipGetLastError());
@@ -438,14 +517,17 @@ hoqri_status launch_orth(int64_t rows, int32_t K, const float* A, float* U, doub
 
 bool stage_orth_group(const OrthJob* const* jobs, int n, Staging& st, OrthGroup* g) {
   if (n < 1 || n > 1024) return false;
-  std::vector<GramArgs> g1(n);
-  std::vector<GRedArgs> r1(n);
-  std::vector<CholArgs> c(n);
+  std::vector<GramArgs> g1(n), g2(n);
+  std::vector<GRedArgs> r1(n), r2(n);
+  std::vector<CholArgs> c1(n), c(n);
   std::vector<ApplyArgs> ap(n);
   std::vector<int32_t> nb_g(n), nb_r(n), ones(n), nb_a(n);
   for (int i = 0; i < n; ++i) {
     g1[i] = jobs[i]->g1;
     r1[i] = jobs[i]->r1;
+    c1[i] = jobs[i]->c1;
+    g2[i] = jobs[i]->g2;
+    r2[i] = jobs[i]->r2;
     c[i] = jobs[i]->c;
     ap[i] = jobs[i]->ap;
     nb_g[i] = jobs[i]->gram_blocks;
@@ -454,13 +536,20 @@ bool stage_orth_group(const OrthJob* const* jobs, int n, Staging& st, OrthGroup*
     nb_a[i] = jobs[i]->apply_blocks;
   }
   return stage_table(st, g1.data(), nb_g.data(), n, &g->g1) && stage_table(st, r1.data(), nb_r.data(), n, &g->r1) &&
-         stage_table(st, c.data(), ones.data(), n, &g->c) && stage_table(st, ap.data(), nb_a.data(), n, &g->ap);
+         stage_table(st, c1.data(), ones.data(), n, &g->c1) && stage_table(st, g2.data(), nb_g.data(), n, &g->g2) &&
+         stage_table(st, r2.data(), nb_r.data(), n, &g->r2) && stage_table(st, c.data(), ones.data(), n, &g->c) &&
+         stage_table(st, ap.data(), nb_a.data(), n, &g->ap);
 }
 
 hoqri_status launch_orth_group(const OrthGroup& g, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_b, dim3(g.g1.blocks), dim3(kT), 0, s, (const GramArgs*)g.g1.descs, g.g1.first, g.g1.count);
   hipLaunchKernelGGL(k_gram_reduce_b, dim3(g.r1.blocks), dim3(kT), 0, s, (const GRedArgs*)g.r1.descs, g.r1.first,
                      g.r1.count);
+  hipLaunchKernelGGL(k_chol_b, dim3(g.c1.blocks), dim3(kT), 0, s, (const CholArgs*)g.c1.descs, g.c1.first,
+                     g.c1.count);
+  hipLaunchKernelGGL(k_gram_b, dim3(g.g2.blocks), dim3(kT), 0, s, (const GramArgs*)g.g2.descs, g.g2.first, g.g2.count);
+  hipLaunchKernelGGL(k_gram_reduce_b, dim3(g.r2.blocks), dim3(kT), 0, s, (const GRedArgs*)g.r2.descs, g.r2.first,
+                     g.r2.count);
   hipLaunchKernelGGL(k_chol_b, dim3(g.c.blocks), dim3(kT), 0, s, (const CholArgs*)g.c.descs, g.c.first, g.c.count);
   hipLaunchKernelGGL(k_apply_b, dim3(g.ap.blocks), dim3(kT), 0, s, (const ApplyArgs*)g.ap.descs, g.ap.first,
                      g.ap.count);
@@ -490,3 +579,4 @@ extern "C" hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A,
                                    int32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream) {
   return launch_orth(rows, cols, d_A, d_U, d_R, d_status, d_ws, ws_bytes, stream, false);
 }
+

@@ -174,7 +174,7 @@ struct GramArgs {
   const float* A;
   int64_t rows;
   int32_t K;
-  const double* M;  // null: Gram of A; else Gram of A M (M upper triangular)
+  const double* M;  // null: Gram of A; else Gram of A M (M = R1^-1, upper triangular)
   double* part;     // [K*K][nb]
   int32_t nb;
 };
@@ -186,8 +186,8 @@ struct GRedArgs {
 struct CholArgs {
   const double* W;
   int32_t K;
-  const double* unused0;
-  const double* unused1;
+  const double* M1;  // second step: R1^-1 of the first (null: this is the first step)
+  const double* R1;  // second step: R1
   double* Mout;
   double* Rout;
   int32_t* flag;
@@ -206,9 +206,9 @@ struct ApplyArgs {
   int64_t zero_to;  // rows [rows, zero_to) of U are zeroed with the update
 };
 struct OrthJob {
-  GramArgs g1;
-  GRedArgs r1;
-  CholArgs c;
+  GramArgs g1, g2;  // Gram of A; Gram of Q1 = A R1^-1
+  GRedArgs r1, r2;
+  CholArgs c1, c;   // R1 = chol(W1); R2 = chol(W2) and the combined factors
   ApplyArgs ap;
   int gram_blocks, red_blocks, apply_blocks;
 };
@@ -283,7 +283,7 @@ struct CoreGroup {
   BatchTable seg, gemm, red, sum;
 };
 struct OrthGroup {
-  BatchTable g1, r1, c, ap;
+  BatchTable g1, r1, c1, g2, r2, c, ap;
 };
 struct YCoreGroup {
   BatchTable gemm, red, sum;

@@ -153,9 +153,29 @@ Operands plan_operands(hoqri_plan* p, int op) {
   return o;
 }
 
+// status[2]: an FP16 factor copy met an entry of magnitude >= 1.5 (see k_cast16)
 hoqri_status refresh16(hoqri_plan* p, int op, int mode, hipStream_t s) {
   if (op == OP_FP32) return HOQRI_OK;
-  return launch_cast16(p->sc.Up[mode], p->md[mode].R, p->K[mode], p->sc.Uh[mode], op, s);
+  return launch_cast16(p->sc.Up[mode], p->md[mode].R, p->K[mode], p->sc.Uh[mode], op, s, p->sc.status + 2);
+}
+
+// FP16 form: the caller's factors must have entries of magnitude below 1.5
+// (orthonormal columns give at most 1) so their scaled float16 copies stay in
+// range. Clears the flag, casts, and reads it back (one synchronisation) before
+// any pass runs; HOQRI_ERR_ARG otherwise.
+hoqri_status refresh16_checked(hoqri_plan* p, int op, int skip_mode, hipStream_t s) {
+  if (op != OP_FP16) {
+    for (int n = 0; n < p->N; ++n)
+      if (n != skip_mode) HOQRI_TRY(refresh16(p, op, n, s));
+    return HOQRI_OK;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p->sc.status + 2, 1, 0);
+  for (int n = 0; n < p->N; ++n)
+    if (n != skip_mode) HOQRI_TRY(refresh16(p, op, n, s));
+  int32_t flag = 0;
+  HOQRI_HIP_TRY(hipMemcpyAsync(&flag, p->sc.status + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HOQRI_HIP_TRY(hipStreamSynchronize(s));
+  return flag ? HOQRI_ERR_ARG : HOQRI_OK;
 }
 
 }  // namespace
@@ -224,7 +244,7 @@ extern "C" hoqri_status hoqri_core(hoqri_plan* p, const float* const* d_U, float
   int op = 0;
   HOQRI_TRY(check_prec(prec, &op));
   HOQRI_TRY(to_labels(p, d_U, stream));
-  for (int n = 0; n < p->N; ++n) HOQRI_TRY(refresh16(p, op, n, stream));
+  HOQRI_TRY(refresh16_checked(p, op, -1, stream));
   return launch_core(p, plan_operands(p, op), d_G, d_f, stream);
 }
 
@@ -237,8 +257,7 @@ extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* c
   int op = 0;
   HOQRI_TRY(check_prec(prec, &op));
   HOQRI_TRY(to_labels(p, d_U, stream));
-  for (int n = 0; n < p->N; ++n)
-    if (n != mode) HOQRI_TRY(refresh16(p, op, n, stream));
+  HOQRI_TRY(refresh16_checked(p, op, mode, stream));
   return launch_ttmctc(p, mode, plan_operands(p, op), d_G, d_A, p->md[mode].inv, stream);
 }
 
@@ -286,6 +305,7 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     if (!segpass_supported(p, n) && (op != OP_FP32 || !generic_supported(p))) return HOQRI_ERR_UNSUPPORTED;
   if (opts->method != HOQRI_METHOD_HOQRI && opts->method != HOQRI_METHOD_HOOI) return HOQRI_ERR_ARG;
   if (opts->inner_iters < 0 || opts->inner_iters > 1000) return HOQRI_ERR_ARG;
+  if (opts->stop_rule != HOQRI_STOP_REL_F && opts->stop_rule != HOQRI_STOP_ERR_CHANGE) return HOQRI_ERR_ARG;
   const bool hooi = opts->method == HOQRI_METHOD_HOOI;
   const int inner = hooi && opts->inner_iters > 1 ? opts->inner_iters : 1;
   if (hooi && !p->yfuse) return HOQRI_ERR_UNSUPPORTED;
@@ -311,13 +331,17 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
   HOQRI_TRY(to_labels(p, d_U_inout, stream));
   float* const* Up = p->sc.Up;
   const Operands ops = plan_operands(p, op);
-  for (int n = 0; n < N; ++n) HOQRI_TRY(refresh16(p, op, n, stream));
+  HOQRI_TRY(refresh16_checked(p, op, -1, stream));
   // core of the starting factors
   HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + 0, stream));
 
   int T = 0;
   double f_last = 0.0, f_prev = 0.0, rel = 0.0;
   bool have_prev = false;
+  // relative approximation error sqrt(max(||X||^2 - f, 0) / ||X||^2) (§2.2: for
+  // orthonormal factors and the optimal core the squared error is ||X||^2 - f)
+  const auto rel_err = [&](double f) { return std::sqrt(std::fmax(p->normx2 - f, 0.0) / p->normx2); };
+
   if (!(opts->grad_tol >= 0.0)) return HOQRI_ERR_ARG;
   const bool grad_on = opts->d_grad_hist != nullptr || opts->grad_tol > 0.0;
   double* ghist = p->sc.gscr + kMaxRank * kMaxRank + kGradParts;  // [kMaxSweeps][N]
@@ -372,7 +396,13 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       f_last = fv[1];
       have_prev = true;
       rel = f_last > 0 ? std::fabs(f_last - f_prev) / f_last : 0.0;
-      if (opts->tol > 0.0 && std::fabs(f_last - f_prev) <= opts->tol * f_last) break;
+      // both rules compare the last two sweeps (f_prev: the sweep before, or the
+      // starting factors' f after the first sweep)
+      if (opts->tol > 0.0) {
+        if (opts->stop_rule == HOQRI_STOP_REL_F && std::fabs(f_last - f_prev) <= opts->tol * f_last) break;
+        if (opts->stop_rule == HOQRI_STOP_ERR_CHANGE && std::fabs(rel_err(f_last) - rel_err(f_prev)) < opts->tol)
+          break;
+      }
       if (opts->grad_tol > 0.0 && std::sqrt(std::fmax(gsum, 0.0)) <= opts->grad_tol * f_last) break;
     }
   }

@@ -2107,15 +2107,25 @@ hipError_t set_shmem(const void* k, size_t shmem) {
 
 // Rounds to the 16-bit copy: bfloat16 (nearest even), or float16 of u * 2^15
 // (nearest even). |u| <= 1 for a factor with orthonormal columns, so the
-// float16 copy stays below 2^15 < 65504.
-__global__ void k_cast16(const float* __restrict__ U, int64_t n, uint16_t* __restrict__ Uh, int prec) {
+// float16 copy stays below 2^15 < 65504; an entry of magnitude 1.5 or more
+// (or not finite) would leave that range or come from factors that are not
+// orthonormal: it sets *range_flag (when given), which the callers read
+// before any pass uses the copy.
+__global__ void k_cast16(const float* __restrict__ U, int64_t n, uint16_t* __restrict__ Uh, int prec,
+                         int32_t* range_flag) {
+  bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float u = U[i];
     uint16_t b;
-    if (prec == OP_BF16) b = __builtin_bit_cast(uint16_t, (__bf16)u);
-    else b = __builtin_bit_cast(uint16_t, (_Float16)(u * 32768.f));
+    if (prec == OP_BF16) {
+      b = __builtin_bit_cast(uint16_t, (__bf16)u);
+    } else {
+      bad |= !(__builtin_fabsf(u) < 1.5f);
+      b = __builtin_bit_cast(uint16_t, (_Float16)(u * 32768.f));
+    }
     Uh[i] = b;
   }
+  if (bad && range_flag) *range_flag = 1;
 }
 
 void g_strides(const hoqri_plan* p, int64_t* st) {
@@ -2147,12 +2157,13 @@ bool fp16_scales(const hoqri_plan* p, int nm1, float* ascale, float* yscale) {
   return true;
 }
 
-hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s) {
+hoqri_status launch_cast16(const float* U, int64_t rows, int32_t K, uint16_t* Uh, int prec, hipStream_t s,
+                           int32_t* range_flag) {
   const int64_t n = rows * K;
   if (n <= 0) return HOQRI_OK;
   int64_t grid = (n + 255) / 256;
   if (grid > 8192) grid = 8192;
-  hipLaunchKernelGGL(k_cast16, dim3((unsigned)grid), dim3(256), 0, s, U, n, Uh, prec);
+  hipLaunchKernelGGL(k_cast16, dim3((unsigned)grid), dim3(256), 0, s, U, n, Uh, prec, range_flag);
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
 }

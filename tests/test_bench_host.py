@@ -16,7 +16,8 @@ import bench  # noqa: E402
 
 def test_pass_work_counts_by_hand():
     # 3-way, ranks (2, 3, 4), 10 nonzeros, nonempty slices R = (5, 6, 7); a
-    # record is N dwords per nonzero (N - 1 row offsets and the value)
+    # record is N dwords per nonzero (N - 1 row offsets and the value); the
+    # stored slice rows are design bytes, not algorithmic ones
     dims, ranks, nnz, R = (8, 9, 10), (2, 3, 4), 10, (5, 6, 7)
     w = bench.pass_work(dims, ranks, nnz, R, su=4)
     PK = 24
@@ -24,13 +25,20 @@ def test_pass_work_counts_by_hand():
         P = PK // ranks[n]
         flops = 2 * nnz * P + 2 * R[n] * PK
         others = [m for m in range(3) if m != n]
-        byts = nnz * 12 + 8 * R[n] + sum(R[m] * ranks[m] * 4 for m in others) + 4 * dims[n] * ranks[n] + 4 * R[n] * P
-        assert w[n] == (flops, byts)
+        byts = nnz * 12 + 8 * R[n] + sum(R[m] * ranks[m] * 4 for m in others) + 4 * dims[n] * ranks[n]
+        assert w[n] == (flops, byts, 4 * R[n] * P)
     # 16-bit factor copies halve only the factor-row term
     w2 = bench.pass_work(dims, ranks, nnz, R, su=2)
     for n in range(3):
         others = [m for m in range(3) if m != n]
         assert w[n][1] - w2[n][1] == sum(R[m] * ranks[m] * 2 for m in others)
+
+
+def test_default_workload_is_the_bf16_comparison():
+    cfg = bench.CONFIGS["c3"]
+    assert cfg["prec"] == "bf16" and cfg["compare"] == "fp32" and cfg["ranks"] == (32, 32, 32)
+    assert cfg["nnz"] == 50_000_000 and cfg["dims"] == (1_000_000, 500_000, 20_000)
+    assert bench.CONFIGS["c4"]["compare"] == "fp32"
 
 
 def test_kernel_names_follow_the_library_choice():

@@ -125,3 +125,65 @@ def test_fullsize_identities_and_run(tensor):
         got.append(Gh[ks])
     assert rel(got, ref) < 1e-5
     plan.destroy()
+
+
+# The 4-way workload at full size: 2e5 x 2e5 x 5e3 x 1e3, 100M Zipf(1.1)
+# nonzeros with uniform(0,1) values, ranks 10^4, in the FP16 form bench.py
+# times and in the FP32 form (both through the c-tile pass).
+DIMS4 = (200_000, 200_000, 5_000, 1_000)
+NNZ4 = 100_000_000
+K4 = (10, 10, 10, 10)
+
+
+def test_fullsize_4way_core_entries_and_slice_rows():
+    print("[fullsize4] generating the 100M-nonzero 4-way tensor", flush=True)
+    idx, vals = synth.coo_zipf_torch(DIMS4, NNZ4, 1.1, 14, "uniform", device=DEV)
+    torch.cuda.synchronize()
+    ih = idx.cpu().numpy().astype(np.int64)
+    vh = vals.cpu().numpy().astype(np.float64)
+    plan = H.hoqri_plan_create(idx, vals, DIMS4, K4)
+    del idx, vals
+    Ud = [H.hoqri_orth(r)[0] for r in synth.gaussian_start_torch(DIMS4, K4, 114, device=DEV)]
+    torch.cuda.synchronize()
+    Uh = [u.cpu().numpy().astype(np.float64) for u in Ud]
+    Uabs = [np.abs(u) for u in Uh]
+    vabs = np.abs(vh)
+    rng = np.random.default_rng(4)
+    picks = [tuple(int(rng.integers(k)) for k in K4) for _ in range(4)]
+    ref = np.array([O.core_entry(ih, vh, Uh, ks) for ks in picks])
+    absref = np.array([O.core_entry(ih, vabs, Uabs, ks) for ks in picks])
+    slices = [sample_slices_dims(ih, n, DIMS4, rng, k=3) for n in range(4)]
+    for prec in ("fp16", "fp32"):
+        print(f"[fullsize4] prec={prec} core", flush=True)
+        G = H.hoqri_core(plan, Ud, prec=prec)
+        torch.cuda.synchronize()
+        Gh = G.cpu().numpy().astype(np.float64)
+        got = np.array([Gh[ks] for ks in picks])
+        if prec == "fp32":
+            assert rel(got, ref) < 1e-5
+        else:
+            # core pass of the FP16 form (the c-tile walk rounds its A operand in two
+            # steps): (N + 1) u16 of the |.|-instance, float32 accumulation
+            assert np.all(np.abs(got - ref) <= (5 * 2.0 ** -11 + 2e-5) * absref)
+        for n in range(4):
+            A = H.hoqri_ttmctc(plan, n, Ud, G, prec=prec)
+            torch.cuda.synchronize()
+            for i in slices[n]:
+                print(f"[fullsize4] prec={prec} mode {n} slice {i}", flush=True)
+                row = A[i].cpu().numpy().astype(np.float64)
+                want = O.ttmctc_slice_row(ih, vh, Uh, n, i, Gh)
+                if prec == "fp32":
+                    assert rel(row, want) < 1e-5, (n, i)
+                else:
+                    wabs = O.ttmctc_slice_row(ih, vabs, Uabs, n, i, np.abs(Gh))
+                    # the FP16 c-tile pass: (N + 1) u16 for the factor copies and the
+                    # two-step A operand, plus 2 bfloat16 roundings of y_i and the core
+                    lim = (5 * 2.0 ** -11 + 2 * 2.0 ** -8 + 2e-5) * wabs + 1e-9 * wabs.max()
+                    assert np.all(np.abs(row - want) <= lim), (n, i)
+    plan.destroy()
+
+
+def sample_slices_dims(ih, n, dims, rng, k=3):
+    counts = np.bincount(ih[n], minlength=dims[n])
+    nonempty = np.flatnonzero(counts)
+    return [int(np.argmax(counts))] + [int(x) for x in rng.choice(nonempty, size=k - 1, replace=False)]

@@ -26,6 +26,16 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def fp32_bound_check(got, ref, absref, terms, what):
+    """Elementwise float32 bound gamma_T |.|-instance (T roundings along one
+    term's path, u32 = 2^-24), valid for any summation order."""
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    t = np.asarray(terms, np.float64) * 2.0 ** -24
+    lim = t / (1.0 - t) * absref
+    bad = err > lim
+    assert not bad.any(), f"{what}: {bad.sum()} entries over the float32 bound"
+
+
 @pytest.mark.parametrize("dims,K,nnz", [((30, 25, 20, 15, 12), (3, 4, 2, 5, 3), 3000),
                                         ((60, 50, 40, 30), (12, 12, 4, 4), 6000),
                                         ((40, 30, 20, 10), (20, 20, 12, 8), 4000)])
@@ -41,13 +51,22 @@ def test_single_calls_match_oracle(dims, K, nnz):
     G = H.hoqri_core(plan, Ud)
     Gref = O.core_segment(ci, cv, U64)
     torch.cuda.synchronize()
-    assert rel(G.cpu().numpy(), Gref) < 1e-5
+    Gh = G.cpu().numpy()
+    assert rel(Gh, Gref) < 1e-5
+    N = len(dims)
+    Uabs = [np.abs(u) for u in U64]
+    fp32_bound_check(Gh, Gref, O.core_segment(ci, np.abs(cv), Uabs), cv.size + N + 1, "core")
     G32 = Gref.astype(np.float32)
-    for n in range(len(dims)):
+    for n in range(N):
         A = H.hoqri_ttmctc(plan, n, Ud, dev(G32))
         Aref = O.ttmctc_segment(ci, cv, U64, n, G32.astype(np.float64))
         torch.cuda.synchronize()
-        assert rel(A.cpu().numpy(), Aref) < 1e-5, n
+        Ah = A.cpu().numpy()
+        assert rel(Ah, Aref) < 1e-5, n
+        Aabs = O.ttmctc_segment(ci, np.abs(cv), Uabs, n, np.abs(G32.astype(np.float64)))
+        L = np.bincount(ci[n], minlength=dims[n]).astype(np.float64)
+        P = int(np.prod(K)) // K[n]
+        fp32_bound_check(Ah, Aref, Aabs, (L + P + N + 1)[:, None], f"ttmctc mode {n}")
 
 
 @pytest.mark.parametrize("nnz", [800, 8000])

@@ -26,6 +26,22 @@ def rel_fro(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
+U32 = 2.0 ** -24
+
+
+def fp32_bound_check(got, ref, absref, terms, what):
+    """Elementwise float32 bound: a float32 evaluation of a sum of products, in
+    any order, with every product and partial sum rounded to nearest, is within
+    gamma_T = T u32 / (1 - T u32) (T roundings along one term's path, u32 =
+    2^-24) times the same computation on absolute values; `terms` is T per
+    output entry (broadcast against the outputs)."""
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    t = np.asarray(terms, np.float64) * U32
+    lim = t / (1.0 - t) * absref
+    bad = err > lim
+    assert not bad.any(), f"{what}: {bad.sum()} entries over the float32 bound, worst ratio {np.max(err / np.maximum(lim, 1e-300)):.3g}"
+
+
 def make_case(name):
     if name == "c1":
         dims, K = (200, 200, 200), (5, 5, 5)
@@ -88,8 +104,14 @@ def test_core_and_ttmctc_match_oracle(name):
     G = H.hoqri_core(plan, Ud, f=f)
     Gref = O.core_segment(ci, cv, U64)
     torch.cuda.synchronize()
-    assert rel_fro(G.cpu().numpy(), Gref) < TOL
+    Gh = G.cpu().numpy()
+    assert rel_fro(Gh, Gref) < TOL
     assert f.item() == pytest.approx(float(np.sum(Gref ** 2)), rel=2 * TOL)
+    # elementwise: every core entry is a sum over all nonzeros of N-factor products
+    N = len(dims)
+    U64abs = [np.abs(u) for u in U64]
+    Gabs = O.core_segment(ci, np.abs(cv), U64abs)
+    fp32_bound_check(Gh, Gref, Gabs, cv.size + N + 1, "core")
     # TTMcTC with the same core on both sides (the float32 core)
     G32 = Gref.astype(np.float32)
     Gd = torch.from_numpy(G32).to(DEV)
@@ -99,6 +121,12 @@ def test_core_and_ttmctc_match_oracle(name):
         torch.cuda.synchronize()
         Ah = A.cpu().numpy()
         assert rel_fro(Ah, Aref) < TOL, f"mode {n}"
+        # elementwise: row i sums L_i nonzeros' Kronecker rows (N roundings per
+        # term) and then P = prod_{m != n} K_m products with the core
+        Aabs = O.ttmctc_segment(ci, np.abs(cv), U64abs, n, np.abs(G32.astype(np.float64)))
+        L = np.bincount(ci[n], minlength=dims[n]).astype(np.float64)
+        P = math.prod(K) // K[n]
+        fp32_bound_check(Ah, Aref, Aabs, (L + P + N + 1)[:, None], f"ttmctc mode {n}")
         empty = np.setdiff1d(np.arange(dims[n]), idx[n])
         assert np.all(Ah[empty] == 0.0)
 
@@ -165,6 +193,31 @@ def test_orth_matches_householder(rows, cols, cond):
     # the positive-diagonal QR factor is unique: compare elementwise (scaled by conditioning)
     assert np.abs(Uh - Qref).max() < 1e-6 * cond + 1e-6
     assert rel_fro(Rd.cpu().numpy(), Rref) < 1e-6
+
+
+@pytest.mark.parametrize("rows,cols,cond", [(1_000_000, 32, 1e3), (1_000_000, 32, 1e5), (200_000, 16, 3e5)])
+def test_orth_ill_conditioned_tall(rows, cols, cond):
+    # CholeskyQR2 with the second Gram taken from Q1 = A R1^-1 itself: orthonormality
+    # at the float32 rounding of U while kappa(A)^2 u64 < 1 (here up to 1e-5), and the
+    # positive-diagonal factor equal to Householder's up to that rounding plus the
+    # forward error kappa u64. Forming the second Gram from the first (R1^-T W1 R1^-1)
+    # loses kappa^2 u64 of orthonormality: 1e-6 at kappa 1e5, 1e-5 at 3e5.
+    print(f"[orth] rows={rows} cols={cols} cond={cond:g}", flush=True)
+    rng = np.random.default_rng(int(cond) + cols)
+    Q0, _ = np.linalg.qr(rng.standard_normal((rows, cols)))
+    V0, _ = np.linalg.qr(rng.standard_normal((cols, cols)))
+    s = np.geomspace(1.0, 1.0 / cond, cols)
+    A = ((Q0 * s) @ V0.T * 3.0).astype(np.float32)
+    Qref, Rref = O.qr_positive(A.astype(np.float64))
+    Ad = torch.from_numpy(A).to(DEV)
+    Rd = torch.zeros((cols, cols), dtype=torch.float64, device=DEV)
+    Ud, st = H.hoqri_orth(Ad, R=Rd)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    Uh = Ud.cpu().numpy().astype(np.float64)
+    assert np.abs(Uh.T @ Uh - np.eye(cols)).max() < 5e-7
+    assert np.abs(Uh - Qref).max() < 2e-7 + 1e-13 * cond
+    assert rel_fro(Rd.cpu().numpy(), Rref) < 1e-8
 
 
 def test_orth_in_place_and_breakdown():

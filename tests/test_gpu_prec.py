@@ -21,15 +21,18 @@ definition). Float16 gradual underflow adds an absolute error far below
 1e-9 max|A| for these shapes (the operand is scaled so its largest
 possible magnitude is below 60000).
 
-Whole runs: the 16-bit forms must reach the FP64 oracle's fit within 1e-4
-relative after the same number of sweeps, with orthonormal factors (the
-orthonormalisation is float64 in every form). The 16-bit roundings move the
-trajectory, not the fixed points: on a uniformly random tensor (fit ~0.002,
-an almost flat objective) the BF16 fit after 10 sweeps of the 200^3 case
-differs by 1.6e-4 relative and by 2.3e-5 after 30 (FP16: 1.0e-4 after 10),
-so that case is compared after 30 sweeps in both forms; Zipf-structured
-tensors stay within 6e-5 from the start.
+Whole runs, at each workload's own sweep count from the same start: a 16-bit
+form qualifies when its fit is within 1e-4 relative of the FP64 oracle's. On
+the Zipf-structured tensors with the benchmark workloads' shapes every form
+qualifies (gaps of 1e-6 to 6e-5). On uniformly random tensors the objective is
+almost flat (fit ~0.002) and the 16-bit roundings move the trajectory: the
+bfloat16 form of the 200^3 parity workload misses 1e-4 after its 10 sweeps
+(1.6e-4), as both 16-bit forms do on the uniform rank-32 tensor; such a form is
+recorded as not qualifying together with its time to fit (the sweeps and
+milliseconds it needs to reach (1 - 1e-4) times the oracle's fit).
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -170,20 +173,88 @@ def run_fit(name, prec, sweeps):
     G, st = H.hoqri_run(plan, Us, max_sweeps=sweeps, prec=prec)
     torch.cuda.synchronize()
     Uo, Go, h = O.hoqri(idx, vals32.astype(np.float64), dims, K, [u.astype(np.float64) for u in U0], sweeps=sweeps)
-    return dims, K, idx, vals32, [u.cpu().numpy().astype(np.float64) for u in Us], G.cpu().numpy(), st, Uo, h
+    return dims, K, idx, vals32, [u.cpu().numpy().astype(np.float64) for u in Us], G.cpu().numpy(), st, Uo, h, plan, U0
 
 
-@pytest.mark.parametrize("prec,name,sweeps", [("bf16", "c1", 30), ("fp16", "c1", 30), ("bf16", "zipf3", 5),
-                                              ("fp16", "zipf3", 5), ("bf16", "n4k10", 5), ("fp16", "n4k10", 5)])
-def test_16bit_run_reaches_oracle_fit(prec, name, sweeps):
+# (form, tensor, the workload's own sweep count, qualifies). A form qualifies
+# when its fit after those sweeps is within 1e-4 relative of the FP64
+# oracle's after the same sweeps from the same start. The Zipf tensors have
+# the shapes of the benchmark workloads (3-way K = 16 and 32 at 20 sweeps;
+# 4-way K = 10 at 15); the 200^3 uniform tensor is the 10-sweep parity
+# workload, whose objective is almost flat (fit ~0.002): there the 16-bit
+# roundings move the trajectory by more than 1e-4 at 10 sweeps and the forms
+# do not qualify; for them the test measures the time to fit, the sweeps (and
+# milliseconds) until the form's fit reaches (1 - 1e-4) times the oracle's fit
+# after the workload's sweeps.
+FIT_GATE = [("bf16", "c1", 10, False), ("fp16", "c1", 10, None), ("bf16", "zipf3", 20, True),
+            ("fp16", "zipf3", 20, True), ("bf16", "n3rag", 20, True), ("bf16", "n4k10", 15, True),
+            ("fp16", "n4k10", 15, True), ("bf16", "n3k32", 15, False), ("fp16", "n3k32", 15, False)]
+
+
+@pytest.mark.parametrize("prec,name,sweeps,qualifies", FIT_GATE)
+def test_16bit_fit_at_the_workload_sweeps(prec, name, sweeps, qualifies):
     print(f"[prec-run] case={name} prec={prec} sweeps={sweeps}", flush=True)
-    dims, K, idx, vals32, U, G, st, Uo, h = run_fit(name, prec, sweeps)
+    dims, K, idx, vals32, U, G, st, Uo, h, plan, U0 = run_fit(name, prec, sweeps)
     assert st.sweeps == sweeps
     fit_o = h["fit"][-1]
-    assert abs(st.fit - fit_o) <= 1e-4 * abs(fit_o), (st.fit, fit_o)
+    gap = abs(st.fit - fit_o) / abs(fit_o)
+    ok = gap <= 1e-4
     assert st.orth_err_max < 1e-5
     # the returned core and f are the float32-operand ones for the returned factors
     ci, cv = O.coalesce(idx, vals32.astype(np.float64), dims)
     Gchk = O.core_segment(ci, cv, U)
     assert np.linalg.norm(G - Gchk) / np.linalg.norm(Gchk) < 1e-5
     assert st.f == pytest.approx(float(np.sum(Gchk ** 2)), rel=2e-5)
+    if qualifies is not None:
+        assert ok == qualifies, f"{prec} {name}: fit gap {gap:.3g} after {sweeps} sweeps"
+    if ok:
+        print(f"[fit-gate] {prec} {name} {sweeps} sweeps: qualifies, gap {gap:.2e}", flush=True)
+        return
+    # not qualifying: time to fit, i.e. the first sweep count at which the form's
+    # fit reaches (1 - 1e-4) fit_o, measured by runs of that many sweeps from the
+    # same start (at most 4x the workload's sweeps), against the FP32 form's time
+    # for the workload's sweeps
+    target = (1.0 - 1e-4) * fit_o
+
+    def timed(p, T):
+        Us = [dev(u) for u in U0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s2 = H.hoqri_run(plan, Us, max_sweeps=T, prec=p)
+        torch.cuda.synchronize()
+        return s2, 1e3 * (time.perf_counter() - t0)
+
+    T = None
+    for t in range(sweeps + 1, 4 * sweeps + 1):
+        s2, ms = timed(prec, t)
+        if s2.fit >= target:
+            T = t
+            break
+    assert T is not None, f"{prec} {name}: fit {s2.fit} still below {target} after {4 * sweeps} sweeps"
+    _, ms32 = timed("fp32", sweeps)
+    print(f"[fit-gate] {prec} {name} {sweeps} sweeps: does not qualify (gap {gap:.2e}); "
+          f"time to fit {T} sweeps, {ms:.2f} ms (FP32 form, {sweeps} sweeps: {ms32:.2f} ms)", flush=True)
+
+
+def test_fp16_rejects_factors_out_of_range():
+    # the float16 copies are u * 2^15: entries of magnitude 1.5 or more (never
+    # in a factor with orthonormal columns) would leave the float16 range, so
+    # the FP16 form refuses them before any pass, leaving the outputs untouched
+    dims, K, idx, vals32, U = make("c1")
+    plan = H.hoqri_plan_create(dev(idx), dev(vals32), dims, K)
+    bad = [u.copy() for u in U]
+    bad[1][7, 2] = 3.0
+    Ud = [dev(u) for u in bad]
+    G = torch.full(K, 5.0, dtype=torch.float32, device=DEV)
+    with pytest.raises(H.HoqriError) as e:
+        H.hoqri_core(plan, Ud, G=G, prec="fp16")
+    assert e.value.status == -1 and torch.all(G == 5.0)
+    A = torch.full((dims[0], K[0]), 5.0, dtype=torch.float32, device=DEV)
+    with pytest.raises(H.HoqriError) as e:
+        H.hoqri_ttmctc(plan, 0, Ud, dev(np.ones(K, np.float32)), A=A, prec="fp16")
+    assert e.value.status == -1 and torch.all(A == 5.0)
+    # the mode being updated is not cast: its factor may hold anything
+    H.hoqri_ttmctc(plan, 1, Ud, dev(np.ones(K, np.float32)), prec="fp16")
+    # BF16 copies keep float32's range: no such limit
+    H.hoqri_core(plan, Ud, prec="bf16")
+    torch.cuda.synchronize()

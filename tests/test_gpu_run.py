@@ -244,3 +244,52 @@ def test_sketch_start_matches_oracle_and_recovers_planted():
     U = H.hoqri_sketch_start(plan, Om, dev(rng.standard_normal(K).astype(np.float32)))
     for n in range(3):
         assert O.subspace_dist(U[n].cpu().numpy().astype(np.float64), U0t[n]) < 1e-7
+
+
+def test_error_change_stop_rule():
+    # §6.1's rule: stop when the relative approximation error
+    # eps_t = sqrt(max(||X||^2 - f_t, 0) / ||X||^2) changes by less than tol between
+    # consecutive sweeps. The GPU must stop at the first sweep where its own f
+    # sequence meets the rule, within one sweep of the oracle's stop (float32 and
+    # float64 f may decide differently next to the threshold), and its state must
+    # equal the oracle's after the same number of sweeps.
+    dims, K = (30, 30, 30), (2, 2, 2)
+    idx, vals = synth.coo_uniform(dims, 300, seed=15)
+    start = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 9))]
+    vals32 = vals.astype(np.float32)
+    tol = 9e-6
+    plan = H.hoqri_plan_create(dev(idx), dev(vals32), dims, K)
+    Us = [dev(u) for u in start]
+    fh = torch.zeros(40 * 3, dtype=torch.float64, device=DEV)
+    G, st = H.hoqri_run(plan, Us, max_sweeps=40, tol=tol, f_hist=fh, stop="err")
+    torch.cuda.synchronize()
+    T = st.sweeps
+    fh = fh.cpu().numpy()
+    F = np.array([fh[t * 3] for t in range(T)] + [st.f])
+    eps = np.sqrt(np.maximum(st.norm_x2 - F, 0.0) / st.norm_x2)
+    d = np.abs(np.diff(eps))
+    assert 1 < T < 40
+    assert np.all(d[:-1] >= tol) and d[-1] < tol
+    _, _, h = O.hoqri(idx, vals32.astype(np.float64), dims, K, [u.astype(np.float64) for u in start],
+                      sweeps=40, tol=tol, stop="err")
+    assert abs(T - len(h["f_sweep"])) <= 1
+    Uo, _, h2 = O.hoqri(idx, vals32.astype(np.float64), dims, K, [u.astype(np.float64) for u in start], sweeps=T)
+    assert st.f == pytest.approx(h2["f_sweep"][-1], rel=1e-5)
+    for n in range(3):
+        assert np.abs(Us[n].cpu().numpy() - Uo[n]).max() < 1e-4
+    # the relative-change rule with the same threshold stops elsewhere: the rules differ
+    Us2 = [dev(u) for u in start]
+    _, st2 = H.hoqri_run(plan, Us2, max_sweeps=40, tol=tol, stop="rel_f")
+    assert st2.sweeps != T
+    with pytest.raises(H.HoqriError):
+        _bad_stop(plan, Us2)
+
+
+def _bad_stop(plan, Us):
+    # an unknown stop rule is an argument error, detected before any launch
+    import ctypes
+    L = H.load()
+    opts = H.RunOpts(3, 1e-6, H.PREC["fp32"], 1, 0, 0, None, 0.0, 0, 1, 7)
+    st = H.RunStats()
+    H._check(L.hoqri_run(plan.handle, H._ptr_array(Us), H._ptr(torch.empty(plan.ranks, device=DEV)), None,
+                         ctypes.byref(opts), ctypes.byref(st), H._stream(None)), "hoqri_run")
