@@ -130,6 +130,20 @@ size_t hoqri_orth_workspace_size(int64_t rows, int32_t cols);
 hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A, float* d_U, double* d_R,
                         int32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* hoqri_orth without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same kernels and results (bitwise those of
+ * hoqri_orth), with the scratch taken from a fixed device array of
+ * hoqri_orth_noalloc_scratch_bytes() bytes (about 32 MiB) per GPU, set up on
+ * the first call on each device and held until the process ends. Allocates
+ * nothing. Arguments and errors as hoqri_orth; HOQRI_ERR_UNSUPPORTED if the
+ * shape needed more scratch than the array holds (no valid shape does).
+ * Calls that overlap on one GPU (several streams or threads) share the array
+ * and race: serialise them. */
+hoqri_status hoqri_orth_noalloc(int64_t rows, int32_t cols, const float* d_A, float* d_U, double* d_R,
+                                int32_t* d_status, hipStream_t stream);
+size_t hoqri_orth_noalloc_scratch_bytes(void);
+
 typedef struct {
   int32_t max_sweeps;   /* sweeps over all N modes (one sweep = one HOQRI iteration) */
   double tol;           /* stop rule threshold (0 disables); the rule is chosen by stop_rule */

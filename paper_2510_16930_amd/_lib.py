@@ -30,7 +30,7 @@ EXPORTS = (
     "hoqri_status_string", "hoqri_timing_enable", "hoqri_timing_read",
     "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats", "hoqri_arena_destroy",
     "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info", "hoqri_server_destroy",
-    "hoqri_sketch_start",
+    "hoqri_sketch_start", "hoqri_orth_noalloc", "hoqri_orth_noalloc_scratch_bytes",
 )
 KERNEL = {"ttmctc": 0, "core": 1, "orth": 2, "fixup": 3}
 
@@ -102,6 +102,9 @@ def load() -> ctypes.CDLL:
     L.hoqri_orth_workspace_size.argtypes = [i64, i32]
     L.hoqri_orth_workspace_size.restype = sz
     L.hoqri_orth.argtypes = [i64, i32, vp, vp, vp, vp, vp, sz, vp]
+    L.hoqri_orth_noalloc.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+    L.hoqri_orth_noalloc_scratch_bytes.argtypes = []
+    L.hoqri_orth_noalloc_scratch_bytes.restype = sz
     L.hoqri_run.argtypes = [vp, P(vp), vp, vp, P(RunOpts), P(RunStats), vp]
     L.hoqri_sketch_start.argtypes = [vp, P(vp), vp, P(vp), vp]
     L.hoqri_timing_enable.argtypes = [vp, i32]
@@ -121,7 +124,7 @@ def load() -> ctypes.CDLL:
     L.hoqri_server_destroy.argtypes = [vp]
     L.hoqri_server_destroy.restype = None
     for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
-                 "hoqri_ttmctc", "hoqri_orth", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
+                 "hoqri_ttmctc", "hoqri_orth", "hoqri_orth_noalloc", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
                  "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats",
                  "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info",
                  "hoqri_sketch_start"):
@@ -277,6 +280,20 @@ def hoqri_orth(A, U=None, R=None, status=None, workspace=None, stream=None):
         workspace = torch.empty(hoqri_orth_workspace_size(rows, cols), dtype=torch.uint8, device=A.device)
     _check(L.hoqri_orth(rows, cols, _ptr(A), _ptr(U), _ptr(R) if R is not None else None, _ptr(status),
                         _ptr(workspace), workspace.numel(), _stream(stream)), "hoqri_orth")
+    return U, status
+
+
+def hoqri_orth_noalloc(A, U, R=None, status=None, stream=None):
+    """hoqri_orth with the library's fixed per-GPU scratch instead of a
+    workspace (allocates nothing; the caller passes U and status). Returns
+    (U, status tensor)."""
+    import torch
+    L = load()
+    _need_cuda(A, torch.float32, "A")
+    _need_cuda(U, torch.float32, "U")
+    rows, cols = A.shape
+    _check(L.hoqri_orth_noalloc(rows, cols, _ptr(A), _ptr(U), _ptr(R) if R is not None else None, _ptr(status),
+                                _stream(stream)), "hoqri_orth_noalloc")
     return U, status
 
 

@@ -18,6 +18,7 @@
 // write for the final product; the K x K work runs in single workgroups.
 #include "passes.h"
 
+#include <mutex>
 #include <vector>
 
 namespace hoqri {
@@ -580,3 +581,51 @@ extern "C" hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A,
   return launch_orth(rows, cols, d_A, d_U, d_R, d_status, d_ws, ws_bytes, stream, false);
 }
 
+// ---------------------------------------------------------------------------
+// The QR step without a caller workspace, for callers that cannot allocate
+// device memory (code under graph capture, tight serving loops): its scratch
+// (Gram partials, the K x K matrices and the breakdown flag) lives in a
+// file-scope device array, one per GPU, held until the process ends. Every
+// piece of it is written before it is read within one call, so nothing has to
+// be cleared between calls; calls that overlap on one GPU share the array and
+// race.
+// ---------------------------------------------------------------------------
+namespace hoqri {
+namespace {
+// the largest workspace hoqri_orth needs: at most 4096 Gram blocks of
+// 32 x 32 float64 partials, plus the flag and five 32 x 32 float64 matrices
+constexpr size_t kNoAllocScratchBytes = 256 + (size_t)4096 * kMaxRank * kMaxRank * 8 + 5 * (size_t)kMaxRank * kMaxRank * 8;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the array's name is a host-side stand-in, not a
+// device address, so host code only ever passes this pointer on).
+hoqri_status noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HOQRI_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HOQRI_ERR_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return HOQRI_OK;
+}
+}  // namespace hoqri
+
+extern "C" size_t hoqri_orth_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" hoqri_status hoqri_orth_noalloc(int64_t rows, int32_t cols, const float* d_A, float* d_U, double* d_R,
+                                           int32_t* d_status, hipStream_t stream) {
+  if (rows < 1 || cols < 1 || cols > kMaxRank || cols > rows || !d_A || !d_U || !d_status) return HOQRI_ERR_ARG;
+  if (orth_ws_bytes(rows, cols) > kNoAllocScratchBytes) return HOQRI_ERR_UNSUPPORTED;
+  void* ws = nullptr;
+  HOQRI_TRY(noalloc_scratch(&ws));
+  return launch_orth(rows, cols, d_A, d_U, d_R, d_status, ws, kNoAllocScratchBytes, stream, false);
+}
