@@ -218,6 +218,36 @@ hoqri_status hoqri_run(hoqri_plan* plan, float* const* d_U_inout, float* d_G_out
 hoqri_status hoqri_sketch_start(hoqri_plan* plan, const float* const* d_Omega, const float* d_Gamma,
                                 float* const* d_U_out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Launch-shape tuning of the TTMcTC passes. Per mode: the number of work
+ * ranges the mode-sorted nonzeros are cut into (one wave walks one range) and
+ * the ranges per workgroup. Results depend on them only through the summation
+ * order (each choice is deterministic); the library's own rule is the default.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t ranges[HOQRI_MAX_ORDER];          /* 1 .. hoqri_plan_max_ranges(plan) */
+  int32_t waves_per_group[HOQRI_MAX_ORDER]; /* 0: the library's rule; else capped by what the pass holds */
+} hoqri_tuning;
+/* Current tuning of a plan (host). */
+hoqri_status hoqri_plan_get_tuning(const hoqri_plan* plan, hoqri_tuning* tuning);
+/* Sets the tuning (host; takes effect at the next call). HOQRI_ERR_ARG for
+ * values out of range. Entries of modes >= N are ignored. */
+hoqri_status hoqri_plan_set_tuning(hoqri_plan* plan, const hoqri_tuning* tuning);
+/* Most work ranges per mode the plan's workspace holds. */
+int32_t hoqri_plan_max_ranges(const hoqri_plan* plan);
+/* Autotuner: for every mode whose TTMcTC takes the segment passes, times one
+ * mode update (the TTMcTC pass and, when the passes store slice rows, the core
+ * product that follows) on the plan's own nonzeros for each candidate (ranges
+ * 1/4, 1/2, 1 and 2 times the library's choice; every admissible ranges per
+ * workgroup), median of 3 after a warm-up, and applies the fastest. With
+ * cache_path (a text file, may be NULL) a previous result for the same shape
+ * class (device architecture, order, ranks, operand form, floor(log2) of nnz
+ * and of every mode's nonempty slices) is applied without timing
+ * (*from_cache = 1), and a new result is appended. Overwrites the plan's run
+ * scratch (factors, core) with timing operands; synchronises `stream`. */
+hoqri_status hoqri_autotune(hoqri_plan* plan, hoqri_prec prec, const char* cache_path, hoqri_tuning* chosen,
+                            int32_t* from_cache, hipStream_t stream);
+
 /* Kernel timing (diagnostics). When enabled on a plan, every launch of the
  * listed kernels made through that plan is bracketed by HIP events recorded on
  * the launch stream, and hoqri_timing_read returns the number of launches and

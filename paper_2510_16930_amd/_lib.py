@@ -31,6 +31,7 @@ EXPORTS = (
     "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats", "hoqri_arena_destroy",
     "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info", "hoqri_server_destroy",
     "hoqri_sketch_start", "hoqri_orth_noalloc", "hoqri_orth_noalloc_scratch_bytes",
+    "hoqri_plan_get_tuning", "hoqri_plan_set_tuning", "hoqri_plan_max_ranges", "hoqri_autotune",
 )
 KERNEL = {"ttmctc": 0, "core": 1, "orth": 2, "fixup": 3}
 
@@ -51,6 +52,10 @@ class RunOpts(ctypes.Structure):
 
 METHOD = {"hoqri": 0, "hooi": 1}
 STOP = {"rel_f": 0, "err": 1}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("ranges", ctypes.c_int32 * 5), ("waves_per_group", ctypes.c_int32 * 5)]
 
 
 class RunStats(ctypes.Structure):
@@ -107,6 +112,11 @@ def load() -> ctypes.CDLL:
     L.hoqri_orth_noalloc_scratch_bytes.restype = sz
     L.hoqri_run.argtypes = [vp, P(vp), vp, vp, P(RunOpts), P(RunStats), vp]
     L.hoqri_sketch_start.argtypes = [vp, P(vp), vp, P(vp), vp]
+    L.hoqri_plan_get_tuning.argtypes = [vp, P(Tuning)]
+    L.hoqri_plan_set_tuning.argtypes = [vp, P(Tuning)]
+    L.hoqri_plan_max_ranges.argtypes = [vp]
+    L.hoqri_plan_max_ranges.restype = i32
+    L.hoqri_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, P(Tuning), P(i32), vp]
     L.hoqri_timing_enable.argtypes = [vp, i32]
     L.hoqri_timing_read.argtypes = [vp, i32, P(i64), P(dbl)]
     L.hoqri_status_string.argtypes = [ctypes.c_int]
@@ -127,7 +137,7 @@ def load() -> ctypes.CDLL:
                  "hoqri_ttmctc", "hoqri_orth", "hoqri_orth_noalloc", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
                  "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats",
                  "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info",
-                 "hoqri_sketch_start"):
+                 "hoqri_sketch_start", "hoqri_plan_get_tuning", "hoqri_plan_set_tuning", "hoqri_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -348,6 +358,45 @@ def hoqri_sketch_start(plan: Plan, Omega, Gamma, U=None, stream=None):
     _check(load().hoqri_sketch_start(plan.handle, _ptr_array(Omega), _ptr(Gamma), _ptr_array(U), _stream(stream)),
            "hoqri_sketch_start")
     return U
+
+
+def _tuning_dict(t: Tuning, N: int):
+    return {"ranges": [int(t.ranges[n]) for n in range(N)],
+            "waves_per_group": [int(t.waves_per_group[n]) for n in range(N)]}
+
+
+def hoqri_plan_get_tuning(plan: Plan):
+    """The plan's launch shapes per mode: {"ranges": [...], "waves_per_group": [...]}."""
+    L = load()
+    t = Tuning()
+    _check(L.hoqri_plan_get_tuning(plan.handle, ctypes.byref(t)), "hoqri_plan_get_tuning")
+    return _tuning_dict(t, len(plan.dims))
+
+
+def hoqri_plan_set_tuning(plan: Plan, ranges, waves_per_group=None):
+    L = load()
+    t = Tuning()
+    for n, w in enumerate(ranges):
+        t.ranges[n] = int(w)
+        t.waves_per_group[n] = int(waves_per_group[n]) if waves_per_group is not None else 0
+    _check(L.hoqri_plan_set_tuning(plan.handle, ctypes.byref(t)), "hoqri_plan_set_tuning")
+
+
+def hoqri_plan_max_ranges(plan: Plan) -> int:
+    return int(load().hoqri_plan_max_ranges(plan.handle))
+
+
+def hoqri_autotune(plan: Plan, prec: str = "fp32", cache_path: str | None = None, stream=None):
+    """Times the candidate launch shapes on the plan and applies the fastest
+    (or a cached result for the same shape class). Returns (tuning dict,
+    from_cache)."""
+    L = load()
+    t = Tuning()
+    fc = ctypes.c_int32(0)
+    path = cache_path.encode() if cache_path else None
+    _check(L.hoqri_autotune(plan.handle, PREC[prec], path, ctypes.byref(t), ctypes.byref(fc), _stream(stream)),
+           "hoqri_autotune")
+    return _tuning_dict(t, len(plan.dims)), bool(fc.value)
 
 
 def hoqri_timing_enable(plan: Plan, enable: bool = True):

@@ -44,7 +44,9 @@ struct ModeData {
   int32_t* empty_row;  // [E]   original indices of the empty slices (= inv + R)
   int64_t R;           // number of nonempty slices
   int64_t E;           // number of empty slices (I_n - R)
-  int32_t ranges;      // work ranges of the segment passes on this mode
+  int32_t ranges;      // work ranges of the TTMcTC pass on this mode (tunable up to ranges_cap)
+  int32_t ranges0;     // the library's own choice (plan creation)
+  int32_t rpw;         // ranges per workgroup of the TTMcTC pass (0: the library's rule)
 };
 
 // Scratch regions used by the passes (all inside the caller's workspace).
@@ -97,6 +99,7 @@ struct hoqri_plan {
   int64_t ybuf_rows;
   int32_t core_w;
   int32_t yfuse;       // TTMcTC passes can store Y_(n) and the core follows from it
+  int32_t ranges_cap;  // most work ranges the range buffers (carries, metadata, row partials) hold
   hoqri::ModeData md[hoqri::kMaxOrder];
   hoqri::Scratch sc;
   void* ws;
@@ -116,6 +119,7 @@ struct Layout {
   size_t run_scratch;  // scratch of the passes (overlaps build_tmp)
   size_t sort_tmp;     // rocPRIM temporary storage
   int32_t ranges[kMaxOrder];
+  int32_t ranges_cap;    // range buffers are sized for this many ranges (room for tuning)
   int32_t core_groups;   // partial blocks reduced by the core pass
   int32_t core_mode;     // mode whose sorted copy the core pass reads
   int32_t core_rows;     // nonzero: core pass writes slice rows y_i, then a small product with U^(c)
@@ -150,11 +154,17 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
                            const int32_t* out_map, hipStream_t s, bool rows = false);
 // G = X x {U^T} from the rows Y_(mode) stored by the last TTMcTC pass of `mode`
 // and the (updated) factor U^(mode) in the plan's scratch; ||G||^2 into *f_out.
-hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s, bool split = false);
+hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s, bool split = false,
+                          bool yb16 = false);
+// The TTMcTC pass of `mode` in operand form `prec` stores its slice rows in
+// bfloat16 (the 2 x 2-block BF16 pass) rather than float32.
+bool ttm_rows_bf16(const hoqri_plan* p, int mode, int prec);
+// Most ranges per workgroup the TTMcTC pass of `mode` takes in form `prec`.
+int ttm_max_rpw(const hoqri_plan* p, int mode, int prec);
 // A = Y_(mode) G_(mode)^T from the rows stored by the last TTMcTC pass of
 // `mode` (label order, rows of empty slices zeroed): one inner step of HOOI's
 // orthogonal iteration when G = U^(mode)T Y_(mode).
-hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s);
+hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s, bool yb16 = false);
 bool segpass_supported(const hoqri_plan* p, int mode);
 // Modes the segment passes do not take use the generic kernels (float32
 // operands; every rank <= 32).

@@ -57,6 +57,7 @@ struct PrepArgs {
   int64_t gstride[kMaxOrder];  // C-order strides of G
   int32_t nblk;           // blocks of this launch (grid-stride loop)
   int32_t wide16;         // bfloat16 operand of the one-wave 16-bit passes: 1 c-tile layout, 2 2x2-block layout
+  int32_t pair;           // block (rb, cb) of y_i holds entries (2r + rb, 2c + cb) instead of (16 rb + r, 16 cb + c)
 };
 
 struct FixArgs {
@@ -76,6 +77,7 @@ struct CoreRedArgs {
   int64_t gstride[kMaxOrder];
   float* G;
   double* fpart;
+  int32_t pair;  // the rows are in the paired order of the 2 x 2-block pass (see PrepArgs)
 };
 
 // Core product of the row-writing core pass: partial[chunk][b][kc][j'] =
@@ -91,6 +93,7 @@ struct CoreGemmArgs {
   int32_t Kc, KC, R, W, B;
   int32_t nchunk;  // partials: chunk c takes the 16-row groups c, c + nchunk, ...
   int32_t split;   // 1: products in split bfloat16 (hi + lo, three per product; 16-bit forms)
+  int32_t yb16;    // 1: the rows are bfloat16 (stored by the 2 x 2-block BF16 pass; implies split)
   float* gpart;
 };
 
@@ -103,6 +106,7 @@ struct RowsAArgs {
   const int32_t* ymeta;
   const float* gtop;
   int32_t R, W, B, KN2, Kn;
+  int32_t yb16;    // 1: the rows are bfloat16
   int64_t groups;  // 16-row groups over the R + 2W rows
   float* A;
   float* carry;
@@ -167,7 +171,9 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
                          const int32_t* out_map, TtmJob* job, bool rows = false);
 hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, CoreJob* job);
 // After the TTMcTC pass of `mode` with rows and the update of U^(mode) (float32, label order).
-hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split = false);
+// yb16: the pass stored the rows in bfloat16 (ttm_rows_bf16).
+hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split = false,
+                           bool yb16 = false);
 
 
 struct GramArgs {

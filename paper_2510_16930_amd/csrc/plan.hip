@@ -463,6 +463,10 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     L->ranges[n] = choose_ranges(nnz);
     if (L->ranges[n] > rmax) rmax = L->ranges[n];
   }
+  // the range buffers leave room for a tuner to double the ranges (up to 16384)
+  rmax = (int32_t)std::min<int64_t>(std::min<int64_t>(2 * (int64_t)rmax, std::max<int32_t>(rmax, 16384)), nnz);
+  if (rmax < 1) rmax = 1;
+  L->ranges_cap = rmax;
   // core mode, from the shape alone: cost ~ nnz / K_n (Kronecker work) plus an
   // upper bound min(I_n, nnz) of its nonempty slices (per-slice work)
   int cm = 0;
@@ -742,7 +746,10 @@ static hoqri_status build_plan(hoqri_plan* p, const int32_t* d_idx, const float*
     p->md[n].E = p->dims[n] - Rh[n];
     p->md[n].empty_row = p->md[n].inv + Rh[n];  // original indices of the empty slices
     p->md[n].ranges = L.ranges[n];
+    p->md[n].ranges0 = L.ranges[n];
+    p->md[n].rpw = 0;
   }
+  p->ranges_cap = L.ranges_cap;
   p->core_mode = L.core_mode;
   p->core_groups = L.core_groups;
   p->core_rows = L.core_rows;
@@ -765,9 +772,7 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
     pass_sizes(p->N, p->K, n, &g1, &g2);
     if (g1 > gtop_max) gtop_max = g1;
   }
-  int32_t rmax = 0;
-  for (int n = 0; n < p->N; ++n)
-    if (L.ranges[n] > rmax) rmax = L.ranges[n];
+  const int32_t rmax = L.ranges_cap;
   Carver r{(char*)p->ws + L.persistent, 0};
   for (int n = 0; n < p->N; ++n) p->sc.Up[n] = r.take<float>(p->dims[n] * p->K[n]);
   for (int n = 0; n < p->N; ++n) p->sc.Uh[n] = r.take<uint16_t>(p->dims[n] * p->K[n]);

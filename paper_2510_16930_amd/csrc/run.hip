@@ -373,9 +373,10 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
         }
         HOQRI_TRY(refresh16(p, op, n, stream));
         // the 16-bit forms take the core from the stored rows in split bfloat16
-        if (fuse) HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream, op != OP_FP32));
+        // (the 2 x 2-block BF16 pass stores them in bfloat16)
+        if (fuse) HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream, op != OP_FP32, ttm_rows_bf16(p, n, op)));
         // HOOI: next orthogonal-iteration step A = Y_(n) (Y_(n)^T U) from the stored rows
-        if (it + 1 < inner) HOQRI_TRY(launch_rows_a(p, n, d_G_out, p->sc.A, stream));
+        if (it + 1 < inner) HOQRI_TRY(launch_rows_a(p, n, d_G_out, p->sc.A, stream, ttm_rows_bf16(p, n, op)));
       }
     }
     if (!fuse) HOQRI_TRY(launch_core(p, ops, d_G_out, fsw + t + 1, stream));
@@ -493,5 +494,234 @@ extern "C" hoqri_status hoqri_timing_read(hoqri_plan* p, int32_t kind, int64_t* 
   }
   *launches = n;
   *total_ms = tot;
+  return HOQRI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape tuning of the TTMcTC passes: per mode, the number of work
+// ranges (nonzeros per wave) and the ranges per workgroup. The autotuner times
+// one mode update's passes (the TTMcTC pass and, with stored slice rows, the
+// core product that follows it) for each candidate on the plan's own
+// nonzeros and keeps the fastest; results are cached in a text file, one line
+// per shape class (device, order, ranks, operand form, and the powers of two
+// of nnz and of every mode's nonempty slices).
+// ---------------------------------------------------------------------------
+#include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace hoqri {
+namespace {
+
+int ilog2(int64_t v) {
+  int e = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++e;
+  }
+  return e;
+}
+
+std::string tune_key(const hoqri_plan* p, hoqri_prec prec) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  std::ostringstream k;
+  k << "hoqri-tune-v1 " << arch << " N=" << p->N << " K=";
+  for (int n = 0; n < p->N; ++n) k << (n ? "," : "") << p->K[n];
+  k << " prec=" << (int)prec << " nnz=2^" << ilog2(p->nnz) << " R=";
+  for (int n = 0; n < p->N; ++n) k << (n ? "," : "") << "2^" << ilog2(p->md[n].R);
+  return k.str();
+}
+
+hoqri_status validate_tuning(const hoqri_plan* p, const hoqri_tuning* t) {
+  for (int n = 0; n < p->N; ++n) {
+    if (t->ranges[n] < 1 || t->ranges[n] > p->ranges_cap) return HOQRI_ERR_ARG;
+    if (t->waves_per_group[n] < 0 || t->waves_per_group[n] > 64) return HOQRI_ERR_ARG;
+  }
+  return HOQRI_OK;
+}
+
+void apply_tuning(hoqri_plan* p, const hoqri_tuning* t) {
+  for (int n = 0; n < p->N; ++n) {
+    p->md[n].ranges = t->ranges[n];
+    p->md[n].rpw = t->waves_per_group[n];
+  }
+}
+
+void read_tuning(const hoqri_plan* p, hoqri_tuning* t) {
+  *t = hoqri_tuning{};
+  for (int n = 0; n < p->N; ++n) {
+    t->ranges[n] = p->md[n].ranges;
+    t->waves_per_group[n] = p->md[n].rpw;
+  }
+}
+
+// "key | W_0 rpw_0 W_1 rpw_1 ..." lines; the last line with the key wins
+bool cache_lookup(const char* path, const std::string& key, int N, hoqri_tuning* t) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const size_t bar = line.find(" | ");
+    if (bar == std::string::npos || line.compare(0, bar, key) != 0 || bar != key.size()) continue;
+    std::istringstream in(line.substr(bar + 3));
+    hoqri_tuning v{};
+    bool ok = true;
+    for (int n = 0; n < N && ok; ++n) ok = static_cast<bool>(in >> v.ranges[n] >> v.waves_per_group[n]);
+    if (ok) {
+      *t = v;
+      found = true;
+    }
+  }
+  return found;
+}
+
+bool cache_store(const char* path, const std::string& key, int N, const hoqri_tuning& t) {
+  std::ofstream f(path, std::ios::app);
+  if (!f) return false;
+  f << key << " |";
+  for (int n = 0; n < N; ++n) f << " " << t.ranges[n] << " " << t.waves_per_group[n];
+  f << "\n";
+  return static_cast<bool>(f);
+}
+
+// Deterministic finite operands for timing: every factor entry 1/sqrt(R_m)
+// (the stored rows of nonempty slices), the core 1/sqrt(prod K).
+hoqri_status tuning_operands(hoqri_plan* p, int op, hipStream_t s) {
+  int64_t PK = 1;
+  for (int n = 0; n < p->N; ++n) PK *= p->K[n];
+  for (int n = 0; n < p->N; ++n) {
+    const int64_t cnt = p->dims[n] * p->K[n];
+    const float v = 1.0f / std::sqrt((float)std::max<int64_t>(p->md[n].R, 1));
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(cnt)), dim3(256), 0, s, p->sc.Up[n], cnt, v);
+    HOQRI_TRY(refresh16(p, op, n, s));
+  }
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(PK)), dim3(256), 0, s, p->sc.G, PK, 1.0f / std::sqrt((float)PK));
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+// Median time (ms) of one mode update's passes with the plan's current tuning.
+hoqri_status time_mode(hoqri_plan* p, int n, int op, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  const Operands ops = plan_operands(p, op);
+  const bool fuse = p->yfuse != 0;
+  auto once = [&]() -> hoqri_status {
+    HOQRI_TRY(launch_ttmctc(p, n, ops, p->sc.G, p->sc.A, nullptr, s, fuse));
+    if (fuse) HOQRI_TRY(launch_ycore(p, n, p->sc.G, p->sc.f_dev, s, op != OP_FP32, ttm_rows_bf16(p, n, op)));
+    return HOQRI_OK;
+  };
+  HOQRI_TRY(once());  // warm-up (kernel load, caches)
+  float t[3];
+  for (int r = 0; r < 3; ++r) {
+    HOQRI_HIP_TRY(hipEventRecord(e0, s));
+    HOQRI_TRY(once());
+    HOQRI_HIP_TRY(hipEventRecord(e1, s));
+    HOQRI_HIP_TRY(hipEventSynchronize(e1));
+    HOQRI_HIP_TRY(hipEventElapsedTime(&t[r], e0, e1));
+  }
+  std::sort(t, t + 3);
+  *ms = t[1];
+  return HOQRI_OK;
+}
+
+}  // namespace
+}  // namespace hoqri
+
+extern "C" hoqri_status hoqri_plan_get_tuning(const hoqri_plan* p, hoqri_tuning* t) {
+  if (!p || !t) return HOQRI_ERR_ARG;
+  read_tuning(p, t);
+  return HOQRI_OK;
+}
+
+extern "C" int32_t hoqri_plan_max_ranges(const hoqri_plan* p) { return p ? p->ranges_cap : 0; }
+
+extern "C" hoqri_status hoqri_plan_set_tuning(hoqri_plan* p, const hoqri_tuning* t) {
+  if (!p || !t) return HOQRI_ERR_ARG;
+  HOQRI_TRY(validate_tuning(p, t));
+  apply_tuning(p, t);
+  return HOQRI_OK;
+}
+
+extern "C" hoqri_status hoqri_autotune(hoqri_plan* p, hoqri_prec prec, const char* cache_path, hoqri_tuning* chosen,
+                                       int32_t* from_cache, hipStream_t stream) {
+  HOQRI_TRY(check_plan(p));
+  int op = 0;
+  HOQRI_TRY(check_prec(prec, &op));
+  if (from_cache) *from_cache = 0;
+  const std::string key = tune_key(p, prec);
+  hoqri_tuning t{};
+  if (cache_path && cache_lookup(cache_path, key, p->N, &t) && validate_tuning(p, &t) == HOQRI_OK) {
+    apply_tuning(p, &t);
+    if (chosen) *chosen = t;
+    if (from_cache) *from_cache = 1;
+    return HOQRI_OK;
+  }
+  if (op == OP_FP16) {
+    float as, ys;
+    if (!fp16_scales(p, p->N - 1, &as, &ys)) return HOQRI_ERR_UNSUPPORTED;
+  }
+  HOQRI_TRY(tuning_operands(p, op, stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return HOQRI_ERR_HIP;
+  }
+  hoqri_status st = HOQRI_OK;
+  read_tuning(p, &t);
+  for (int n = 0; n < p->N && st == HOQRI_OK; ++n) {
+    if (!segpass_supported(p, n)) continue;  // generic kernels: nothing to tune
+    const int64_t W0 = p->md[n].ranges0;
+    std::vector<int32_t> Ws;
+    for (int64_t w : {W0 / 4, W0 / 2, W0, 2 * W0}) {
+      const int64_t c = std::min<int64_t>(std::max<int64_t>(w, 1), std::min<int64_t>(p->ranges_cap, p->nnz));
+      if (std::find(Ws.begin(), Ws.end(), (int32_t)c) == Ws.end()) Ws.push_back((int32_t)c);
+    }
+    const int rmax = ttm_max_rpw(p, n, op);
+    std::vector<int32_t> Rs = {0};  // the library's rule first
+    for (int r : {1, 2, 4, 8, 12})
+      if (r <= rmax) Rs.push_back(r);
+    float best = 0.f;
+    int32_t bw = p->md[n].ranges0, br = 0;
+    bool have = false;
+    for (int32_t w : Ws) {
+      for (int32_t r : Rs) {
+        p->md[n].ranges = w;
+        p->md[n].rpw = r;
+        float ms = 0.f;
+        st = time_mode(p, n, op, stream, e0, e1, &ms);
+        if (st != HOQRI_OK) break;
+        if (!have || ms < best) {
+          best = ms;
+          bw = w;
+          br = r;
+          have = true;
+        }
+      }
+      if (st != HOQRI_OK) break;
+    }
+    p->md[n].ranges = bw;
+    p->md[n].rpw = br;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HOQRI_OK) {
+    for (int n = 0; n < p->N; ++n) {
+      p->md[n].ranges = p->md[n].ranges0;
+      p->md[n].rpw = 0;
+    }
+    return st;
+  }
+  read_tuning(p, &t);
+  if (chosen) *chosen = t;
+  if (cache_path) (void)cache_store(cache_path, key, p->N, t);
   return HOQRI_OK;
 }

@@ -33,6 +33,7 @@
 // the workgroup and the TTMcTC partial products are added in LDS.
 #include "passes.h"
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -87,6 +88,7 @@ __device__ inline f4 mfma4(float a, float b, f4 c) {
 }
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
@@ -572,13 +574,20 @@ __global__ __launch_bounds__(512) void k_ttm_b(const SegArgs* d, const int32_t* 
 // entries 16 rb + q of the first and 16 cb + q of the second other factor;
 // lane group g holds the k-slots 4g + t as in walk_range. A finished y_i is
 // staged in LDS in bfloat16 and multiplied by G_(n)^T (bfloat16 copy) on the
-// matrix cores with float32 accumulation; the stored slice rows of Y_(n) stay
-// float32 and are written straight from the accumulators.
+// matrix cores with float32 accumulation; the stored slice rows of Y_(n) are
+// those same bfloat16 values (2 KB per slice at 32 x 32 instead of 4 KB), so
+// the core of the updated factor sees exactly the y_i the product with the
+// core saw.
 // ---------------------------------------------------------------------------
 constexpr int kYs22 = 1024 + 16;  // LDS entries per staged y_i (the pad puts slots 8 banks apart)
 __host__ __device__ constexpr int ttm22_wave_bytes(int slots) { return slots * kYs22 * 2 + (2 * slots + 128) * 4; }
 
-template <typename OnSeg>
+// PAIR (both other ranks even): lane q gathers one dword per row, entries
+// 2q and 2q + 1, and block (rb, cb) takes entries 2r + rb of the first and
+// 2c + cb of the second other factor (half the gather instructions; the
+// stage-two operand and the core's scatter follow the same order). Otherwise
+// lane q gathers entries q and 16 + q, one 16-bit load each.
+template <bool PAIR, typename OnSeg>
 __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
                                     uint32_t k2, int lane, int32_t* wlds, OnSeg&& on_seg) {
   constexpr int NM1 = 2;
@@ -600,6 +609,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
 
   // raw bfloat16 entries of k-slots t = 0..3, one per register: packing them
   // where they are loaded would make the loop wait for loads still in flight
+  // (PAIR: ga[0][t] / gb[0][t] hold both entries of the lane's dword)
   struct Set {
     int32_t rec;
     uint32_t ga[2][4];  // first other factor, entry 16 rb + q
@@ -619,10 +629,15 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
     for (int t = 0; t < 4; ++t) {
       const uint32_t oa = ((uint32_t)SJ.j0[t] << 1) + k2;
       const uint32_t ob = ((uint32_t)SJ.j1[t] << 1) + k2;
-      S.ga[0][t] = ld_u16(rU0, oa);
-      S.ga[1][t] = ld_u16(rU0, oa + 32u);
-      S.gb[0][t] = ld_u16(rU1, ob);
-      S.gb[1][t] = ld_u16(rU1, ob + 32u);
+      if constexpr (PAIR) {
+        S.ga[0][t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, oa, 0, 0);
+        S.gb[0][t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, ob, 0, 0);
+      } else {
+        S.ga[0][t] = ld_u16(rU0, oa);
+        S.ga[1][t] = ld_u16(rU0, oa + 32u);
+        S.gb[0][t] = ld_u16(rU1, ob);
+        S.gb[1][t] = ld_u16(rU1, ob + 32u);
+      }
     }
   };
 
@@ -641,13 +656,24 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
 
   auto step = [&](int32_t blk, Set& C, Set& N2) {
     float xa[2][4];
-    const s4 xb0 = {(short)C.gb[0][0], (short)C.gb[0][1], (short)C.gb[0][2], (short)C.gb[0][3]};
-    const s4 xb1 = {(short)C.gb[1][0], (short)C.gb[1][1], (short)C.gb[1][2], (short)C.gb[1][3]};
+    s4 xb0, xb1;
     const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
+    if constexpr (PAIR) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < 4; ++t) {
+        xb0[t] = (short)(C.gb[0][t] & 0xffffu);
+        xb1[t] = (short)(C.gb[0][t] >> 16);
+        xa[0][t] = xq[t] * __builtin_bit_cast(float, C.ga[0][t] << 16);
+        xa[1][t] = xq[t] * __builtin_bit_cast(float, C.ga[0][t] & 0xffff0000u);
+      }
+    } else {
+      xb0 = s4{(short)C.gb[0][0], (short)C.gb[0][1], (short)C.gb[0][2], (short)C.gb[0][3]};
+      xb1 = s4{(short)C.gb[1][0], (short)C.gb[1][1], (short)C.gb[1][2], (short)C.gb[1][3]};
 #pragma unroll
-      for (int h = 0; h < 2; ++h) xa[h][t] = xq[t] * f16bits_to_f32<P_BF16>(C.ga[h][t]);
+      for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) xa[h][t] = xq[t] * f16bits_to_f32<P_BF16>(C.ga[h][t]);
+      }
     }
     load_idx(blk + 3, C);
     gather(N2);
@@ -719,7 +745,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
 // The workgroup first copies it into LDS (KN2 x 32 KB): every stage two reads
 // all of it, and from LDS that costs a short latency instead of an L2 round
 // trip per step.
-template <int KN2, int SL>
+template <int KN2, int SL, bool PAIR>
 __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
@@ -753,7 +779,7 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
     a.meta[w * 4 + 3] = 0;
   }
   const uint16_t* gt = gl + lane * 8;
-  constexpr uint32_t yrowf = 1024;  // floats per stored row (4 blocks)
+  constexpr uint32_t yrowf = 1024;  // entries per stored row (4 blocks, bfloat16)
 
   int slot = 0;
   auto stage_two = [&]() {
@@ -797,16 +823,18 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
     slot = 0;
   };
 
-  walk_range22(a, lo, hi, s_first, s_last, (uint32_t)q * 2u, lane, wlds,
+  walk_range22<PAIR>(a, lo, hi, s_first, s_last, (uint32_t)q * (PAIR ? 4u : 2u), lane, wlds,
                        [&](int32_t s, int32_t row, const f4* y) {
     int kind = KIND_COMPLETE;
     if (s == s_first && head_clip) kind = KIND_HEAD;
     else if (s == s_last && tail_clip) kind = KIND_TAIL;
     // stage y_s in bfloat16 (nearest even), block b at 256 b + c*16 + r
     uint16_t* ys = ybat + slot * kYs22 + q * 16 + 4 * g;
+    u2 yb[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const b4 v = {(__bf16)y[b].x, (__bf16)y[b].y, (__bf16)y[b].z, (__bf16)y[b].w};
+      yb[b] = __builtin_bit_cast(u2, v);
       *reinterpret_cast<s4*>(ys + 256 * b) = __builtin_bit_cast(s4, v);
     }
     if (lane == 0) {
@@ -814,19 +842,21 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
       slot_kind[slot] = kind;
     }
     if (a.yrow) {
-      // the float32 y_s for the core of the updated factor: row by label; a
+      // the bfloat16 y_s for the core of the updated factor: row by label; a
       // split slice leaves its partial per range and zeros in its own row
-      const uint32_t vo = (uint32_t)(q * 16 + 4 * g) * 4u;
-      const auto own = make_rsrc(a.yrow + (size_t)row * yrowf, yrowf * 4u);
+      const uint32_t vo = (uint32_t)(q * 16 + 4 * g) * 2u;
+      uint16_t* const yrow16 = reinterpret_cast<uint16_t*>(a.yrow);
+      const auto own = make_rsrc(yrow16 + (size_t)row * yrowf, yrowf * 2u);
       if (kind == KIND_COMPLETE) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, y[b]), own, vo + 1024u * b, 0, 0);
+        for (int b = 0; b < 4; ++b) __builtin_amdgcn_raw_buffer_store_b64(yb[b], own, vo + 512u * b, 0, 0);
       } else {
-        const auto dst = make_rsrc(a.ycarry + ((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * yrowf, yrowf * 4u);
+        uint16_t* const yc16 = reinterpret_cast<uint16_t*>(a.ycarry);
+        const auto dst = make_rsrc(yc16 + ((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * yrowf, yrowf * 2u);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, y[b]), dst, vo + 1024u * b, 0, 0);
-          __builtin_amdgcn_raw_buffer_store_b128(i4{0, 0, 0, 0}, own, vo + 1024u * b, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(yb[b], dst, vo + 512u * b, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(u2{0u, 0u}, own, vo + 512u * b, 0, 0);
         }
       }
     }
@@ -841,14 +871,14 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
 constexpr int kSlots22 = 4;
 constexpr int kMaxRpw22 = 12;
 
-template <int KN2>
+template <int KN2, bool PAIR>
 __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22(SegArgs a) {
-  ttm22_body<KN2, kSlots22>(a, blockIdx.x);
+  ttm22_body<KN2, kSlots22, PAIR>(a, blockIdx.x);
 }
-template <int KN2>
+template <int KN2, bool PAIR>
 __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
-  ttm22_body<KN2, kSlots22>(d[r], blockIdx.x - first[r]);
+  ttm22_body<KN2, kSlots22, PAIR>(d[r], blockIdx.x - first[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1321,7 +1351,8 @@ __device__ inline void prep_body(const PrepArgs& p, const int blk) {
     }
     const int rb = b / p.CB, cb = b % p.CB;
     const int c = jp >> 4, r = jp & 15;
-    const int rg = 16 * rb + r, cg = 16 * cb + c;
+    // paired order of the 2 x 2-block pass: block (rb, cb) holds entries 2r + rb, 2c + cb
+    const int rg = p.pair ? 2 * r + rb : 16 * rb + r, cg = p.pair ? 2 * c + cb : 16 * cb + c;
     const int kn = 16 * kb + (lane & 15);
     float v = 0.f;
     if (rg < p.krow && cg < p.kcol && kn < p.Kn) {
@@ -1421,6 +1452,9 @@ __global__ __launch_bounds__(512) void k_core_rows_b(const SegArgs* d, const int
 // product of 16 rows takes three v_mfma_f32_16x16x16_bf16 (hi hi, hi lo,
 // lo hi), k-slot 4g + t standing for row 4t + g, instead of four float32
 // products of 4 rows.
+// YB (rows stored in bfloat16 by the 2 x 2-block BF16 pass; with SPLIT): the
+// row entries are exact bfloat16 operands, so a product of 16 rows takes two
+// (hi y, lo y), and each lane loads 8 bytes per row instead of 16.
 constexpr int kGemmThreads = 1024;
 __device__ inline void split_bf16(const float* x, s4* hi, s4* lo) {
   const b4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
@@ -1432,8 +1466,14 @@ __device__ inline void split_bf16(const float* x, s4* hi, s4* lo) {
   *hi = hs;
   *lo = __builtin_bit_cast(s4, l);
 }
-template <int KTT, bool SPLIT>
+// entry c (0..3) of 4 bfloat16 packed in two dwords, as raw bits
+__device__ inline short bf16_part(u2 v, int c) {
+  return (short)((c & 1) ? (v[c >> 1] >> 16) : (v[c >> 1] & 0xffffu));
+}
+template <int KTT, bool SPLIT, bool YB = false>
 __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
+  static_assert(!YB || SPLIT, "bfloat16 rows are read by the split products of the 16-bit forms");
+  typedef typename std::conditional<YB, u2, f4>::type yv_t;
   constexpr int KTM = KTT == 0 ? 2 : KTT;
   __shared__ f4 red[3][4][KTM * 4][64];  // row lanes 1..3, column quarter, accumulator, lane
   const int chunk = blk / p.B, b = blk - chunk * p.B;
@@ -1450,8 +1490,25 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   const int64_t NC = p.nchunk;
   const int64_t R = p.R;
   const int col = b * 256 + 64 * cq + 4 * q;
-  auto product = [&](const f4* yv, float (*ua)[KTM]) {
-    if constexpr (SPLIT) {
+  auto product = [&](const yv_t* yv, float (*ua)[KTM]) {
+    if constexpr (YB) {
+      s4 yh[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        yh[c] = s4{bf16_part(yv[0], c), bf16_part(yv[1], c), bf16_part(yv[2], c), bf16_part(yv[3], c)};
+#pragma unroll
+      for (int kt = 0; kt < KTM; ++kt) {
+        if (kt >= KT) continue;
+        const float uc[4] = {ua[0][kt], ua[1][kt], ua[2][kt], ua[3][kt]};
+        s4 uh, ul;
+        split_bf16(uc, &uh, &ul);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[kt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(uh, yh[c], acc[kt][c], 0, 0, 0);
+          acc[kt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ul, yh[c], acc[kt][c], 0, 0, 0);
+        }
+      }
+    } else if constexpr (SPLIT) {
       s4 yh[4], yl[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -1489,12 +1546,18 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   // after the barrier, so a group's loads are in flight together, and the
   // next group's loads are issued before a group's products.
   const int64_t NG = (R + 15) / 16;
-  auto load_rows = [&](int64_t j, f4* y, float (*u)[KTM]) {
+  const yv_t yzero = {};
+  // entries col .. col + 3 of stored row v (float32, or bfloat16 with YB)
+  auto row_at = [&](const float* base, size_t v) -> yv_t {
+    if constexpr (YB) return *reinterpret_cast<const u2*>(reinterpret_cast<const uint16_t*>(base) + v * row + col);
+    else return *reinterpret_cast<const f4*>(base + v * row + col);
+  };
+  auto load_rows = [&](int64_t j, yv_t* y, float (*u)[KTM]) {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int64_t v = 16 * j + 4 * st + g;
       const int64_t vv = v < R ? v : 0;
-      y[st] = *reinterpret_cast<const f4*>(p.ybuf + (size_t)vv * row + col);
+      y[st] = row_at(p.ybuf, (size_t)vv);
 #pragma unroll
       for (int kt = 0; kt < KTM; ++kt) {
         const int k = 16 * kt + q;
@@ -1502,17 +1565,17 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
       }
     }
   };
-  auto masked_product = [&](int64_t j, f4* y, float (*u)[KTM]) {
+  auto masked_product = [&](int64_t j, yv_t* y, float (*u)[KTM]) {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const bool ok = j < NG && 16 * j + 4 * st + g < R;
-      y[st] = ok ? y[st] : f4{0.f, 0.f, 0.f, 0.f};
+      y[st] = ok ? y[st] : yzero;
 #pragma unroll
       for (int kt = 0; kt < KTM; ++kt) u[st][kt] = (ok && 16 * kt + q < p.Kc) ? u[st][kt] : 0.f;
     }
     product(y, u);
   };
-  f4 yv[4], yn[4];
+  yv_t yv[4], yn[4];
   float ua[4][KTM], un[4][KTM];
   const int64_t j0 = chunk + NC * rl, dj = 4 * NC;
   if (j0 < NG) {
@@ -1534,7 +1597,7 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
     for (int st = 0; st < 4; ++st) {
       const int64_t x = 16 * j + 4 * st + g;
       int32_t lab = -1;
-      const float* src = p.ycarry;
+      size_t src = 0;  // row of ycarry
       if (x < NP) {
         const int64_t w = x >> 1;
         const int kind = (int)(x & 1);
@@ -1542,11 +1605,11 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
         const bool head = fl & 1;
         const bool tail = (fl & 2) && !(sf == sl && head);  // a slice clipped on both sides is a head
         if (kind == 0 ? head : tail) {
-          src = p.ycarry + ((size_t)w * 2 + kind) * row;
+          src = (size_t)w * 2 + kind;
           lab = p.seg_row[kind == 0 ? sf : sl];
         }
       }
-      yv[st] = lab >= 0 ? *reinterpret_cast<const f4*>(src + col) : f4{0.f, 0.f, 0.f, 0.f};
+      yv[st] = lab >= 0 ? row_at(p.ycarry, src) : yzero;
 #pragma unroll
       for (int kt = 0; kt < KTM; ++kt) {
         const int k = 16 * kt + q;
@@ -1588,7 +1651,8 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
 // A from stored rows, one wave per 16-row group: lane (g, q) takes row q of
 // the group and entries j' = 64 g + 4u + v of tile b (the stage-two operand's
 // order), so the product is the TTMcTC pass's stage two with the rows read
-// from memory: D(row 4g + v, kn = 16 kb + q) on every lane.
+// from memory: D(row 4g + v, kn = 16 kb + q) on every lane. Rows stored in
+// bfloat16 (p.yb16) are widened exactly to float32.
 __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, q = lane & 15;
@@ -1598,9 +1662,11 @@ __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
   const int64_t R = p.R, NP = 2 * (int64_t)p.W;
   // where row x of the group comes from and goes to: complete rows v < R; then
   // the valid split-slice partials (head 0 / tail 1 of range w)
-  auto locate = [&](int64_t x, const float** src, float** dst, int ld) -> bool {
+  // src: (buffer, entry offset of the row); dst: output row
+  auto locate = [&](int64_t x, const float** src, size_t* soff, float** dst, int ld) -> bool {
     if (x < R) {
-      *src = p.ybuf + (size_t)x * rowf;
+      *src = p.ybuf;
+      *soff = (size_t)x * rowf;
       *dst = p.A + (size_t)x * ld;
       return true;
     }
@@ -1611,20 +1677,29 @@ __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
     const bool head = fl & 1;
     const bool tail = (fl & 2) && !(sf == sl && head);
     if (kind == 0 ? !head : !tail) return false;
-    *src = p.ycarry + ((size_t)w * 2 + kind) * rowf;
+    *src = p.ycarry;
+    *soff = ((size_t)w * 2 + kind) * rowf;
     *dst = p.carry + ((size_t)w * 2 + kind) * 32;
     return true;
   };
   const float* src = p.ybuf;
+  size_t soff = 0;
   float* dst = nullptr;
-  const bool ok = locate(grp * 16 + q, &src, &dst, p.Kn);
+  const bool ok = locate(grp * 16 + q, &src, &soff, &dst, p.Kn);
   f4 d[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
   for (int b = 0; b < p.B; ++b) {
     const float* gtl = p.gtop + (size_t)b * p.KN2 * 4096 + lane * 4;
-    const float* yr = src + b * 256 + 64 * g;
+    const size_t yo = soff + b * 256 + 64 * g;
 #pragma unroll 4
     for (int u = 0; u < 16; ++u) {
-      const f4 t = *reinterpret_cast<const f4*>(yr + 4 * u);
+      f4 t;
+      if (p.yb16) {
+        const u2 h = *reinterpret_cast<const u2*>(reinterpret_cast<const uint16_t*>(src) + yo + 4 * u);
+        t = f4{__builtin_bit_cast(float, h[0] << 16), __builtin_bit_cast(float, h[0] & 0xffff0000u),
+               __builtin_bit_cast(float, h[1] << 16), __builtin_bit_cast(float, h[1] & 0xffff0000u)};
+      } else {
+        t = *reinterpret_cast<const f4*>(src + yo + 4 * u);
+      }
       const f4 yv = ok ? t : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
@@ -1638,8 +1713,9 @@ __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const float* s2;
+    size_t o2;
     float* out;
-    if (!locate(grp * 16 + 4 * g + v, &s2, &out, p.Kn)) continue;
+    if (!locate(grp * 16 + 4 * g + v, &s2, &o2, &out, p.Kn)) continue;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
       const int kn = 16 * kb + q;
@@ -1650,9 +1726,9 @@ __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
 
 __global__ __launch_bounds__(256) void k_rows_a(RowsAArgs p) { rows_a_body(p, blockIdx.x); }
 
-template <int KTT, bool SPLIT>
+template <int KTT, bool SPLIT, bool YB>
 __global__ __launch_bounds__(kGemmThreads) void k_core_gemm(CoreGemmArgs p) {
-  core_gemm_body<KTT, SPLIT>(p, blockIdx.x);
+  core_gemm_body<KTT, SPLIT, YB>(p, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kGemmThreads) void k_core_gemm_b(const CoreGemmArgs* d, const int32_t* first,
@@ -1662,12 +1738,15 @@ __global__ __launch_bounds__(kGemmThreads) void k_core_gemm_b(const CoreGemmArgs
 }
 
 void launch_core_gemm(const CoreGemmArgs& m, int blocks, hipStream_t s) {
-  if (m.split) {
-    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, true>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
-    else hipLaunchKernelGGL((k_core_gemm<2, true>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+  if (m.yb16) {
+    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, true, true>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+    else hipLaunchKernelGGL((k_core_gemm<2, true, true>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+  } else if (m.split) {
+    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, true, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+    else hipLaunchKernelGGL((k_core_gemm<2, true, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
   } else {
-    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
-    else hipLaunchKernelGGL((k_core_gemm<2, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+    if (m.KC <= 16) hipLaunchKernelGGL((k_core_gemm<1, false, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
+    else hipLaunchKernelGGL((k_core_gemm<2, false, false>), dim3(blocks), dim3(kGemmThreads), 0, s, m);
   }
 }
 
@@ -1764,7 +1843,8 @@ __device__ inline void red_body(const CoreRedArgs& p, const int blk) {
     const int kc = (e >> 8) % (16 * p.KN2);
     const int b = (e >> 8) / (16 * p.KN2);
     const int rb = b / p.CB, cb = b % p.CB;
-    const int rg = 16 * rb + (jp & 15), cg = 16 * cb + (jp >> 4);
+    const int rg = p.pair ? 2 * (jp & 15) + rb : 16 * rb + (jp & 15);
+    const int cg = p.pair ? 2 * (jp >> 4) + cb : 16 * cb + (jp >> 4);
     if (rg < p.krow && cg < p.kcol && kc < p.Kc) {
       int64_t flat = (int64_t)rg * p.kcol + cg;
       int64_t off = (int64_t)kc * p.gstride[p.mode];
@@ -1985,6 +2065,7 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
 // Key offset of the 2 x 2-block BF16 TTMcTC pass (core keys add 1000), and of
 // the 4-way 16-bit pass with c-tiles (plus 1000 x the tiles per wave).
 constexpr int kWideKey = 2000;
+constexpr int kPairKey = 4000;  // the 2 x 2-block pass in paired order (added to kWideKey)
 constexpr int kWide4Key = 10000;
 
 // Kernel instances: one single-plan and one batched launch per
@@ -2049,6 +2130,8 @@ bool seg_kernels(int key, SegKernels* k) {
     nc4 = (key - kWide4Key) / 1000;
     key %= 1000;
   }
+  const bool pair = key >= kWideKey + kPairKey;
+  if (pair) key -= kPairKey;
   const bool wide = key >= kWideKey;
   if (wide) key -= kWideKey;
   key %= 1000;
@@ -2066,12 +2149,12 @@ bool seg_kernels(int key, SegKernels* k) {
   }
   if (!ok || !wide) return ok;
   if (nm1 != 2 || prec != P_BF16) return false;
-  if (kn2 == 1) {
-    k->ttm = (const void*)k_ttm22<1>;
-    k->ttm_b = (const void*)k_ttm22_b<1>;
+  if (pair) {
+    k->ttm = kn2 == 1 ? (const void*)k_ttm22<1, true> : (const void*)k_ttm22<2, true>;
+    k->ttm_b = kn2 == 1 ? (const void*)k_ttm22_b<1, true> : (const void*)k_ttm22_b<2, true>;
   } else {
-    k->ttm = (const void*)k_ttm22<2>;
-    k->ttm_b = (const void*)k_ttm22_b<2>;
+    k->ttm = kn2 == 1 ? (const void*)k_ttm22<1, false> : (const void*)k_ttm22<2, false>;
+    k->ttm_b = kn2 == 1 ? (const void*)k_ttm22_b<1, false> : (const void*)k_ttm22_b<2, false>;
   }
   return true;
 }
@@ -2138,6 +2221,23 @@ void g_strides(const hoqri_plan* p, int64_t* st) {
 
 }  // namespace
 
+// The 2 x 2-block pass gathers entry pairs (one dword) when both other ranks
+// are even (every factor row then starts on a 4-byte boundary).
+bool ttm_pair(const PassGeom& g) { return g.Ko[0] % 2 == 0 && g.Ko[1] % 2 == 0; }
+
+int ttm_max_rpw(const hoqri_plan* p, int mode, int prec) {
+  if (!segpass_supported(p, mode)) return 1;
+  const PassGeom g = geom(p, mode);
+  const int KN2 = (p->K[mode] + 15) / 16;
+  if (ttm_wide(g, prec)) return rpw22(KN2);
+  if (ttm_wide4(g, prec)) return 1;  // the c-tile pass takes one range per workgroup
+  return g.B >= 8 ? 1 : 8 / g.B;     // 512 threads per workgroup
+}
+
+bool ttm_rows_bf16(const hoqri_plan* p, int mode, int prec) {
+  return segpass_supported(p, mode) && ttm_wide(geom(p, mode), prec);
+}
+
 bool segpass_supported(const hoqri_plan* p, int mode) {
   PassGeom g = geom(p, mode);
   return g.nm1 <= 3 && g.B <= 8 && p->K[mode] <= 32;
@@ -2180,10 +2280,13 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   const bool nc4 = ttm_wide4(g, op.prec);
   int nw4 = 1;  // waves per range of the c-tile pass
   const int tiles4 = nc4 ? tiles4c(g.Ko[2], &nw4) : 0;
-  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (nc4 ? kWide4Key + 1000 * tiles4 : 0);
+  const bool pair = wide && ttm_pair(g);
+  job->key = seg_key(g.nm1, KN2, op.prec) + (wide ? kWideKey : 0) + (pair ? kPairKey : 0) +
+             (nc4 ? kWide4Key + 1000 * tiles4 : 0);
   // stage-two operand
   PrepArgs& pa = job->prep;
   pa.wide16 = wide ? 2 : (nc4 ? (op.prec == OP_FP32 ? 3 : 1) : 0);
+  pa.pair = pair ? 1 : 0;
   pa.G = G;
   pa.gtop = p->sc.gtop;
   pa.B = g.B;
@@ -2210,6 +2313,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   if (W > p->nnz) W = p->nnz;
   a.W = (int32_t)W;
   a.RPW = wide ? rpw22(KN2) : nc4 ? 1 : (g.B == 1 ? 4 : 1);
+  if (md.rpw > 0) a.RPW = std::min(md.rpw, ttm_max_rpw(p, mode, op.prec));
   a.gtop = p->sc.gtop;
   a.A = A;
   a.Kn = p->K[mode];
@@ -2480,7 +2584,7 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
 // the updated factor U^(mode): G_(mode) = U^(mode)T Y_(mode). The rows (nonempty
 // slices, then the split-slice partials) are cut into at most kYChunks chunks
 // of equal length; partials are reduced in chunk order.
-hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split) {
+hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split, bool yb16) {
   if (!p->yfuse || !segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
@@ -2502,7 +2606,8 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   int64_t chunks = (nv + kCoreChunk - 1) / kCoreChunk;
   if (chunks > kYChunks) chunks = kYChunks;
   m.nchunk = (int32_t)chunks;
-  m.split = split ? 1 : 0;
+  m.split = (split || yb16) ? 1 : 0;
+  m.yb16 = yb16 ? 1 : 0;
   m.gpart = p->sc.gpart;
   job->gemm_blocks = (int)(chunks * g.B);
   CoreRedArgs& r = job->red;
@@ -2523,6 +2628,7 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   g_strides(p, r.gstride);
   r.G = G;
   r.fpart = p->sc.fpart;
+  r.pair = (yb16 && ttm_pair(g)) ? 1 : 0;  // the rows of the 2 x 2-block pass are in paired order
   const int total = g.B * 16 * KN2 * 256;
   job->red_blocks = (total + kRedOut - 1) / kRedOut;
   job->sum.part = p->sc.fpart;
@@ -2531,9 +2637,9 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   return HOQRI_OK;
 }
 
-hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s, bool split) {
+hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipStream_t s, bool split, bool yb16) {
   YCoreJob job;
-  HOQRI_TRY(prepare_ycore(p, mode, G, f_out, &job, split));
+  HOQRI_TRY(prepare_ycore(p, mode, G, f_out, &job, split, yb16));
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
   launch_core_gemm(job.gemm, job.gemm_blocks, s);
   hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
@@ -2542,7 +2648,7 @@ hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipS
   return HOQRI_OK;
 }
 
-hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s) {
+hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s, bool yb16) {
   TtmJob job;  // for the stage-two operand and the fix-up of this mode's ranges
   const Operands op{OP_FP32, p->sc.Up, p->sc.Uh};
   HOQRI_TRY(prepare_ttm(p, mode, op, G, A, nullptr, &job, true));
@@ -2556,12 +2662,14 @@ hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hi
   r.B = job.seg.B;
   r.KN2 = job.prep.KN2;
   r.Kn = p->K[mode];
+  r.yb16 = yb16 ? 1 : 0;
   r.groups = ((int64_t)r.R + 2 * (int64_t)r.W + 15) / 16;
   r.A = A;
   r.carry = p->sc.carry;
   // k_rows_a reads the operand in the classic float32 order, whatever order
-  // this mode's TTMcTC pass uses
+  // this mode's TTMcTC pass uses, with the rows' own entry order
   job.prep.wide16 = 0;
+  job.prep.pair = (yb16 && ttm_pair(geom(p, mode))) ? 1 : 0;
   TimerScope ts(p, HOQRI_KERNEL_CORE, s);
   hipLaunchKernelGGL(k_prep_gtop, dim3(job.prep_blocks), dim3(256), 0, s, job.prep);
   hipLaunchKernelGGL(k_rows_a, dim3((unsigned)((r.groups + 3) / 4)), dim3(256), 0, s, r);

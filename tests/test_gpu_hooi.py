@@ -106,3 +106,30 @@ def test_bad_method_rejected():
     U0 = [dev(u.astype(np.float32)) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 2))]
     with pytest.raises(H.HoqriError):
         H.hoqri_run(plan, U0, max_sweeps=1, method="hooi", inner_iters=-1)
+
+
+def test_hooi_bf16_on_bfloat16_slice_rows():
+    # ranks 20 x 24 x 20: every mode's y_i spans 2 x 2 blocks, so the BF16 pass
+    # stores the slice rows in bfloat16 and HOOI's inner steps read them from
+    # there; on a planted tensor the updates reach the oracle's SVD subspaces
+    # to bfloat16 accuracy (f within the 16-bit bar of 1e-4)
+    dims, K = (600, 500, 400), (20, 24, 20)
+    rng = np.random.default_rng(41)
+    rows = [np.sort(rng.choice(d, size=k + 6, replace=False)) for d, k in zip(dims, K)]
+    Us = [np.linalg.qr(rng.standard_normal((r.size, k)))[0] for r, k in zip(rows, K)]
+    block = O.tucker_dense(rng.standard_normal(K) * 10.0, Us)
+    grids = np.meshgrid(*rows, indexing="ij")
+    idx_n, v_n = synth.coo_uniform(dims, 30_000, seed=42)
+    idx = np.concatenate([np.stack([g.ravel() for g in grids]).astype(np.int64), idx_n.astype(np.int64)], axis=1)
+    ci, cv = O.coalesce(idx, np.concatenate([block.ravel(), 0.02 * v_n]), dims)
+    idx, vals = ci.astype(np.int32), cv.astype(np.float32)
+    U0 = [u.astype(np.float32) for u in O.orthonormal_start(synth.gaussian_start(dims, K, 3))]
+    plan = H.hoqri_plan_create(dev(idx), dev(vals), dims, K)
+    Us = [dev(u) for u in U0]
+    G, st = H.hoqri_run(plan, Us, max_sweeps=2, method="hooi", inner_iters=20, prec="bf16")
+    torch.cuda.synchronize()
+    Uo, Go, h = O.hooi(idx, vals.astype(np.float64), dims, K, [u.astype(np.float64) for u in U0], sweeps=2)
+    assert st.f == pytest.approx(h["f_sweep"][-1], rel=1e-4)
+    assert st.orth_err_max < 1e-5
+    for n in range(3):
+        assert O.subspace_dist(Us[n].cpu().numpy().astype(np.float64), Uo[n]) < 1e-3
