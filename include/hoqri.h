@@ -301,6 +301,9 @@ typedef struct {
   int32_t max_admit_per_step; /* plan builds per step (0: no limit) */
   int32_t report_orth_err;  /* nonzero: compute ||U^T U - I||_F of finished requests */
   int32_t keep_on_breakdown; /* as in hoqri_run_opts */
+  int32_t use_graphs;       /* nonzero: each step's batched launches are captured into a HIP graph and
+                               replayed as one launch (the previous step's executable graph is updated
+                               in place when its topology is unchanged); results are bitwise the same */
 } hoqri_server_opts;
 
 typedef struct {

@@ -67,7 +67,8 @@ class RunStats(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("max_admit_per_step", ctypes.c_int32),
-                ("report_orth_err", ctypes.c_int32), ("keep_on_breakdown", ctypes.c_int32)]
+                ("report_orth_err", ctypes.c_int32), ("keep_on_breakdown", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -477,13 +478,13 @@ class Server:
 
     def __init__(self, arena_bytes: int, max_slots: int = 64, max_sweeps: int = 30, tol: float = 1e-6,
                  max_admit_per_step: int = 0, report_orth_err: bool = False, keep_on_breakdown: bool = True,
-                 device=None):
+                 device=None, use_graphs: bool = False):
         import torch
         L = load()
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device or "cuda")
         opts = ServerOpts(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(max_slots), int(max_sweeps),
                           float(tol), int(max_admit_per_step), int(bool(report_orth_err)),
-                          int(bool(keep_on_breakdown)))
+                          int(bool(keep_on_breakdown)), int(bool(use_graphs)))
         h = ctypes.c_void_p()
         _check(L.hoqri_server_create(ctypes.byref(opts), ctypes.byref(h)), "hoqri_server_create")
         self._h = h

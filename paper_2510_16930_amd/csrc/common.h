@@ -129,6 +129,7 @@ struct Layout {
   size_t ybuf_floats;    // slice-row buffer
   size_t ycarry_floats;  // its split-slice partials
   size_t gpart_floats;   // core partials
+  size_t fpart_doubles;  // per-block partial sums of ||G||^2 of the core reduction (one per 16 entries)
 };
 constexpr int kCoreChunk = 64;  // rows per partial of the core product U^(c)T Y (core-mode pass)
 constexpr int kYChunks = 1024;  // most partials of the core product from stored rows
@@ -224,5 +225,11 @@ inline int other_modes(int N, int mode, int* out) {
 }
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// y_i as a matrix whose rows are the first few other modes and whose columns
+// are the rest (C order, so row-major in this matrix): the segment passes take
+// the last other mode as the columns; four other modes (order 5) are split
+// two and two, so both halves of the Kronecker product stay short.
+inline int yi_row_modes(int nm1) { return nm1 >= 4 ? nm1 - 2 : nm1 - 1; }
 
 }  // namespace hoqri

@@ -52,8 +52,8 @@ struct PrepArgs {
   const float* G;
   float* gtop;
   int32_t B, CB, KN2, krow, kcol, Kn, mode, N, nm1;
-  int32_t om[3];          // other modes ascending
-  int32_t Ko[3];          // their ranks
+  int32_t om[kMaxOrder - 1];  // other modes ascending
+  int32_t Ko[kMaxOrder - 1];  // their ranks
   int64_t gstride[kMaxOrder];  // C-order strides of G
   int32_t nblk;           // blocks of this launch (grid-stride loop)
   int32_t wide16;         // bfloat16 operand of the one-wave 16-bit passes: 1 c-tile layout, 2 2x2-block layout
@@ -73,7 +73,7 @@ struct FixArgs {
 struct CoreRedArgs {
   const float* gpart;
   int32_t groups, B, CB, KN2, krow, kcol, Kc, mode, nm1;
-  int32_t om[3], Ko[3];
+  int32_t om[kMaxOrder - 1], Ko[kMaxOrder - 1];
   int64_t gstride[kMaxOrder];
   float* G;
   double* fpart;
@@ -107,6 +107,7 @@ struct RowsAArgs {
   const float* gtop;
   int32_t R, W, B, KN2, Kn;
   int32_t yb16;    // 1: the rows are bfloat16
+  const int32_t* out_map;  // null: A rows by label; else label r goes to row out_map[r]
   int64_t groups;  // 16-row groups over the R + 2W rows
   float* A;
   float* carry;

@@ -364,18 +364,20 @@ hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, in
 // partial size (floats) of the core pass on mode n; see segpass_f32.hip.
 // Stage-two operand and core-partial sizes of mode n's segment pass (zero when
 // the shape is beyond the passes: then mode n takes the generic kernels).
+// Stage-two operand (any mode: the segment passes and the split-Kronecker
+// pass's product from stored rows) and core-pass partials (segment passes).
 static void pass_sizes(int32_t N, const int32_t* K, int n, size_t* gtop, size_t* gpart) {
   int om[kMaxOrder];
   int no = other_modes(N, n, om);
-  int64_t krow = 1;
-  for (int c = 0; c < no - 1; ++c) krow *= K[om[c]];
-  int64_t kcol = K[om[no - 1]];
+  const int nr = yi_row_modes(no);
+  int64_t krow = 1, kcol = 1;
+  for (int c = 0; c < no; ++c) (c < nr ? krow : kcol) *= K[om[c]];
   int64_t RB = (krow + 15) / 16, CB = (kcol + 15) / 16;
   int64_t B = RB * CB;
   int64_t KN2 = (K[n] + 15) / 16;
-  if (B > 8 || K[n] > 32 || no > 3) B = 0;
-  *gtop = (size_t)(B * KN2 * 4096);
-  *gpart = (size_t)(B * 256 * 16 * KN2);
+  const bool seg = B <= 8 && K[n] <= 32 && no <= 3;
+  *gtop = K[n] <= 32 ? (size_t)(B * KN2 * 4096) : 0;
+  *gpart = seg ? (size_t)(B * 256 * 16 * KN2) : 0;
 }
 
 // Work ranges of a pass: about 3072 nonzeros each on large tensors; smaller
@@ -516,19 +518,29 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   }
   L->yfuse = 1;
   {
-    size_t yrows = 0, yrow = 0, ygp = 0;
+    // every mode's pass stores its slice rows: the segment passes (at most 8
+    // tiles of y_i, split slices leave partials) or the split-Kronecker pass
+    // (whole slices), as long as the largest mode's rows stay within
+    // max(4 x one mode's nonzero stream, 1 GiB)
+    size_t yrows = 0, yrow = 0, ygp = 0, ybig = 0;
     for (int n = 0; n < N; ++n) {
       int om[kMaxOrder];
       const int no = other_modes(N, n, om);
-      int64_t krow = 1;
-      for (int q = 0; q < no - 1; ++q) krow *= K[om[q]];
-      const int64_t Bn = ((krow + 15) / 16) * ((K[om[no - 1]] + 15) / 16);
-      if (Bn > 8 || K[n] > 32 || no > 3) L->yfuse = 0;
+      const int nr = yi_row_modes(no);
+      int64_t krow = 1, kcol = 1;
+      for (int q = 0; q < no; ++q) (q < nr ? krow : kcol) *= K[om[q]];
+      const int64_t Bn = ((krow + 15) / 16) * ((kcol + 15) / 16);
+      if (K[n] > 32) L->yfuse = 0;
+      const bool seg = Bn <= 8 && no <= 3;
       const size_t rows = (size_t)(dims[n] < nnz ? dims[n] : nnz);
+      const size_t chunks = seg ? (size_t)kYChunks
+                                : std::min<size_t>(kYChunks, (rows + kCoreChunk - 1) / kCoreChunk);
       yrows = std::max(yrows, rows);
       yrow = std::max(yrow, (size_t)Bn * 256);
-      ygp = std::max(ygp, (size_t)kYChunks * Bn * 16 * ((K[n] + 15) / 16) * 256);
+      ybig = std::max(ybig, rows * (size_t)Bn * 256 * 4);
+      ygp = std::max(ygp, chunks * Bn * 16 * ((K[n] + 15) / 16) * 256);
     }
+    if (ybig > std::max<size_t>((size_t)4 * (size_t)nnz * 4 * N, (size_t)1 << 30)) L->yfuse = 0;
     if (L->yfuse) {
       ybuf_f = std::max(ybuf_f, yrows * yrow);
       ycarry_f = std::max(ycarry_f, (size_t)std::max<int32_t>(rmax, L->core_w) * 2 * yrow);
@@ -538,6 +550,21 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   L->ybuf_floats = ybuf_f;
   L->ycarry_floats = ycarry_f;
   L->gpart_floats = gpart_f;
+  // the core reduction writes one float64 partial per 16 entries of G_(n)'s
+  // padded tile layout: B_n 16 ceil(K_n/16) 256 / 16 for the mode reduced
+  {
+    size_t fp = 4096;
+    for (int n = 0; n < N; ++n) {
+      int om[kMaxOrder];
+      const int no = other_modes(N, n, om);
+      const int nr = yi_row_modes(no);
+      int64_t krow = 1, kcol = 1;
+      for (int q = 0; q < no; ++q) (q < nr ? krow : kcol) *= K[om[q]];
+      const size_t Bn = (size_t)(((krow + 15) / 16) * ((kcol + 15) / 16));
+      fp = std::max(fp, Bn * (size_t)((K[n] + 15) / 16) * 256);
+    }
+    L->fpart_doubles = fp;
+  }
   int64_t IKsum = 0;
   for (int n = 0; n < N; ++n) IKsum += dims[n] * K[n];
   Carver r{nullptr, 0};
@@ -546,7 +573,7 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   r.take<float>(IKmax);                 // A
   r.take<float>(PK);                    // G
   r.take<float>(gpart_f);               // core partials
-  r.take<double>(4096);                 // fpart
+  r.take<double>(L->fpart_doubles);     // fpart
   r.take<float>(gtop_max);              // stage-two operand
   r.take<float>((size_t)rmax * 2 * 32); // carries
   r.take<int32_t>((size_t)rmax * 4);    // range metadata
@@ -779,7 +806,7 @@ static void carve_scratch(hoqri_plan* p, const Layout& L) {
   p->sc.A = r.take<float>(IKmax);
   p->sc.G = r.take<float>(PK);
   p->sc.gpart = r.take<float>(L.gpart_floats);
-  p->sc.fpart = r.take<double>(4096);
+  p->sc.fpart = r.take<double>(L.fpart_doubles);
   p->sc.gtop = r.take<float>(gtop_max);
   p->sc.carry = r.take<float>((size_t)rmax * 2 * 32);
   p->sc.meta = r.take<int32_t>((size_t)rmax * 4);

@@ -301,8 +301,11 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     return HOQRI_ERR_ARG;
   int op = 0;
   HOQRI_TRY(check_prec(opts->prec, &op));
+  // modes beyond the segment passes: float32, and bfloat16 where the split-Kronecker pass stores rows
   for (int n = 0; n < p->N; ++n)
-    if (!segpass_supported(p, n) && (op != OP_FP32 || !generic_supported(p))) return HOQRI_ERR_UNSUPPORTED;
+    if (!segpass_supported(p, n) &&
+        (!generic_supported(p) || !(op == OP_FP32 || (op == OP_BF16 && p->yfuse))))
+      return HOQRI_ERR_UNSUPPORTED;
   if (opts->method != HOQRI_METHOD_HOQRI && opts->method != HOQRI_METHOD_HOOI) return HOQRI_ERR_ARG;
   if (opts->inner_iters < 0 || opts->inner_iters > 1000) return HOQRI_ERR_ARG;
   if (opts->stop_rule != HOQRI_STOP_REL_F && opts->stop_rule != HOQRI_STOP_ERR_CHANGE) return HOQRI_ERR_ARG;

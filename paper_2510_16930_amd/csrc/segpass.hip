@@ -675,7 +675,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
         for (int h = 0; h < 2; ++h) xa[h][t] = xq[t] * f16bits_to_f32<P_BF16>(C.ga[h][t]);
       }
     }
-    load_idx(blk + 3, C);
+    load_idx(blk + 4, C);
     gather(N2);
     const int32_t eb = blk * 16;
     auto product = [&](float (*av)[4]) {
@@ -717,23 +717,30 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
     }
   };
 
-  Set S0, S1, S2;
-  // prologue in the loop's own issue order (the record of b+2 ahead of the
-  // rows of b+1), held by scheduling barriers: the wait at the loop head then
-  // covers only the loads the body needs instead of every load in flight
+  // four register sets rotated by renaming: while block b is multiplied, the
+  // rows of b+1..b+3 and the record of b+4 are in flight. The prologue issues
+  // in the loop's own order (a record ahead of the previous block's rows), held
+  // by scheduling barriers, so the wait at the loop head covers only the loads
+  // the body needs instead of every load in flight
+  Set S0, S1, S2, S3;
   load_idx(b0, S0);
   load_idx(b0 + 1, S1);
   gather(S0);
   load_idx(b0 + 2, S2);
   __builtin_amdgcn_sched_barrier(0);
   gather(S1);
+  load_idx(b0 + 3, S3);
   __builtin_amdgcn_sched_barrier(0);
-  for (int32_t ib = 0; ib < nblk; ib += 3) {
-    step(b0 + ib, S0, S2);
+  gather(S2);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int32_t ib = 0; ib < nblk; ib += 4) {
+    step(b0 + ib, S0, S3);
     if (done || ib + 1 >= nblk) break;
     step(b0 + ib + 1, S1, S0);
     if (done || ib + 2 >= nblk) break;
     step(b0 + ib + 2, S2, S1);
+    if (done || ib + 3 >= nblk) break;
+    step(b0 + ib + 3, S3, S2);
     if (done) break;
   }
 }
@@ -1667,7 +1674,7 @@ __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
     if (x < R) {
       *src = p.ybuf;
       *soff = (size_t)x * rowf;
-      *dst = p.A + (size_t)x * ld;
+      *dst = p.A + (size_t)(p.out_map ? p.out_map[x] : x) * ld;
       return true;
     }
     if (x >= R + NP) return false;
@@ -2002,6 +2009,105 @@ __global__ __launch_bounds__(256) void k_core_generic(GenArgs a) {
   for (int k = 0; k < a.Kn; ++k) a.Gout[goff + k * a.gstride_n] = acc[k];
 }
 
+// Split-Kronecker pass for modes beyond the segment passes (order 5, or more
+// than 8 16x16 tiles of y_i): y_i as a matrix whose rows are the Kronecker
+// product of the first other modes and whose columns that of the rest
+// (yi_row_modes), cut into 16x16 tiles. One workgroup per nonempty slice;
+// its 8 waves take the tiles in turn, and a tile is accumulated over the
+// slice's nonzeros on the matrix cores, 4 nonzeros per v_mfma_f32_16x16x4f32:
+// lane (g, q) supplies x_e times the row-mode factor entries of row 16 rb + q
+// (A operand, nonzero 4s + g) and the column-mode factor entries of column
+// 16 cb + q (B operand), so each Kronecker half is formed once per lane and
+// nonzero instead of the whole row. BF16 form: 16 nonzeros per
+// v_mfma_f32_16x16x16bf16_1k, lane group g forming nonzeros 4g .. 4g + 3 of
+// the step, both operands rounded to bfloat16 (nearest even) from their
+// float32 products, float32 accumulation. The finished tile is stored (in
+// float32) as tile b of the slice's row of Y_(n) (entry c*16 + r, the segment
+// passes' layout), from which A^(n) and the core follow as for stored slice
+// rows.
+struct GenRowsArgs {
+  const int32_t* rec;
+  const int32_t* seg_off;
+  const int32_t* seg_row;
+  int32_t R, N, nm1, nr;            // other modes, the first nr of which index the rows of y_i
+  const float* U[kMaxOrder - 1];    // other modes ascending (label order)
+  int32_t Ko[kMaxOrder - 1];
+  int32_t krow, kcol, CB, B;
+  float* ybuf;                      // [label][B * 256]
+};
+constexpr int kGenWaves = 8;
+template <bool BF16>
+__global__ __launch_bounds__(64 * kGenWaves) void k_gen_rows(GenRowsArgs a) {
+  const int32_t s = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, q = lane & 15;
+  const int32_t e_lo = a.seg_off[s], e_hi = a.seg_off[s + 1];
+  float* yr = a.ybuf + (size_t)a.seg_row[s] * a.B * 256;
+  const int N = a.N;
+  for (int b = wv; b < a.B; b += kGenWaves) {
+    const int rb = b / a.CB, cb = b - rb * a.CB;
+    const int r = 16 * rb + q, c = 16 * cb + q;
+    const bool rok = r < a.krow, cok = c < a.kcol;
+    // this lane's entry of each other mode (padded rows / columns read entry 0)
+    int ko[kMaxOrder - 1] = {0, 0, 0, 0};
+    {
+      int rem = rok ? r : 0;
+      for (int m = a.nr - 1; m >= 0; --m) {
+        ko[m] = rem % a.Ko[m];
+        rem /= a.Ko[m];
+      }
+      rem = cok ? c : 0;
+      for (int m = a.nm1 - 1; m >= a.nr; --m) {
+        ko[m] = rem % a.Ko[m];
+        rem /= a.Ko[m];
+      }
+    }
+    // the two Kronecker halves of nonzero e for this lane (0 past the slice)
+    auto halves = [&](int32_t e, float& av, float& bv) {
+      av = 0.f;
+      bv = 0.f;
+      if (e < e_hi) {
+        // record of nonzero e = 16 blk + 4 t + g': the offsets label * K_m and the value
+        const int32_t* rp = a.rec + (size_t)(e >> 4) * 16 * N + (e & 3) * 4 * N;
+        const int t = (e & 15) >> 2;
+        float wa = __int_as_float(rp[4 * (N - 1) + t]);
+        float wb = 1.f;
+#pragma unroll
+        for (int m = 0; m < kMaxOrder - 1; ++m) {
+          if (m >= a.nm1) break;
+          const float u = a.U[m][(int64_t)rp[4 * m + t] + ko[m]];
+          if (m < a.nr) wa *= u;
+          else wb *= u;
+        }
+        av = rok ? wa : 0.f;
+        bv = cok ? wb : 0.f;
+      }
+    };
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (BF16) {
+#pragma unroll 2
+      for (int32_t e0 = e_lo; e0 < e_hi; e0 += 16) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) halves(e0 + 4 * g + t, av[t], bv[t]);
+        const b4 ab = {(__bf16)av[0], (__bf16)av[1], (__bf16)av[2], (__bf16)av[3]};
+        const b4 bb = {(__bf16)bv[0], (__bf16)bv[1], (__bf16)bv[2], (__bf16)bv[3]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, ab), __builtin_bit_cast(s4, bb), acc,
+                                                        0, 0, 0);
+      }
+    } else {
+#pragma unroll 4
+      for (int32_t e0 = e_lo; e0 < e_hi; e0 += 4) {
+        float av, bv;
+        halves(e0 + g, av, bv);
+        acc = mfma4(av, bv, acc);
+      }
+    }
+    // lane (g, q) holds rows 4g + v of column q of the tile: entry q*16 + 4g + v
+    *reinterpret_cast<f4*>(yr + (size_t)b * 256 + q * 16 + 4 * g) = acc;
+  }
+}
+
 // ||G||^2 in float64 by one workgroup (fixed order)
 __global__ __launch_bounds__(256) void k_sumsq(const float* G, int64_t n, double* out) {
   __shared__ double sh[256];
@@ -2027,9 +2133,10 @@ PassGeom geom(const hoqri_plan* p, int mode) {
   PassGeom g{};
   g.nm1 = other_modes(p->N, mode, g.om);
   g.krow = 1;
+  g.kcol = 1;
   for (int c = 0; c < g.nm1; ++c) g.Ko[c] = p->K[g.om[c]];
-  for (int c = 0; c < g.nm1 - 1; ++c) g.krow *= g.Ko[c];
-  g.kcol = g.Ko[g.nm1 - 1];
+  const int nr = yi_row_modes(g.nm1);
+  for (int c = 0; c < g.nm1; ++c) (c < nr ? g.krow : g.kcol) *= g.Ko[c];
   g.RB = (g.krow + 15) / 16;
   g.CB = (g.kcol + 15) / 16;
   g.B = g.RB * g.CB;
@@ -2298,7 +2405,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   pa.mode = mode;
   pa.N = p->N;
   pa.nm1 = g.nm1;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kMaxOrder - 1; ++c) {
     pa.om[c] = c < g.nm1 ? g.om[c] : 0;
     pa.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
   }
@@ -2404,7 +2511,7 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
     r.Kc = p->K[mode];
     r.mode = mode;
     r.nm1 = g.nm1;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kMaxOrder - 1; ++c) {
       r.om[c] = c < g.nm1 ? g.om[c] : 0;
       r.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
     }
@@ -2450,7 +2557,7 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
   r.Kc = p->K[mode];
   r.mode = mode;
   r.nm1 = g.nm1;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kMaxOrder - 1; ++c) {
     r.om[c] = c < g.nm1 ? g.om[c] : 0;
     r.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
   }
@@ -2499,11 +2606,109 @@ bool generic_supported(const hoqri_plan* p) {
   return true;
 }
 
+// The split-Kronecker pass of mode `mode` (float32 or bfloat16 operands, from
+// the float32 factors): the rows of Y_(mode) for every nonempty slice into the
+// plan's slice-row buffer.
+hoqri_status launch_gen_rows(hoqri_plan* p, int mode, int prec, hipStream_t s) {
+  const PassGeom g = geom(p, mode);
+  const ModeData& md = p->md[mode];
+  GenRowsArgs a{};
+  a.rec = md.rec;
+  a.seg_off = md.seg_off;
+  a.seg_row = md.seg_row;
+  a.R = (int32_t)md.R;
+  a.N = p->N;
+  a.nm1 = g.nm1;
+  a.nr = yi_row_modes(g.nm1);
+  for (int c = 0; c < g.nm1; ++c) {
+    a.U[c] = p->sc.Up[g.om[c]];
+    a.Ko[c] = g.Ko[c];
+  }
+  a.krow = g.krow;
+  a.kcol = g.kcol;
+  a.CB = g.CB;
+  a.B = g.B;
+  a.ybuf = p->sc.ybuf;
+  if (a.R > 0) {
+    if (prec == OP_BF16) hipLaunchKernelGGL(k_gen_rows<true>, dim3((unsigned)a.R), dim3(64 * kGenWaves), 0, s, a);
+    else hipLaunchKernelGGL(k_gen_rows<false>, dim3((unsigned)a.R), dim3(64 * kGenWaves), 0, s, a);
+  }
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
+// Stage-two operand (float32 order) of a mode that takes the split-Kronecker pass.
+PrepArgs gen_prep(const hoqri_plan* p, int mode, const float* G) {
+  const PassGeom g = geom(p, mode);
+  PrepArgs pa{};
+  pa.wide16 = 0;
+  pa.pair = 0;
+  pa.G = G;
+  pa.gtop = p->sc.gtop;
+  pa.B = g.B;
+  pa.CB = g.CB;
+  pa.KN2 = (p->K[mode] + 15) / 16;
+  pa.krow = g.krow;
+  pa.kcol = g.kcol;
+  pa.Kn = p->K[mode];
+  pa.mode = mode;
+  pa.N = p->N;
+  pa.nm1 = g.nm1;
+  for (int c = 0; c < kMaxOrder - 1; ++c) {
+    pa.om[c] = c < g.nm1 ? g.om[c] : 0;
+    pa.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
+  }
+  g_strides(p, pa.gstride);
+  const int64_t total = (int64_t)g.B * pa.KN2 * 4096;
+  pa.nblk = (int)((total + 255) / 256);
+  return pa;
+}
+
+// A^(mode) = Y_(mode) G_(mode)^T from the stored rows of a mode with no split
+// slices (whole slices per workgroup), rows by label or through out_map.
+hoqri_status gen_rows_a(hoqri_plan* p, int mode, const float* G, float* A, const int32_t* out_map, hipStream_t s) {
+  const PrepArgs pa = gen_prep(p, mode, G);
+  RowsAArgs r{};
+  r.ybuf = p->sc.ybuf;
+  r.ycarry = p->sc.ycarry;
+  r.ymeta = p->sc.meta;
+  r.gtop = p->sc.gtop;
+  r.R = (int32_t)p->md[mode].R;
+  r.W = 0;
+  r.B = pa.B;
+  r.KN2 = pa.KN2;
+  r.Kn = p->K[mode];
+  r.yb16 = 0;
+  r.out_map = out_map;
+  r.groups = ((int64_t)r.R + 15) / 16;
+  r.A = A;
+  r.carry = p->sc.carry;
+  hipLaunchKernelGGL(k_prep_gtop, dim3(pa.nblk), dim3(256), 0, s, pa);
+  if (r.groups > 0) hipLaunchKernelGGL(k_rows_a, dim3((unsigned)((r.groups + 3) / 4)), dim3(256), 0, s, r);
+  const ModeData& md = p->md[mode];
+  if (md.E > 0) {
+    int64_t tot = md.E * p->K[mode];
+    int grid = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid), dim3(256), 0, s, out_map ? md.empty_row : (const int32_t*)nullptr,
+                       md.R, md.E, p->K[mode], A);
+  }
+  HOQRI_HIP_TRY(hipGetLastError());
+  return HOQRI_OK;
+}
+
 hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const float* G, float* A,
                            const int32_t* out_map, hipStream_t s, bool rows) {
   if (!segpass_supported(p, mode)) {
-    // generic kernel: float32 operands only, no stored rows
-    if (rows || op.prec != OP_FP32 || !generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
+    if (!generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
+    if (p->yfuse && (op.prec == OP_FP32 || op.prec == OP_BF16)) {
+      // split-Kronecker pass: the slice rows of Y_(mode), then A from them
+      TimerScope ts(p, HOQRI_KERNEL_TTMCTC, s);
+      HOQRI_TRY(launch_gen_rows(p, mode, op.prec, s));
+      return gen_rows_a(p, mode, G, A, out_map, s);
+    }
+    if (op.prec != OP_FP32) return HOQRI_ERR_UNSUPPORTED;
+    // generic scalar kernel (slice rows too large to store): no stored rows
+    if (rows) return HOQRI_ERR_UNSUPPORTED;
     GenArgs a = gen_args(p, mode);
     a.G = G;
     a.A = A;
@@ -2550,7 +2755,22 @@ hoqri_status launch_ttmctc(hoqri_plan* p, int mode, const Operands& op, const fl
 
 hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_out, hipStream_t s) {
   if (!segpass_supported(p, p->core_mode)) {
-    if (op.prec != OP_FP32 || !generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
+    if (!generic_supported(p)) return HOQRI_ERR_UNSUPPORTED;
+    if (p->yfuse && (op.prec == OP_FP32 || op.prec == OP_BF16)) {
+      // split-Kronecker pass on the core mode, then G_(c) = U^(c)T Y_(c)
+      YCoreJob job;
+      {
+        TimerScope ts(p, HOQRI_KERNEL_CORE, s);
+        HOQRI_TRY(launch_gen_rows(p, p->core_mode, op.prec, s));
+      }
+      HOQRI_TRY(prepare_ycore(p, p->core_mode, G, f_out, &job, false, false));
+      launch_core_gemm(job.gemm, job.gemm_blocks, s);
+      hipLaunchKernelGGL(k_core_reduce, dim3(job.red_blocks), dim3(kRedThreads), 0, s, job.red);
+      hipLaunchKernelGGL(k_sum_f, dim3(1), dim3(256), 0, s, job.sum);
+      HOQRI_HIP_TRY(hipGetLastError());
+      return HOQRI_OK;
+    }
+    if (op.prec != OP_FP32) return HOQRI_ERR_UNSUPPORTED;
     GenArgs a = gen_args(p, p->core_mode);
     a.Uc = op.U32[p->core_mode];
     a.Gout = G;
@@ -2585,12 +2805,13 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
 // slices, then the split-slice partials) are cut into at most kYChunks chunks
 // of equal length; partials are reduced in chunk order.
 hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split, bool yb16) {
-  if (!p->yfuse || !segpass_supported(p, mode)) return HOQRI_ERR_UNSUPPORTED;
+  if (!p->yfuse) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
   const int KN2 = (p->K[mode] + 15) / 16;
   *job = YCoreJob{};
   int64_t W = p->md[mode].ranges;
   if (W > p->nnz) W = p->nnz;
+  if (!segpass_supported(p, mode)) W = 0;  // the split-Kronecker pass keeps slices whole
   CoreGemmArgs& m = job->gemm;
   m.ybuf = p->sc.ybuf;
   m.ycarry = p->sc.ycarry;
@@ -2621,7 +2842,7 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   r.Kc = p->K[mode];
   r.mode = mode;
   r.nm1 = g.nm1;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kMaxOrder - 1; ++c) {
     r.om[c] = c < g.nm1 ? g.om[c] : 0;
     r.Ko[c] = c < g.nm1 ? g.Ko[c] : 1;
   }
@@ -2649,6 +2870,11 @@ hoqri_status launch_ycore(hoqri_plan* p, int mode, float* G, double* f_out, hipS
 }
 
 hoqri_status launch_rows_a(hoqri_plan* p, int mode, const float* G, float* A, hipStream_t s, bool yb16) {
+  if (!segpass_supported(p, mode)) {
+    if (!p->yfuse) return HOQRI_ERR_UNSUPPORTED;
+    TimerScope ts(p, HOQRI_KERNEL_CORE, s);
+    return gen_rows_a(p, mode, G, A, nullptr, s);
+  }
   TtmJob job;  // for the stage-two operand and the fix-up of this mode's ranges
   const Operands op{OP_FP32, p->sc.Up, p->sc.Uh};
   HOQRI_TRY(prepare_ttm(p, mode, op, G, A, nullptr, &job, true));

@@ -145,6 +145,11 @@ struct hoqri_server {
   std::vector<hoqri::Active> active;  // engine thread only
   std::vector<int> free_slots;        // engine thread only
   int64_t step_no = 0;
+  // step graph (use_graphs): the executable graph of the last step's launches,
+  // updated in place when the next step's launches have the same topology
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;  // private stream the step is captured on (the caller's may be the null stream)
+  int64_t graph_instantiations = 0, graph_updates = 0;
   // shared with the builder thread (guarded by mu)
   std::mutex mu;
   std::condition_variable cv_build;   // builder: work or memory became available
@@ -164,6 +169,49 @@ using namespace hoqri;
 namespace {
 
 size_t stage_bytes(int slots) { return align_up(65536 + (size_t)slots * 4096); }
+
+// Captures the launches of a step into a graph (on the server's private
+// stream: capture records work without running it, and the caller's stream may
+// be the null stream, which cannot be captured) and launches it on `s` as one
+// launch: the executable graph of the previous step is updated in place when
+// the topology (the sequence of kernels and copies) is unchanged, else a new
+// one is instantiated. The captured copies read the pinned staging tables at
+// replay time, which hold this step's tables.
+template <class F>
+hoqri_status graph_step(hoqri_server* S, hipStream_t s, F&& launches) {
+  HOQRI_HIP_TRY(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
+  const hoqri_status ls = launches(S->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(S->cap, &g);
+  if (ls != HOQRI_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return ls != HOQRI_OK ? ls : HOQRI_ERR_HIP;
+  }
+  bool updated = false;
+  if (S->gexec) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    updated = hipGraphExecUpdate(S->gexec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+    if (!updated) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(S->gexec);
+      S->gexec = nullptr;
+    }
+  }
+  if (!updated) {
+    if (hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      S->gexec = nullptr;
+      (void)hipGraphDestroy(g);
+      return HOQRI_ERR_HIP;
+    }
+    ++S->graph_instantiations;
+  } else {
+    ++S->graph_updates;
+  }
+  (void)hipGraphDestroy(g);
+  HOQRI_HIP_TRY(hipGraphLaunch(S->gexec, s));
+  return HOQRI_OK;
+}
 
 hoqri_result make_result(const Pending& q, hoqri_status st) {
   hoqri_result r{};
@@ -378,9 +426,18 @@ extern "C" hoqri_status hoqri_server_create(const hoqri_server_opts* opts, hoqri
     return HOQRI_ERR_NOMEM;
   }
   for (int i = slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+  // graph capture runs on a private stream of default priority
+  if (opts->use_graphs && hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking) != hipSuccess) {
+    S->cap = nullptr;
+    (void)hipHostFree(S->pinned);
+    delete S->arena;
+    delete S;
+    return HOQRI_ERR_HIP;
+  }
   try {
     S->builder = std::thread(builder_loop, S);
   } catch (...) {
+    if (S->cap) (void)hipStreamDestroy(S->cap);
     (void)hipHostFree(S->pinned);
     delete S->arena;
     delete S;
@@ -487,18 +544,25 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
                                S->o.keep_on_breakdown ? S->d_skip + a.slot : nullptr, p->dims[a.n]));
         HOQRI_TRY(prepare_ycore(p, a.n, p->sc.G, S->d_f + a.slot, &yj[k]));
       }
-      HOQRI_TRY((run_groups<TtmJob, TtmGroup>(tj, st, s, stage_ttm_group, launch_ttm_group)));
-      std::vector<const OrthJob*> op(oj.size());
-      for (size_t k = 0; k < oj.size(); ++k) op[k] = &oj[k];
-      OrthGroup og;
-      if (!stage_orth_group(op.data(), (int)op.size(), st, &og)) return HOQRI_ERR_NOMEM;
-      std::vector<const YCoreJob*> yp(yj.size());
-      for (size_t k = 0; k < yj.size(); ++k) yp[k] = &yj[k];
-      YCoreGroup yg;
-      if (!stage_ycore_group(yp.data(), (int)yp.size(), st, &yg)) return HOQRI_ERR_NOMEM;
-      HOQRI_HIP_TRY(st.upload(s));
-      HOQRI_TRY(launch_orth_group(og, s));
-      HOQRI_TRY(launch_ycore_group(yg, s));
+      // the launches of this step: table uploads from pinned memory and one
+      // batched launch per kernel kind (no memset nodes)
+      auto launches = [&](hipStream_t ls) -> hoqri_status {
+        HOQRI_TRY((run_groups<TtmJob, TtmGroup>(tj, st, ls, stage_ttm_group, launch_ttm_group)));
+        std::vector<const OrthJob*> op(oj.size());
+        for (size_t k = 0; k < oj.size(); ++k) op[k] = &oj[k];
+        OrthGroup og;
+        if (!stage_orth_group(op.data(), (int)op.size(), st, &og)) return HOQRI_ERR_NOMEM;
+        std::vector<const YCoreJob*> yp(yj.size());
+        for (size_t k = 0; k < yj.size(); ++k) yp[k] = &yj[k];
+        YCoreGroup yg;
+        if (!stage_ycore_group(yp.data(), (int)yp.size(), st, &yg)) return HOQRI_ERR_NOMEM;
+        HOQRI_HIP_TRY(st.upload(ls));
+        HOQRI_TRY(launch_orth_group(og, ls));
+        HOQRI_TRY(launch_ycore_group(yg, ls));
+        return HOQRI_OK;
+      };
+      if (S->o.use_graphs) HOQRI_TRY(graph_step(S, s, launches));
+      else HOQRI_TRY(launches(s));
       for (int i : going) {
         Active& a = act[i];
         if (++a.n == a.plan->N) {
@@ -586,6 +650,8 @@ extern "C" void hoqri_server_destroy(hoqri_server* S) {
     if (b.plan) hoqri_plan_destroy(b.plan);
   for (Active& a : S->active)
     if (a.plan) hoqri_plan_destroy(a.plan);
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->cap) (void)hipStreamDestroy(S->cap);
   if (S->pinned) (void)hipHostFree(S->pinned);
   delete S->arena;
   delete S;

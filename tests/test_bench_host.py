@@ -48,6 +48,7 @@ def test_kernel_names_follow_the_library_choice():
     assert bench.ttm_kernel_name((10,) * 4, (10,) * 4, "fp32").startswith("k_ttm4c<fp32>")
     assert bench.ttm_kernel_name((10,) * 4, (20, 10, 10, 10), "fp16").startswith("k_ttm<fp16>")
     assert bench.ttm_kernel_name((10, 10, 10), (16, 16, 16), "bf16").startswith("k_ttm<bf16>")
+    assert bench.ttm_kernel_name((80,) * 5, (10,) * 5, "fp32").startswith("k_gen_rows")
 
 
 def test_traffic_reader(tmp_path, monkeypatch):

@@ -44,8 +44,9 @@ def alone(q, max_sweeps, tol):
     return Us, G, st
 
 
-def serve(reqs, arena_bytes, max_slots, max_sweeps, tol, waves=1):
-    srv = H.Server(arena_bytes, max_slots=max_slots, max_sweeps=max_sweeps, tol=tol, report_orth_err=True)
+def serve(reqs, arena_bytes, max_slots, max_sweeps, tol, waves=1, use_graphs=False):
+    srv = H.Server(arena_bytes, max_slots=max_slots, max_sweeps=max_sweeps, tol=tol, report_orth_err=True,
+                   use_graphs=use_graphs)
     outs = {}
     for i, q in enumerate(reqs):
         outs[i] = ([u.clone() for u in q["U0"]], torch.empty(q["ranks"], dtype=torch.float32, device=DEV))
@@ -72,12 +73,17 @@ def serve(reqs, arena_bytes, max_slots, max_sweeps, tol, waves=1):
     return outs, results, max_active
 
 
-def test_batched_results_equal_alone_bitwise():
+@pytest.mark.parametrize("use_graphs", [False, True])
+def test_batched_results_equal_alone_bitwise(use_graphs):
+    # with use_graphs every step's launches are one replayed graph, updated in
+    # place from step to step (eager work and synchronisations in between):
+    # each replay must give the eager results bitwise
     reqs = make_requests(10, seed=3, orders=(3, 3, 3, 4, 2))
     sizes = [H.hoqri_plan_workspace_size(len(q["dims"]), q["dims"], q["ranks"], q["vals"].numel()) for q in reqs]
     arena = sum(sorted(sizes)[-3:]) + (8 << 20)  # about three plans at a time
-    print(f"[serve] 10 requests, arena {arena >> 20} MiB", flush=True)
-    outs, results, max_active = serve(reqs, arena, max_slots=4, max_sweeps=6, tol=1e-6, waves=3)
+    print(f"[serve] 10 requests, arena {arena >> 20} MiB, graphs {use_graphs}", flush=True)
+    outs, results, max_active = serve(reqs, arena, max_slots=4, max_sweeps=6, tol=1e-6, waves=3,
+                                      use_graphs=use_graphs)
     assert max_active >= 2  # requests really overlapped
     for i, q in enumerate(reqs):
         r = results[i]
