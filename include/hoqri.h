@@ -134,7 +134,7 @@ hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A, float* d_U
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): the same kernels and results (bitwise those of
  * hoqri_orth), with the scratch taken from a fixed device array of
- * hoqri_orth_noalloc_scratch_bytes() bytes (about 32 MiB) per GPU, set up on
+ * hoqri_orth_noalloc_scratch_bytes() bytes (about 8 MiB) per GPU, set up on
  * the first call on each device and held until the process ends. Allocates
  * nothing. Arguments and errors as hoqri_orth; HOQRI_ERR_UNSUPPORTED if the
  * shape needed more scratch than the array holds (no valid shape does).

@@ -6,6 +6,11 @@ paper_2510_16930_amd/libhoqri.so. Packed float32 instructions are disabled
 accumulators are kept in ordinary vector registers (-amdgpu-mfma-vgpr-form):
 in the segment passes, whose accumulators are reset at slice ends, the
 accumulator-register form copies every accumulator out and back in each step.
+The segment passes are also compiled with regions of wave-uniform branches
+left unstructured (-structurizecfg-skip-uniform-regions): their block loops
+branch on wave-uniform slice bounds only, and structurizing those regions
+puts copies of the accumulators and of undefined scalar values on the path
+of every 16-nonzero block.
 """
 from __future__ import annotations
 
@@ -36,9 +41,13 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+# extra flags per translation unit
+FILE_FLAGS = {"segpass.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

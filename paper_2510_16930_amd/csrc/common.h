@@ -33,8 +33,9 @@ constexpr int kMaxSweeps = 4096;
 struct ModeData {
   // The nonzeros in mode-n sorted order as block records: for every block of
   // 16 nonzeros (e = 16b + 4t + g) and lane group g, N dwords-quads in turn:
-  // for each other mode m' (ascending, mode n skipped) the factor element
-  // offsets label(i_m) * K_m of nonzeros 4t+g (t = 0..3), then their values
+  // for each other mode m' (ascending, mode n skipped) the byte offsets
+  // 2 label(i_m) K_m of the nonzeros' factor rows in a 16-bit copy (4t+g,
+  // t = 0..3; a float32 row starts at twice that), then their values
   // (float32 bits). rec[b][g][a][t], 16 N dwords per block; padding is zero.
   int32_t* rec;
   int32_t* seg_row;    // [R]   mode-n index of each nonempty slice (ascending)
@@ -132,7 +133,15 @@ struct Layout {
   size_t fpart_doubles;  // per-block partial sums of ||G||^2 of the core reduction (one per 16 entries)
 };
 constexpr int kCoreChunk = 64;  // rows per partial of the core product U^(c)T Y (core-mode pass)
-constexpr int kYChunks = 1024;  // most partials of the core product from stored rows
+constexpr int kYChunks = 256;  // most partials of the core product from stored rows
+// Partials of the core product from stored rows for nv rows: one per 1024
+// rows at least, a multiple of 8 (the product's blocks are spread over the
+// eight XCDs by chunk), at most kYChunks.
+inline int64_t ycore_chunks(int64_t nv) {
+  int64_t c = (nv + 1023) / 1024;
+  c = (c + 7) / 8 * 8;
+  return c < kYChunks ? c : kYChunks;
+}
 
 hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz, Layout* L);
 hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, int64_t nnz);

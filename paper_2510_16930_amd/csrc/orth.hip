@@ -14,8 +14,12 @@
 // A Cholesky pivot <= 1e-13 * trace(W) (or not finite) in either step flags
 // breakdown: A is numerically rank deficient; U is then left untouched.
 //
+// Only the diagonal 16 x 16 blocks and the block above them are formed (the
+// factorisation reads nothing below the diagonal): three float64 products
+// per step instead of four, on matrix cores whose float64 rate is the
+// vector rate.
 // Memory traffic: two reads of A for the Gram matrices and one read + one
-// write for the final product; the K x K work runs in single workgroups.
+// write for the final product; the K x K work runs in single waves.
 #include "passes.h"
 
 #include <mutex>
@@ -26,17 +30,17 @@ namespace {
 
 constexpr int kT = 256;
 static_assert(kMaxRank == 32, "rank blocks are at most 32 wide");
-// Element loops of the Cholesky step run over (i, j) = (e >> sh, e & (2^sh - 1))
-// for e < K 2^sh, with 2^sh the power of two >= K (16 or 32): shifts, not
-// divisions by K.
-__device__ inline int rank_shift(int K) { return K <= 16 ? 4 : 5; }
 constexpr int kChunk = 32;    // rows staged per step
 constexpr double kBreakRel = 1e-13;
 
+// Gram blocks: one per 1024 rows, at most kGramBlocks (several per CU, each
+// streaming its rows; more, shorter blocks spend their time on start-up and
+// on writing their K x K partials)
+constexpr int kGramBlocks = 1024;
 int gram_blocks(int64_t rows) {
-  int64_t nb = (rows + 255) / 256;
+  int64_t nb = (rows + 1023) / 1024;
   if (nb < 1) nb = 1;
-  if (nb > 4096) nb = 4096;
+  if (nb > kGramBlocks) nb = kGramBlocks;
   return (int)nb;
 }
 
@@ -45,24 +49,30 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // Adds the 4 waves' Gram tiles in wave order and stores the block's partial:
 // tile (pb, qb) holds entry (16 pb + 4 v + gg, 16 qb + q) in D[pb][qb][v]
 // (the float64 16x16 result layout); part[e * nb + blk] for entry e = p*K + q.
+// Only tiles (0,0), (0,1) and (1,1) are formed (the block below the diagonal
+// blocks is zero), so LDS holds three tiles per wave.
 __device__ inline void gram_store(const d4 (&D)[2][2], const GramArgs& g, const int blk) {
-  __shared__ double red[kT / 64][kMaxRank * kMaxRank];
+  __shared__ double red[kT / 64][3][256];
   const int K = g.K;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int q = lane & 15, gg = lane >> 4;
 #pragma unroll
-  for (int pb = 0; pb < 2; ++pb)
-#pragma unroll
-    for (int qb = 0; qb < 2; ++qb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pr = 16 * pb + 4 * v + gg, pc = 16 * qb + q;
-        if (pr < K && pc < K) red[wv][pr * K + pc] = D[pb][qb][v];
-      }
+  for (int v = 0; v < 4; ++v) {
+    const int pos = (4 * v + gg) * 16 + q;
+    red[wv][0][pos] = D[0][0][v];
+    red[wv][1][pos] = D[0][1][v];
+    red[wv][2][pos] = D[1][1][v];
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < K * K; e += kT) {
-    double t = red[0][e];
-    for (int w = 1; w < kT / 64; ++w) t += red[w][e];
+    const int p = e / K, c = e - p * K;
+    const int pb = p >> 4, qb = c >> 4;
+    double t = 0.0;
+    if (pb <= qb) {
+      const int tile = pb + qb, pos = (p & 15) * 16 + (c & 15);
+      t = red[0][tile][pos];
+      for (int w = 1; w < kT / 64; ++w) t += red[w][tile][pos];
+    }
     g.part[(size_t)e * g.nb + blk] = t;
   }
 }
@@ -88,20 +98,25 @@ __device__ inline void gram_body(const GramArgs& g, const int blk) {
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb) D[pb][qb] = d4{0.0, 0.0, 0.0, 0.0};
   const bool two = K > 16;
-  // 8 steps of 4 rows per group: the group's loads go to clamped (valid)
-  // addresses and are all issued before its products; rows past r1 and
-  // columns past K are masked afterwards
+  // groups of 8 steps of 4 rows: loads go to clamped (valid) addresses, and
+  // the next group's loads are issued before a group's products; rows past r1
+  // and columns past K are masked afterwards
   constexpr int NS = 8;
+  constexpr int64_t kStride = 4 * NS * (kT / 64);
   const int q0 = q < K ? q : 0, q1 = 16 + q < K ? 16 + q : 0;
-  for (int64_t base = r0 + 4 * wv; base < r1; base += 4 * NS * (kT / 64)) {
-    float x0[NS], x1[NS];
+  float x0[NS], x1[NS], y0[NS], y1[NS];
+  auto fetch = [&](int64_t base, float* a0, float* a1) {
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
       const int64_t row = base + st * 4 * (kT / 64) + gg;
       const int64_t rr = row < r1 ? row : r0;
-      x0[st] = A[rr * K + q0];
-      x1[st] = A[rr * K + q1];  // (same line as x0; used only when K > 16)
+      a0[st] = A[rr * K + q0];
+      a1[st] = A[rr * K + q1];  // (same line as a0; used only when K > 16)
     }
+  };
+  if (r0 + 4 * wv < r1) fetch(r0 + 4 * wv, x0, x1);
+  for (int64_t base = r0 + 4 * wv; base < r1; base += kStride) {
+    fetch(base + kStride < r1 ? base + kStride : base, y0, y1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int st = 0; st < NS; ++st) {
@@ -111,9 +126,13 @@ __device__ inline void gram_body(const GramArgs& g, const int blk) {
       if (two) {
         const double a1 = (ok && 16 + q < K) ? (double)x1[st] : 0.0;
         D[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, D[0][1], 0, 0, 0);
-        D[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, D[1][0], 0, 0, 0);
         D[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, D[1][1], 0, 0, 0);
       }
+    }
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      x0[st] = y0[st];
+      x1[st] = y1[st];
     }
   }
   gram_store(D, g, blk);
@@ -154,14 +173,26 @@ __device__ inline void gramq_body(const GramArgs& g, const int blk) {
   for (int pb = 0; pb < 2; ++pb)
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb) W[pb][qb] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t base = r0 + 16 * wv; base < r1; base += 16 * (kT / 64)) {
+  // a tile's nr * K floats are contiguous in A; the next tile's are loaded
+  // into registers before this tile's products
+  float cur[8], nxt[8];
+  auto fetch = [&](int64_t base, float* x) {
     const int nr = (int)((r1 - base) < 16 ? (r1 - base) : 16);
-    // the tile's nr * K floats are contiguous in A
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int t = lane + 64 * i;
-      if (t < nr * K) tile[wv][t / K][t % K] = A[base * K + t];
+      x[i] = t < nr * K ? A[base * K + t] : 0.f;
     }
+  };
+  if (r0 + 16 * wv < r1) fetch(r0 + 16 * wv, cur);
+  for (int64_t base = r0 + 16 * wv; base < r1; base += 16 * (kT / 64)) {
+    const int nr = (int)((r1 - base) < 16 ? (r1 - base) : 16);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int t = lane + 64 * i;
+      if (t < nr * K) tile[wv][t / K][t % K] = cur[i];
+    }
+    if (base + 16 * (kT / 64) < r1) fetch(base + 16 * (kT / 64), nxt);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -179,7 +210,6 @@ __device__ inline void gramq_body(const GramArgs& g, const int blk) {
       W[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[0][r], D[0][r], W[0][0], 0, 0, 0);
       if (KT > 1) {
         W[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[0][r], D[1][r], W[0][1], 0, 0, 0);
-        W[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[1][r], D[0][r], W[1][0], 0, 0, 0);
         W[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[1][r], D[1][r], W[1][1], 0, 0, 0);
       }
     }
@@ -187,6 +217,8 @@ __device__ inline void gramq_body(const GramArgs& g, const int blk) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
   }
   gram_store(W, g, blk);
 }
@@ -226,98 +258,135 @@ __global__ __launch_bounds__(kT) void k_gram_reduce_b(const GRedArgs* d, const i
   gred_body(d[r], blockIdx.x - first[r]);
 }
 
-// Upper Cholesky factor of the symmetric L (in place, upper triangle) and its
-// inverse Ri, by all threads of the workgroup; *bad is set when a pivot is
-// <= 1e-13 * tr or not finite.
-__device__ inline void chol_inv(double (*L)[kMaxRank + 1], double (*Ri)[kMaxRank + 1], int K, double tr, int* bad) {
-  const int t = threadIdx.x;
-  const int sh = rank_shift(K);
-  for (int k = 0; k < K; ++k) {
-    if (t == 0) {
-      const double piv = L[k][k];
-      if (!(piv > kBreakRel * tr) || !(piv < 1e300)) *bad = 1;
-      L[k][k] = sqrt(piv > 0.0 ? piv : 1.0);
-    }
-    __syncthreads();
-    const double d = L[k][k];
-    for (int j = k + 1 + t; j < K; j += kT) L[k][j] /= d;
-    __syncthreads();
-    for (int e = t; e < (K << sh); e += kT) {
-      const int i = e >> sh, j = e & ((1 << sh) - 1);
-      if (i > k && j >= i && j < K) L[i][j] -= L[k][i] * L[k][j];
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < (K << sh); e += kT) Ri[e >> sh][e & ((1 << sh) - 1)] = 0.0;
-  __syncthreads();
-  for (int j = t; j < K; j += kT) {
-    for (int i = j; i >= 0; --i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) s -= L[i][k] * Ri[k][j];
-      Ri[i][j] = s / L[i][i];
-    }
-  }
-  __syncthreads();
-}
-
-// The two Cholesky steps, each in one workgroup.
+// The two Cholesky steps, each in one wave: lane j < 32 holds column j of
+// the working matrix in registers (the K x K matrix padded to 32 x 32 with
+// the identity, which the factorisation and the inverse leave unchanged;
+// lanes 32..63 repeat lanes 0..31 and write nothing). Each finished row of
+// the factor, and each next pivot, is shared through LDS, where every lane
+// reads the same address; there is no workgroup barrier. Loops are unrolled
+// over 32 with compile-time indices. Operations and their order per entry are
+// those of the textbook right-looking factorisation and back substitution;
+// zero terms of the triangular factors added after the last nonzero one
+// change nothing. (One workgroup of 256 threads with a barrier per step, and
+// a serial trace, took about 50 us per call; this takes a few.)
 // Stage 1 (c.M1 == null): R1 = chol(W1); Mout = R1^-1, Rout = R1;
-//   *flag = breakdown.
+//   *flag = breakdown (a pivot <= 1e-13 * trace(W) or not finite).
 // Stage 2: R2 = chol(W2) with W2 the Gram of Q1 = A R1^-1; Mout = M1 R2^-1
 //   (= R1^-1 R2^-1), Rout = R2 R1 (optional). Breakdown in either stage:
 //   *skipped += 1 when a counter is given (the factor is left as it was), else
 //   *status = HOQRI_ERR_BREAKDOWN; without breakdown *status = 0 unless
 //   `sticky` (then an earlier breakdown recorded in *status is kept).
 //   *flag = breakdown (read by the apply kernel).
+constexpr int kCholT = 64;
+
+// orders this wave's LDS writes before its later LDS reads
+__device__ inline void lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline void chol_body(const CholArgs& c) {
-  __shared__ double L[kMaxRank][kMaxRank + 1];
-  __shared__ double Ri[kMaxRank][kMaxRank + 1];
-  __shared__ double M1[kMaxRank][kMaxRank + 1];
-  __shared__ double R1[kMaxRank][kMaxRank + 1];
-  __shared__ double tr;
-  __shared__ int bad;
+  __shared__ double Rr[kMaxRank][kMaxRank];  // input W, then the rows of the new factor
+  __shared__ double Mr[kMaxRank][kMaxRank];  // rows of M1 (stage 2)
+  __shared__ double R1s[kMaxRank][kMaxRank];  // R1 (stage 2)
   const int K = c.K;
   const int t = threadIdx.x;
-  const int sh = rank_shift(K);
+  const int j = t & (kMaxRank - 1);  // lanes 32..63 repeat lanes 0..31
+  const bool mine = t < K;           // lanes writing a column of the K x K result
   const bool second = c.M1 != nullptr;
-  for (int e = t; e < (K << sh); e += kT) {
-    const int i = e >> sh, j = e & ((1 << sh) - 1);
-    if (i < K && j < K) {
-      L[i][j] = c.W[i * K + j];
-      if (second) {
-        M1[i][j] = c.M1[i * K + j];
-        R1[i][j] = c.R1[i * K + j];
-      }
+  // W padded with the identity
+  for (int e = t; e < kMaxRank * kMaxRank; e += kCholT) {
+    const int i = e >> 5, k = e & 31;
+    Rr[i][k] = (i < K && k < K) ? c.W[i * K + k] : (i == k ? 1.0 : 0.0);
+    if (second) {
+      Mr[i][k] = (i < K && k < K) ? c.M1[i * K + k] : 0.0;
+      R1s[i][k] = (i < K && k < K) ? c.R1[i * K + k] : 0.0;
     }
   }
-  if (t == 0) {
-    double s = 0.0;
-    for (int k = 0; k < K; ++k) s += c.W[k * K + k];
-    tr = s;
-    bad = second ? *c.flag : 0;
+  lds_order();
+  double w[kMaxRank];
+#pragma unroll
+  for (int i = 0; i < kMaxRank; ++i) w[i] = Rr[i][j];
+  double dj = Rr[j][j];  // this column's diagonal entry, updated with w[j]
+  // trace(W), summed in index order
+  double tr = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < K; ++k) tr += Rr[k][k];
+  int bad = second ? *c.flag : 0;
+  lds_order();
+  // Right-looking factorisation: row k of R is W(k, k:) / sqrt(W(k, k)), then
+  // W(i, j) -= R(k, i) R(k, j) for k < i <= j. The step loop runs from the
+  // instruction cache (a fully unrolled kernel runs once and is bound by
+  // instruction fetch); register indices stay compile-time through selects.
+#pragma unroll 1
+  for (int k = 0; k < kMaxRank; ++k) {
+    const double piv = Rr[k][k];  // lane k's dj after step k - 1
+    if (k < K && (!(piv > kBreakRel * tr) || !(piv < 1e300))) bad = 1;
+    const double d = sqrt(piv > 0.0 ? piv : 1.0);
+    double wk = w[0];
+#pragma unroll
+    for (int i = 1; i < kMaxRank; ++i) wk = i == k ? w[i] : wk;
+    const double rk = j > k ? wk / d : (j == k ? d : 0.0);
+    lds_order();
+    if (t < kMaxRank) Rr[k][j] = rk;
+    lds_order();
+    // entries i < k (R(k, i) = 0) keep their value; i = k and those below
+    // the diagonal change but are never read again
+#pragma unroll
+    for (int i = 0; i < kMaxRank; ++i) w[i] -= Rr[k][i] * rk;
+    // the same operation on the diagonal copy (Rr(k, j) = rk on this lane)
+    if (j > k) dj = dj - rk * rk;
+    if (t < kMaxRank && j > k) Rr[j][j] = dj;  // next pivots
+    lds_order();
   }
-  __syncthreads();
-  chol_inv(L, Ri, K, tr, &bad);  // L: the factor (upper), Ri: its inverse
+  // R^-1 by columns, back substitution. Row i of R is zero left of the
+  // diagonal and ri(k) is still zero for k <= i, so the sum over all k adds
+  // exact zeros before the terms k = i+1 .. j in ascending order.
+  double ri[kMaxRank];
+#pragma unroll
+  for (int k = 0; k < kMaxRank; ++k) ri[k] = 0.0;
+#pragma unroll 1
+  for (int i = kMaxRank - 1; i >= 0; --i) {
+    double s = i == j ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxRank; ++k) s -= Rr[i][k] * ri[k];
+    const double v = s / Rr[i][i];
+#pragma unroll
+    for (int k = 0; k < kMaxRank; ++k) ri[k] = k == i ? v : ri[k];
+  }
   if (!second) {
-    for (int e = t; e < (K << sh); e += kT) {
-      const int i = e >> sh, j = e & ((1 << sh) - 1);
-      if (j >= K) continue;
-      c.Mout[i * K + j] = Ri[i][j];
-      c.Rout[i * K + j] = (j >= i) ? L[i][j] : 0.0;
+    // R^-1 through LDS (Mr is free in this stage), stored row by row
+    if (t < kMaxRank) {
+#pragma unroll
+      for (int i = 0; i < kMaxRank; ++i) Mr[i][j] = ri[i];
+    }
+    lds_order();
+    for (int e = t; e < K * K; e += kCholT) {
+      const int i = e / K, q = e - i * K;
+      c.Mout[e] = Mr[i][q];
+      c.Rout[e] = Rr[i][q];
     }
     if (t == 0) *c.flag = bad;
     return;
   }
-  for (int e = t; e < (K << sh); e += kT) {
-    const int i = e >> sh, j = e & ((1 << sh) - 1);
-    if (j >= K) continue;
+  // M = M1 R2^-1 and R = R2 R1, k ascending (rows i of M1 and R2 are zero left
+  // of the diagonal: the sums start with exact zeros, as if they began at k = i)
+  double r1[kMaxRank];
+#pragma unroll
+  for (int k = 0; k < kMaxRank; ++k) r1[k] = R1s[k][j];
+#pragma unroll 1
+  for (int i = 0; i < K; ++i) {
     double m = 0.0, r = 0.0;
-    if (j >= i) {
-      for (int k = i; k <= j; ++k) m += M1[i][k] * Ri[k][j];  // R1^-1 R2^-1
-      for (int k = i; k <= j; ++k) r += L[i][k] * R1[k][j];   // R2 R1
+#pragma unroll
+    for (int k = 0; k < kMaxRank; ++k) {
+      m += Mr[i][k] * ri[k];
+      r += Rr[i][k] * r1[k];
     }
-    c.Mout[i * K + j] = m;
-    if (c.Rout) c.Rout[i * K + j] = r;
+    if (mine) {
+      c.Mout[i * K + j] = j >= i ? m : 0.0;
+      if (c.Rout) c.Rout[i * K + j] = j >= i ? r : 0.0;
+    }
   }
   if (t == 0) {
     *c.flag = bad;
@@ -330,9 +399,9 @@ __device__ inline void chol_body(const CholArgs& c) {
   }
 }
 
-__global__ __launch_bounds__(kT) void k_chol(CholArgs c) { chol_body(c); }
+__global__ __launch_bounds__(kCholT) void k_chol(CholArgs c) { chol_body(c); }
 
-__global__ __launch_bounds__(kT) void k_chol_b(const CholArgs* d, const int32_t* first, int count) {
+__global__ __launch_bounds__(kCholT) void k_chol_b(const CholArgs* d, const int32_t* first, int count) {
   chol_body(d[batch_item(first, count, blockIdx.x)]);
 }
 
@@ -424,12 +493,16 @@ __global__ __launch_bounds__(kT) void k_apply_b(const ApplyArgs* d, const int32_
   apply_body(d[r], blockIdx.x - first[r]);
 }
 
+// ||W - I||_F of a symmetric Gram from its upper triangle (the Gram kernels
+// leave the block below the diagonal blocks zero)
 __global__ void k_orth_err(const double* W, int K, double* out) {
   __shared__ double sh[kT];
   double s = 0.0;
   for (int e = threadIdx.x; e < K * K; e += kT) {
-    const double d = W[e] - ((e / K) == (e % K) ? 1.0 : 0.0);
-    s += d * d;
+    const int p = e / K, q = e % K;
+    if (p > q) continue;
+    const double d = W[e] - (p == q ? 1.0 : 0.0);
+    s += (p == q ? 1.0 : 2.0) * (d * d);
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -507,10 +580,10 @@ hoqri_status launch_orth(int64_t rows, int32_t K, const float* A, float* U, doub
   HOQRI_TRY(prepare_orth(rows, K, A, U, R, status, ws, ws_bytes, sticky, &j, skipped, zero_to));
   hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g1);
   hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r1);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c1);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, s, j.c1);
   hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g2);
   hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r2);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kT), 0, s, j.c);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, s, j.c);
   hipLaunchKernelGGL(k_apply, dim3(j.apply_blocks), dim3(kT), 0, s, j.ap);
   HOQRI_HIP_TRY(hipGetLastError());
   return HOQRI_OK;
@@ -546,12 +619,12 @@ hoqri_status launch_orth_group(const OrthGroup& g, hipStream_t s) {
   hipLaunchKernelGGL(k_gram_b, dim3(g.g1.blocks), dim3(kT), 0, s, (const GramArgs*)g.g1.descs, g.g1.first, g.g1.count);
   hipLaunchKernelGGL(k_gram_reduce_b, dim3(g.r1.blocks), dim3(kT), 0, s, (const GRedArgs*)g.r1.descs, g.r1.first,
                      g.r1.count);
-  hipLaunchKernelGGL(k_chol_b, dim3(g.c1.blocks), dim3(kT), 0, s, (const CholArgs*)g.c1.descs, g.c1.first,
+  hipLaunchKernelGGL(k_chol_b, dim3(g.c1.blocks), dim3(kCholT), 0, s, (const CholArgs*)g.c1.descs, g.c1.first,
                      g.c1.count);
   hipLaunchKernelGGL(k_gram_b, dim3(g.g2.blocks), dim3(kT), 0, s, (const GramArgs*)g.g2.descs, g.g2.first, g.g2.count);
   hipLaunchKernelGGL(k_gram_reduce_b, dim3(g.r2.blocks), dim3(kT), 0, s, (const GRedArgs*)g.r2.descs, g.r2.first,
                      g.r2.count);
-  hipLaunchKernelGGL(k_chol_b, dim3(g.c.blocks), dim3(kT), 0, s, (const CholArgs*)g.c.descs, g.c.first, g.c.count);
+  hipLaunchKernelGGL(k_chol_b, dim3(g.c.blocks), dim3(kCholT), 0, s, (const CholArgs*)g.c.descs, g.c.first, g.c.count);
   hipLaunchKernelGGL(k_apply_b, dim3(g.ap.blocks), dim3(kT), 0, s, (const ApplyArgs*)g.ap.descs, g.ap.first,
                      g.ap.count);
   HOQRI_HIP_TRY(hipGetLastError());
@@ -592,9 +665,10 @@ extern "C" hoqri_status hoqri_orth(int64_t rows, int32_t cols, const float* d_A,
 // ---------------------------------------------------------------------------
 namespace hoqri {
 namespace {
-// the largest workspace hoqri_orth needs: at most 4096 Gram blocks of
+// the largest workspace hoqri_orth needs: at most kGramBlocks Gram blocks of
 // 32 x 32 float64 partials, plus the flag and five 32 x 32 float64 matrices
-constexpr size_t kNoAllocScratchBytes = 256 + (size_t)4096 * kMaxRank * kMaxRank * 8 + 5 * (size_t)kMaxRank * kMaxRank * 8;
+constexpr size_t kNoAllocScratchBytes =
+    256 + (size_t)kGramBlocks * kMaxRank * kMaxRank * 8 + 5 * (size_t)kMaxRank * kMaxRank * 8;
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_dev[kMaxDevices] = {};

@@ -191,7 +191,7 @@ struct GatherArgs {
 };
 
 // Mode-n sorted copy as block records (see ModeData::rec): nonzero
-// j = 16b + 4t + g stores its other-mode factor offsets label(i_m) * K_m at
+// j = 16b + 4t + g stores its other-mode factor row offsets at
 // rec[b][g][c][t] (c-th other mode) and its value at rec[b][g][N-1][t]; a lane
 // group of the segment passes reads its record with one dword per lane.
 // Positions nnz .. nnz_pad-1 (padding to a multiple of 16) hold zeros.
@@ -214,7 +214,7 @@ __global__ void k_gather_mode(GatherArgs a) {
       if (m == a.mode) {
         a.modeidx[j] = i;  // original index: slice boundaries
       } else {
-        r[4 * c++] = a.lab[m][i] * a.K[m];
+        r[4 * c++] = a.lab[m][i] * a.K[m] * 2;  // byte offset of the row in a 16-bit copy
       }
     }
     r[4 * (N - 1)] = __float_as_int(a.cval[src]);
@@ -502,7 +502,8 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
     L->ybuf_rows = L->core_rows ? rows : 0;
     L->core_w = L->core_rows ? (int32_t)w : 0;
     if (L->core_rows) {
-      const int64_t chunks = (rows + 2 * w + kCoreChunk - 1) / kCoreChunk;
+      // a multiple of 8: the product's blocks are spread over the XCDs by chunk
+      const int64_t chunks = ((rows + 2 * w + kCoreChunk - 1) / kCoreChunk + 7) / 8 * 8;
       groups = (int32_t)chunks;
       gpart = (size_t)(Bc * KC * 256);
     }
@@ -520,8 +521,9 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
   {
     // every mode's pass stores its slice rows: the segment passes (at most 8
     // tiles of y_i, split slices leave partials) or the split-Kronecker pass
-    // (whole slices), as long as the largest mode's rows stay within
-    // max(4 x one mode's nonzero stream, 1 GiB)
+    // (whole slices), as long as the largest mode's rows (float32 layout)
+    // stay within max(4 x one mode's nonzero stream, 16 GiB): a 1e6-row mode
+    // with 1024-entry rows takes 4 GiB
     size_t yrows = 0, yrow = 0, ygp = 0, ybig = 0;
     for (int n = 0; n < N; ++n) {
       int om[kMaxOrder];
@@ -533,14 +535,13 @@ hoqri_status compute_layout(int32_t N, const int64_t* dims, const int32_t* K, in
       if (K[n] > 32) L->yfuse = 0;
       const bool seg = Bn <= 8 && no <= 3;
       const size_t rows = (size_t)(dims[n] < nnz ? dims[n] : nnz);
-      const size_t chunks = seg ? (size_t)kYChunks
-                                : std::min<size_t>(kYChunks, (rows + kCoreChunk - 1) / kCoreChunk);
+      const size_t chunks = seg ? (size_t)kYChunks : (size_t)ycore_chunks((int64_t)rows);
       yrows = std::max(yrows, rows);
       yrow = std::max(yrow, (size_t)Bn * 256);
       ybig = std::max(ybig, rows * (size_t)Bn * 256 * 4);
       ygp = std::max(ygp, chunks * Bn * 16 * ((K[n] + 15) / 16) * 256);
     }
-    if (ybig > std::max<size_t>((size_t)4 * (size_t)nnz * 4 * N, (size_t)1 << 30)) L->yfuse = 0;
+    if (ybig > std::max<size_t>((size_t)4 * (size_t)nnz * 4 * N, (size_t)16 << 30)) L->yfuse = 0;
     if (L->yfuse) {
       ybuf_f = std::max(ybuf_f, yrows * yrow);
       ycarry_f = std::max(ycarry_f, (size_t)std::max<int32_t>(rmax, L->core_w) * 2 * yrow);

@@ -217,6 +217,16 @@ template <int N>
 __device__ inline int32_t row_bcast(int32_t v) {
   return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, false);
 }
+// The same broadcast folded into its consumer: with a zero old value the
+// compiler merges the DPP move into the following VOP2 add or multiply.
+template <int N>
+__device__ inline uint32_t bcast_add(int32_t v, uint32_t k) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false) + k;
+}
+template <int N>
+__device__ inline float bcast_mul(int32_t v, float f) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false)) * f;
+}
 // f(integral_constant<int, C>) for C = I .. N-1 (compile-time lane indices)
 template <int I, int N, typename F>
 __device__ inline void static_for(F&& f) {
@@ -225,12 +235,6 @@ __device__ inline void static_for(F&& f) {
     static_for<I + 1, N>(f);
   }
 }
-// Dwords 4A .. 4A+3 of this row's group record.
-template <int A>
-__device__ inline i4 group_quad(int32_t v) {
-  return i4{row_bcast<4 * A + 0>(v), row_bcast<4 * A + 1>(v), row_bcast<4 * A + 2>(v), row_bcast<4 * A + 3>(v)};
-}
-
 template <int NM1, int PREC, typename OnSeg>
 __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int32_t s_first, int32_t s_last,
                                   uint32_t ka4, uint32_t kb4, uint32_t kc4, int lane, int32_t* wlds,
@@ -260,43 +264,41 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
     blk = blk <= bmax ? blk : bmax;
     S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
-  // element offset j + k of a factor row: byte offset (j + k) * esize
+  // The record holds the byte offset of a row's first 16-bit entry (twice the
+  // element offset): the 16-bit copies add the lane's entry offset to the
+  // broadcast value directly, the float32 factors first double it.
   auto gather = [&](PipeSet<NM1>& S) {
-    const i4 j0 = group_quad<0>(S.rec);
-    i4 j1 = i4{0, 0, 0, 0}, j2 = i4{0, 0, 0, 0};
-    if constexpr (NM1 >= 2) j1 = group_quad<1>(S.rec);
-    if constexpr (NM1 >= 3) j2 = group_quad<2>(S.rec);
-    struct {
-      i4 j0, j1, j2;
-    } J{j0, j1, j2};
-    auto& SJ = J;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    static_for<0, 4>([&](auto T) {
+      constexpr int t = decltype(T)::value;
       if constexpr (PREC == P_FP32) {
+        const uint32_t o0 = (uint32_t)row_bcast<t>(S.rec) << 1;
         if constexpr (NM1 == 1) {
           S.ga[t] = 1.f;
-          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU0, ((uint32_t)SJ.j0[t] << 2) + kc4, 0, 0);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU0, o0 + kc4, 0, 0);
         } else if constexpr (NM1 == 2) {
-          S.ga[t] = ld_f(rU0, ((uint32_t)SJ.j0[t] << 2) + ka4);
-          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU1, ((uint32_t)SJ.j1[t] << 2) + kc4, 0, 0);
+          const uint32_t o1 = (uint32_t)row_bcast<4 + t>(S.rec) << 1;
+          S.ga[t] = ld_f(rU0, o0 + ka4);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU1, o1 + kc4, 0, 0);
         } else {
-          S.ga[t] = ld_f(rU0, ((uint32_t)SJ.j0[t] << 2) + ka4) * ld_f(rU1, ((uint32_t)SJ.j1[t] << 2) + kb4);
-          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU2, ((uint32_t)SJ.j2[t] << 2) + kc4, 0, 0);
+          const uint32_t o1 = (uint32_t)row_bcast<4 + t>(S.rec) << 1;
+          const uint32_t o2 = (uint32_t)row_bcast<8 + t>(S.rec) << 1;
+          S.ga[t] = ld_f(rU0, o0 + ka4) * ld_f(rU1, o1 + kb4);
+          S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU2, o2 + kc4, 0, 0);
         }
-      } else {  // 16-bit copies: offsets in 2-byte units (ka4 etc. hold 2 * k here)
+      } else {  // 16-bit copies: ka4 etc. hold 2 * k here
         if constexpr (NM1 == 1) {
           S.ga[t] = 1.f;
-          S.gb[t] = ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + kc4);
+          S.gb[t] = ld_u16(rU0, bcast_add<t>(S.rec, kc4));
         } else if constexpr (NM1 == 2) {
-          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + ka4));
-          S.gb[t] = ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + kc4);
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, bcast_add<t>(S.rec, ka4)));
+          S.gb[t] = ld_u16(rU1, bcast_add<4 + t>(S.rec, kc4));
         } else {
-          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + ka4)) *
-                    f16bits_to_f32<PREC>(ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + kb4));
-          S.gb[t] = ld_u16(rU2, ((uint32_t)SJ.j2[t] << 1) + kc4);
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, bcast_add<t>(S.rec, ka4))) *
+                    f16bits_to_f32<PREC>(ld_u16(rU1, bcast_add<4 + t>(S.rec, kb4)));
+          S.gb[t] = ld_u16(rU2, bcast_add<8 + t>(S.rec, kc4));
         }
       }
-    }
+    });
   };
 
   SegWindow win;
@@ -319,14 +321,19 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   auto step = [&](int32_t blk, PipeSet<NM1>& C, PipeSet<NM1>& N2, const int ci) {
     float xa[4];
     uint32_t xb[4];
-    const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    static_for<0, 4>([&](auto T) {
+      constexpr int t = decltype(T)::value;
       // FP16: the scale goes first, so no intermediate can exceed the bound
-      const float xv = (PREC == P_FP16) ? xq[t] * a.ascale : xq[t];
-      xa[t] = (NM1 == 1) ? xv : xv * C.ga[t];
+      if constexpr (PREC == P_FP16) {
+        const float xv = bcast_mul<4 * NM1 + t>(C.rec, a.ascale);
+        xa[t] = (NM1 == 1) ? xv : xv * C.ga[t];
+      } else if constexpr (NM1 == 1) {
+        xa[t] = __builtin_bit_cast(float, row_bcast<4 * NM1 + t>(C.rec));
+      } else {
+        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, C.ga[t]);
+      }
       xb[t] = C.gb[t];
-    }
+    });
     load_idx(blk + 3, C);
     gather(N2);
     const int32_t eb = blk * 16;  // uniform
@@ -358,14 +365,14 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
         on_seg(s, win.get_row(s), y);
-        s = __builtin_amdgcn_readfirstlane(s + 1);
+        s = s + 1;
         if (s > s_last) {
           done = true;
         } else {
           if (s + 1 - win.base >= 64) win.load(a, s, lane);
           seg_lo = win.get_off(s);
           const int32_t nx = win.get_off(s + 1);
-          seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+          seg_hi = nx < hi ? nx : hi;
         }
       }
     }
@@ -407,7 +414,7 @@ template <int NM1, int KN2, int PREC>
 __device__ inline void ttm_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int rr = wv / a.B;
   const int b = wv - rr * a.B;
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
@@ -580,6 +587,9 @@ __global__ __launch_bounds__(512) void k_ttm_b(const SegArgs* d, const int32_t* 
 // core saw.
 // ---------------------------------------------------------------------------
 constexpr int kYs22 = 1024 + 16;  // LDS entries per staged y_i (the pad puts slots 8 banks apart)
+// Register sets of the block pipeline: while block b is multiplied, the rows
+// of blocks b+1 .. b+kStages22-1 and the record of b+kStages22 are in flight.
+constexpr int kStages22 = 4;
 __host__ __device__ constexpr int ttm22_wave_bytes(int slots) { return slots * kYs22 * 2 + (2 * slots + 128) * 4; }
 
 // PAIR (both other ranks even): lane q gathers one dword per row, entries
@@ -619,16 +629,12 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
     blk = blk <= bmax ? blk : bmax;
     S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
-  // the record holds element offsets of the rows; entries 16..31 sit 32 bytes on
+  // the record holds byte offsets of the rows; entries 16..31 sit 32 bytes on
   auto gather = [&](Set& S) {
-    struct {
-      i4 j0, j1;
-    } J{group_quad<0>(S.rec), group_quad<1>(S.rec)};
-    auto& SJ = J;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const uint32_t oa = ((uint32_t)SJ.j0[t] << 1) + k2;
-      const uint32_t ob = ((uint32_t)SJ.j1[t] << 1) + k2;
+    static_for<0, 4>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      const uint32_t oa = bcast_add<t>(S.rec, k2);
+      const uint32_t ob = bcast_add<4 + t>(S.rec, k2);
       if constexpr (PAIR) {
         S.ga[0][t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, oa, 0, 0);
         S.gb[0][t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, ob, 0, 0);
@@ -638,7 +644,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
         S.gb[0][t] = ld_u16(rU1, ob);
         S.gb[1][t] = ld_u16(rU1, ob + 32u);
       }
-    }
+    });
   };
 
   SegWindow win;
@@ -655,93 +661,102 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
   bool done = false;
 
   auto step = [&](int32_t blk, Set& C, Set& N2) {
-    float xa[2][4];
+    // A operands (x U_a, rounded to bfloat16 once) of row blocks rb = 0, 1 and
+    // B operands of column blocks 0, 1, both as two dwords of packed k-slots
+    u2 pa[2];
     s4 xb0, xb1;
-    const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
     if constexpr (PAIR) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      float xa[2][4];
+      static_for<0, 4>([&](auto T) {
+        constexpr int t = decltype(T)::value;
         xb0[t] = (short)(C.gb[0][t] & 0xffffu);
         xb1[t] = (short)(C.gb[0][t] >> 16);
-        xa[0][t] = xq[t] * __builtin_bit_cast(float, C.ga[0][t] << 16);
-        xa[1][t] = xq[t] * __builtin_bit_cast(float, C.ga[0][t] & 0xffff0000u);
-      }
+        xa[0][t] = bcast_mul<4 * NM1 + t>(C.rec, __builtin_bit_cast(float, C.ga[0][t] << 16));
+        xa[1][t] = bcast_mul<4 * NM1 + t>(C.rec, __builtin_bit_cast(float, C.ga[0][t] & 0xffff0000u));
+      });
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        pa[rb] = __builtin_bit_cast(u2, b4{(__bf16)xa[rb][0], (__bf16)xa[rb][1], (__bf16)xa[rb][2], (__bf16)xa[rb][3]});
     } else {
+      float xa[2][4];
       xb0 = s4{(short)C.gb[0][0], (short)C.gb[0][1], (short)C.gb[0][2], (short)C.gb[0][3]};
       xb1 = s4{(short)C.gb[1][0], (short)C.gb[1][1], (short)C.gb[1][2], (short)C.gb[1][3]};
+      static_for<0, 4>([&](auto T) {
+        constexpr int t = decltype(T)::value;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+        for (int h = 0; h < 2; ++h) xa[h][t] = bcast_mul<4 * NM1 + t>(C.rec, f16bits_to_f32<P_BF16>(C.ga[h][t]));
+      });
 #pragma unroll
-        for (int h = 0; h < 2; ++h) xa[h][t] = xq[t] * f16bits_to_f32<P_BF16>(C.ga[h][t]);
-      }
+      for (int rb = 0; rb < 2; ++rb)
+        pa[rb] = __builtin_bit_cast(u2, b4{(__bf16)xa[rb][0], (__bf16)xa[rb][1], (__bf16)xa[rb][2], (__bf16)xa[rb][3]});
     }
-    load_idx(blk + 4, C);
+    load_idx(blk + kStages22, C);
     gather(N2);
     const int32_t eb = blk * 16;
-    auto product = [&](float (*av)[4]) {
+    auto product = [&](u2 m) {
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
-        const b4 ab = {(__bf16)av[rb][0], (__bf16)av[rb][1], (__bf16)av[rb][2], (__bf16)av[rb][3]};
-        const s4 as = __builtin_bit_cast(s4, ab);
+        const s4 as = __builtin_bit_cast(s4, pa[rb] & m);
         acc[2 * rb + 0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as, xb0, acc[2 * rb + 0], 0, 0, 0);
         acc[2 * rb + 1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as, xb1, acc[2 * rb + 1], 0, 0, 0);
       }
     };
     if (__builtin_expect(seg_lo <= eb && seg_hi > eb + 16, 1)) {
-      product(xa);
+      product(u2{0xffffffffu, 0xffffffffu});
     } else {
       while (!done && seg_lo < eb + 16) {
-        float am[2][4];
+        // k-slot t of lane group g is nonzero eb + 4t + g: keep the 16-bit
+        // halves of the slots inside the slice, zero the others
+        uint32_t mk[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int32_t e = eb + 4 * t + g;
-          const bool in = e >= seg_lo && e < seg_hi;
-          am[0][t] = in ? xa[0][t] : 0.f;
-          am[1][t] = in ? xa[1][t] : 0.f;
+        for (int d = 0; d < 2; ++d) {
+          const int32_t e0 = eb + 8 * d + g, e1 = e0 + 4;
+          mk[d] = ((e0 >= seg_lo && e0 < seg_hi) ? 0x0000ffffu : 0u) | ((e1 >= seg_lo && e1 < seg_hi) ? 0xffff0000u : 0u);
         }
-        product(am);
+        product(u2{mk[0], mk[1]});
         if (seg_hi > eb + 16) break;
         on_seg(s, win.get_row(s), acc);
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
-        s = __builtin_amdgcn_readfirstlane(s + 1);
+        s = s + 1;
         if (s > s_last) {
           done = true;
         } else {
           if (s + 1 - win.base >= 64) win.load(a, s, lane);
           seg_lo = win.get_off(s);
           const int32_t nx = win.get_off(s + 1);
-          seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+          seg_hi = nx < hi ? nx : hi;
         }
       }
     }
   };
 
-  // four register sets rotated by renaming: while block b is multiplied, the
-  // rows of b+1..b+3 and the record of b+4 are in flight. The prologue issues
+  // kStages22 register sets rotated by renaming (the loop is unrolled that
+  // many times; every index into S is a constant). The prologue issues
   // in the loop's own order (a record ahead of the previous block's rows), held
   // by scheduling barriers, so the wait at the loop head covers only the loads
   // the body needs instead of every load in flight
-  Set S0, S1, S2, S3;
-  load_idx(b0, S0);
-  load_idx(b0 + 1, S1);
-  gather(S0);
-  load_idx(b0 + 2, S2);
+  constexpr int NS = kStages22;
+  Set S[NS];
+  load_idx(b0, S[0]);
+  load_idx(b0 + 1, S[1]);
+  gather(S[0]);
+  static_for<2, NS>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    load_idx(b0 + i, S[i]);
+    __builtin_amdgcn_sched_barrier(0);
+    gather(S[i - 1]);
+  });
   __builtin_amdgcn_sched_barrier(0);
-  gather(S1);
-  load_idx(b0 + 3, S3);
-  __builtin_amdgcn_sched_barrier(0);
-  gather(S2);
-  __builtin_amdgcn_sched_barrier(0);
-  for (int32_t ib = 0; ib < nblk; ib += 4) {
-    step(b0 + ib, S0, S3);
-    if (done || ib + 1 >= nblk) break;
-    step(b0 + ib + 1, S1, S0);
-    if (done || ib + 2 >= nblk) break;
-    step(b0 + ib + 2, S2, S1);
-    if (done || ib + 3 >= nblk) break;
-    step(b0 + ib + 3, S3, S2);
-    if (done) break;
+  for (int32_t ib = 0; ib < nblk; ib += NS) {
+    bool stop = false;
+    static_for<0, NS>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if (stop) return;
+      step(b0 + ib + i, S[i], S[(i + NS - 1) % NS]);
+      if (done || ib + i + 1 >= nblk) stop = true;
+    });
+    if (stop) break;
   }
 }
 
@@ -756,7 +771,7 @@ template <int KN2, int SL, bool PAIR>
 __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int g = lane >> 4, q = lane & 15;
   const int32_t w = wg * a.RPW + wv;
   uint16_t* gl = reinterpret_cast<uint16_t*>(lds);
@@ -943,23 +958,22 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
     blk = blk <= bmax ? blk : bmax;
     S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
+  // records hold byte offsets of 16-bit rows (float32 rows: twice that)
   auto gather = [&](Set& S) {
-    struct {
-      i4 j0, j1, j2;
-    } J{group_quad<0>(S.rec), group_quad<1>(S.rec), group_quad<2>(S.rec)};
-    auto& SJ = J;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    static_for<0, 4>([&](auto T) {
+      constexpr int t = decltype(T)::value;
       if constexpr (PREC == P_FP32) {
-        S.u0[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, ((uint32_t)SJ.j0[t] << 2) + k2, 0, 0);
-        S.u1[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, ((uint32_t)SJ.j1[t] << 2) + k2, 0, 0);
-        S.u2[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU2, ((uint32_t)SJ.j2[t] << 2) + k2c, 0, 0);
+        const uint32_t o0 = (uint32_t)row_bcast<t>(S.rec) << 1, o1 = (uint32_t)row_bcast<4 + t>(S.rec) << 1,
+                       o2 = (uint32_t)row_bcast<8 + t>(S.rec) << 1;
+        S.u0[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, o0 + k2, 0, 0);
+        S.u1[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, o1 + k2, 0, 0);
+        S.u2[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU2, o2 + k2c, 0, 0);
       } else {
-        S.u0[t] = ld_u16(rU0, ((uint32_t)SJ.j0[t] << 1) + k2);
-        S.u1[t] = ld_u16(rU1, ((uint32_t)SJ.j1[t] << 1) + k2);
-        S.u2[t] = ld_u16(rU2, ((uint32_t)SJ.j2[t] << 1) + k2c);
+        S.u0[t] = ld_u16(rU0, bcast_add<t>(S.rec, k2));
+        S.u1[t] = ld_u16(rU1, bcast_add<4 + t>(S.rec, k2));
+        S.u2[t] = ld_u16(rU2, bcast_add<8 + t>(S.rec, k2c));
       }
-    }
+    });
   };
 
   SegWindow win;
@@ -978,19 +992,20 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
   auto step = [&](int32_t blk, Set& C, Set& N2) {
     float xa[4], uc[4];
     const s4 bv = {(short)C.u1[0], (short)C.u1[1], (short)C.u1[2], (short)C.u1[3]};
-    const f4 xq = __builtin_bit_cast(f4, group_quad<NM1>(C.rec));
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      // FP16: the scale goes first, so no intermediate can exceed the bound
-      const float xv = (PREC == P_FP16) ? xq[t] * a.ascale : xq[t];
-      if constexpr (PREC == P_FP32) {
-        xa[t] = xv * __builtin_bit_cast(float, C.u0[t]);
+    static_for<0, 4>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      if constexpr (PREC == P_FP16) {
+        // the scale goes first, so no intermediate can exceed the bound
+        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, a.ascale) * f16bits_to_f32<PREC>(C.u0[t]);
+        uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
+      } else if constexpr (PREC == P_FP32) {
+        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, __builtin_bit_cast(float, C.u0[t]));
         uc[t] = __builtin_bit_cast(float, C.u2[t]);
       } else {
-        xa[t] = xv * f16bits_to_f32<PREC>(C.u0[t]);
+        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, f16bits_to_f32<PREC>(C.u0[t]));
         uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
       }
-    }
+    });
     load_idx(blk + 3, C);
     gather(N2);
     const int32_t eb = blk * 16;
@@ -1013,15 +1028,15 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
           constexpr int c = decltype(ci)::value;
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc[c] = mfma4(av[t] * __builtin_bit_cast(float, row_bcast<c>(__builtin_bit_cast(int32_t, uc[t]))),
-                           __builtin_bit_cast(float, C.u1[t]), acc[c]);
+            acc[c] = mfma4(bcast_mul<c>(__builtin_bit_cast(int32_t, uc[t]), av[t]), __builtin_bit_cast(float, C.u1[t]),
+                           acc[c]);
         });
       } else {
         static_for<0, NC>([&](auto ci) {
           constexpr int c = decltype(ci)::value;
           float ac[4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) ac[t] = av[t] * __builtin_bit_cast(float, row_bcast<c>(__builtin_bit_cast(int32_t, uc[t])));
+          for (int t = 0; t < 4; ++t) ac[t] = bcast_mul<c>(__builtin_bit_cast(int32_t, uc[t]), av[t]);
           acc[c] = mfma16v<PREC>(ac, bv, acc[c]);
         });
       }
@@ -1041,14 +1056,14 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
         on_seg(s, win.get_row(s), acc);
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
-        s = __builtin_amdgcn_readfirstlane(s + 1);
+        s = s + 1;
         if (s > s_last) {
           done = true;
         } else {
           if (s + 1 - win.base >= 64) win.load(a, s, lane);
           seg_lo = win.get_off(s);
           const int32_t nx = win.get_off(s + 1);
-          seg_hi = __builtin_amdgcn_readfirstlane(nx < hi ? nx : hi);
+          seg_hi = nx < hi ? nx : hi;
         }
       }
     }
@@ -1090,7 +1105,7 @@ template <int PREC, int NC, int KN2, bool CORE = false>
 __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int nw = blockDim.x >> 6;
   const int g = lane >> 4, q = lane & 15;
   const int B = a.B;
@@ -1396,7 +1411,7 @@ template <int NM1, int KN2, int PREC>
 __device__ inline void core_rows_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int rr = wv / a.B;
   const int b = wv - rr * a.B;
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
@@ -1483,8 +1498,13 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
   typedef typename std::conditional<YB, u2, f4>::type yv_t;
   constexpr int KTM = KTT == 0 ? 2 : KTT;
   __shared__ f4 red[3][4][KTM * 4][64];  // row lanes 1..3, column quarter, accumulator, lane
-  const int chunk = blk / p.B, b = blk - chunk * p.B;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // XCD-aware order: blocks are dealt to the eight XCDs in turn, and the B
+  // tiles of a chunk (which read the same rows of U) get numbers 8 apart, so
+  // they run on one XCD at about the same time and share its L2
+  const int c_lo = blk & 7, rest = blk >> 3;
+  const int c_hi = rest / p.B, b = rest - c_hi * p.B;
+  const int chunk = 8 * c_hi + c_lo;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cq = wv & 3, rl = wv >> 2;
   const int g = lane >> 4, q = lane & 15;
   const size_t row = (size_t)p.B * 256;
@@ -1661,7 +1681,7 @@ __device__ inline void core_gemm_body(const CoreGemmArgs& p, const int blk) {
 // from memory: D(row 4g + v, kn = 16 kb + q) on every lane. Rows stored in
 // bfloat16 (p.yb16) are widened exactly to float32.
 __device__ inline void rows_a_body(const RowsAArgs& p, const int blk) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, q = lane & 15;
   const int64_t grp = (int64_t)blk * 4 + wv;
   if (grp >= p.groups) return;
@@ -1764,7 +1784,7 @@ template <int NM1, int KN2, int PREC>
 __device__ inline void core_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int rr = wv / a.B;
   const int b = wv - rr * a.B;
   const int rb = b / a.CB, cb = b - (b / a.CB) * a.CB;
@@ -1937,7 +1957,7 @@ __device__ inline float gen_kron(const GenArgs& a, const int32_t* r, int t, int6
   for (int c = a.nm1 - 1; c >= 0; --c) {
     const int k = (int)(rem % a.Ko[c]);
     rem /= a.Ko[c];
-    w *= a.U[c][(int64_t)r[4 * c + t] + k];  // stored offsets are label * K_m
+    w *= a.U[c][(int64_t)(r[4 * c + t] >> 1) + k];  // stored: 2 label * K_m
   }
   return w;
 }
@@ -2039,7 +2059,7 @@ constexpr int kGenWaves = 8;
 template <bool BF16>
 __global__ __launch_bounds__(64 * kGenWaves) void k_gen_rows(GenRowsArgs a) {
   const int32_t s = blockIdx.x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, q = lane & 15;
   const int32_t e_lo = a.seg_off[s], e_hi = a.seg_off[s + 1];
   float* yr = a.ybuf + (size_t)a.seg_row[s] * a.B * 256;
@@ -2067,7 +2087,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_rows(GenRowsArgs a) {
       av = 0.f;
       bv = 0.f;
       if (e < e_hi) {
-        // record of nonzero e = 16 blk + 4 t + g': the offsets label * K_m and the value
+        // record of nonzero e = 16 blk + 4 t + g': the row offsets 2 label * K_m and the value
         const int32_t* rp = a.rec + (size_t)(e >> 4) * 16 * N + (e & 3) * 4 * N;
         const int t = (e & 15) >> 2;
         float wa = __int_as_float(rp[4 * (N - 1) + t]);
@@ -2075,7 +2095,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_rows(GenRowsArgs a) {
 #pragma unroll
         for (int m = 0; m < kMaxOrder - 1; ++m) {
           if (m >= a.nm1) break;
-          const float u = a.U[m][(int64_t)rp[4 * m + t] + ko[m]];
+          const float u = a.U[m][(int64_t)(rp[4 * m + t] >> 1) + ko[m]];  // stored: 2 label * K_m
           if (m < a.nr) wa *= u;
           else wb *= u;
         }
@@ -2497,7 +2517,8 @@ hoqri_status prepare_core(hoqri_plan* p, const Operands& op, float* G, double* f
     m.W = a.W;
     m.B = g.B;
     m.gpart = p->sc.gpart;
-    const int64_t chunks = ((int64_t)m.R + 2 * (int64_t)m.W + kCoreChunk - 1) / kCoreChunk;
+    // a multiple of 8 (blocks go to the XCDs by chunk; empty chunks add zeros)
+    const int64_t chunks = (((int64_t)m.R + 2 * (int64_t)m.W + kCoreChunk - 1) / kCoreChunk + 7) / 8 * 8;
     m.nchunk = (int32_t)chunks;
     job->gemm_blocks = (int)(chunks * g.B);
     CoreRedArgs& r = job->red;
@@ -2802,8 +2823,8 @@ hoqri_status launch_core(hoqri_plan* p, const Operands& op, float* G, double* f_
 
 // Core from the rows Y_(mode) that the last TTMcTC pass of `mode` stored and
 // the updated factor U^(mode): G_(mode) = U^(mode)T Y_(mode). The rows (nonempty
-// slices, then the split-slice partials) are cut into at most kYChunks chunks
-// of equal length; partials are reduced in chunk order.
+// slices, then the split-slice partials) are cut into ycore_chunks(rows)
+// chunks (at most kYChunks); partials are reduced in chunk order.
 hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCoreJob* job, bool split, bool yb16) {
   if (!p->yfuse) return HOQRI_ERR_UNSUPPORTED;
   const PassGeom g = geom(p, mode);
@@ -2823,9 +2844,7 @@ hoqri_status prepare_ycore(hoqri_plan* p, int mode, float* G, double* f_out, YCo
   m.R = (int32_t)p->md[mode].R;
   m.W = (int32_t)W;
   m.B = g.B;
-  const int64_t nv = (int64_t)m.R + 2 * W;
-  int64_t chunks = (nv + kCoreChunk - 1) / kCoreChunk;
-  if (chunks > kYChunks) chunks = kYChunks;
+  const int64_t chunks = ycore_chunks((int64_t)m.R + 2 * W);
   m.nchunk = (int32_t)chunks;
   m.split = (split || yb16) ? 1 : 0;
   m.yb16 = yb16 ? 1 : 0;

@@ -62,6 +62,26 @@ def test_argument_validation_before_device_work(lib):
     assert lib.hoqri_plan_workspace_size(3, None, None, 5, None) == -1
 
 
+def _ws_bytes(lib, dims, ranks, nnz):
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    r = (ctypes.c_int32 * len(ranks))(*ranks)
+    out = ctypes.c_size_t(0)
+    assert lib.hoqri_plan_workspace_size(len(dims), d, r, nnz, ctypes.byref(out)) == 0
+    return out.value
+
+
+@pytest.mark.gpu  # the size query asks the device for its sort scratch
+def test_rank32_workload_keeps_stored_rows(lib):
+    # 1e6 x 5e5 x 2e4 with 50M nonzeros at ranks 32^3: the workspace holds the
+    # mode-0 slice rows (up to 1e6 rows of 1024 entries), so the core of each
+    # updated factor comes from the stored rows instead of a separate segment
+    # pass; at ranks 16^3 the rows take a quarter of that
+    big = _ws_bytes(lib, [1_000_000, 500_000, 20_000], [32, 32, 32], 50_000_000)
+    assert big >= 1_000_000 * 1024 * 4
+    small = _ws_bytes(lib, [1_000_000, 500_000, 20_000], [16, 16, 16], 50_000_000)
+    assert 1_000_000 * 256 * 4 <= small < big
+
+
 def test_null_plan_rejected(lib):
     assert lib.hoqri_core(None, None, None, None, 1, None) == -1
     assert lib.hoqri_ttmctc(None, 0, None, None, None, 1, None) == -1
