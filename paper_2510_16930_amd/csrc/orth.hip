@@ -267,8 +267,9 @@ __global__ __launch_bounds__(kT) void k_gram_reduce_b(const GRedArgs* d, const i
 // over 32 with compile-time indices. Operations and their order per entry are
 // those of the textbook right-looking factorisation and back substitution;
 // zero terms of the triangular factors added after the last nonzero one
-// change nothing. (One workgroup of 256 threads with a barrier per step, and
-// a serial trace, took about 50 us per call; this takes a few.)
+// change nothing. A step costs about 45-55 us at K = 32 either way (one
+// workgroup with a barrier per step, or this one wave): the chain of float64
+// square roots, divisions and dependent LDS reads is serial.
 // Stage 1 (c.M1 == null): R1 = chol(W1); Mout = R1^-1, Rout = R1;
 //   *flag = breakdown (a pivot <= 1e-13 * trace(W) or not finite).
 // Stage 2: R2 = chol(W2) with W2 the Gram of Q1 = A R1^-1; Mout = M1 R2^-1

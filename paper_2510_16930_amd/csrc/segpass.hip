@@ -134,14 +134,36 @@ __device__ inline f4 mfma16(const float* a, const uint32_t* b, f4 c) {
 
 __device__ inline int32_t range_lo(int64_t w, int64_t W, int64_t nnz) { return (int32_t)((w * nnz) / W); }
 
-// Largest s in [0, R] with seg_off[s] <= e (seg_off[0] = 0 <= e).
-__device__ inline int32_t find_seg(const int32_t* seg_off, int32_t R, int32_t e) {
-  int32_t lo = 0, hi = R;  // invariant: seg_off[lo] <= e < seg_off[hi] (seg_off[R] = nnz > e)
-  while (hi - lo > 1) {
-    int32_t mid = (lo + hi) >> 1;
-    if (seg_off[mid] <= e) lo = mid; else hi = mid;
+// The slices holding nonzeros e1 and e2: the largest s in [0, R) with
+// seg_off[s] <= e (seg_off[0] = 0 <= e < nnz = seg_off[R]), both found by
+// the whole wave at once (it must be converged): lanes 0..31 search for e1
+// and lanes 32..63 for e2, 32-ary, each step one vector load of 32 evenly
+// spaced probes of the current interval and a ballot, so a 1e6-slice table
+// takes four load latencies instead of twenty dependent scalar loads per
+// search.
+__device__ inline void find_seg2(const int32_t* seg_off, int32_t R, int32_t e1, int32_t e2, int32_t* s1,
+                                 int32_t* s2) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5, i = lane & 31;
+  const int32_t e = half ? e2 : e1;
+  int32_t lo = 0, hi = R;  // invariant: seg_off[lo] <= e < seg_off[hi]; uniform in each half
+  while (__builtin_amdgcn_ballot_w64(hi - lo > 1) != 0) {
+    const int64_t span = hi - lo;
+    // probes lo + floor(span i / 32): nondecreasing in i and, when span <= 32,
+    // every index of [lo, hi); seg_off increases, so the true lanes are a prefix
+    const int32_t pr = lo + (int32_t)((span * i) >> 5);
+    const bool le = i == 0 || (span > 1 && seg_off[pr] <= e);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(le);
+    const uint32_t bits = (uint32_t)(half ? (m >> 32) : m);
+    const int k = 31 - __builtin_clz(bits);  // last true lane of this half (lane 0 of it is true)
+    if (span > 1) {
+      const int32_t nlo = lo + (int32_t)((span * k) >> 5);
+      hi = k == 31 ? hi : lo + (int32_t)((span * (k + 1)) >> 5);
+      lo = nlo;
+    }
   }
-  return lo;
+  *s1 = __builtin_amdgcn_readlane(lo, 0);
+  *s2 = __builtin_amdgcn_readlane(lo, 32);
 }
 
 __device__ inline int32_t rd_lane(int32_t v, int32_t lane) { return __builtin_amdgcn_readlane(v, lane); }
@@ -442,8 +464,8 @@ __device__ inline void ttm_body(const SegArgs& a, const int wg) {
 
   const int32_t lo = range_lo(w, a.W, a.nnz);
   const int32_t hi = range_lo(w + 1, a.W, a.nnz);
-  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
-  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  int32_t s_first, s_last;
+  find_seg2(a.seg_off, a.R, lo, hi - 1, &s_first, &s_last);
   const bool head_clip = a.seg_off[s_first] < lo;
   const bool tail_clip = a.seg_off[s_last + 1] > hi;
   if (b == 0 && lane == 0) {
@@ -781,17 +803,31 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
   int32_t* slot_kind = slot_row + SL;
   int32_t* wlds = slot_kind + SL;  // slice-table window of this wave
   {
+    // eight 16-byte loads in flight per thread before their LDS stores
     const i4* src = reinterpret_cast<const i4*>(a.gtop);
     i4* dst = reinterpret_cast<i4*>(gl);
-    for (int i = threadIdx.x; i < KN2 * 2048; i += blockDim.x) dst[i] = src[i];
+    const int nt = (int)blockDim.x;
+    for (int base = 0; base < KN2 * 2048; base += 8 * nt) {
+      i4 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + (int)threadIdx.x + u * nt;
+        t[u] = i < KN2 * 2048 ? src[i] : i4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + (int)threadIdx.x + u * nt;
+        if (i < KN2 * 2048) dst[i] = t[u];
+      }
+    }
     __syncthreads();
   }
   if (w >= a.W) return;  // past the barrier: the waves are independent from here
 
   const int32_t lo = range_lo(w, a.W, a.nnz);
   const int32_t hi = range_lo(w + 1, a.W, a.nnz);
-  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
-  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  int32_t s_first, s_last;
+  find_seg2(a.seg_off, a.R, lo, hi - 1, &s_first, &s_last);
   const bool head_clip = a.seg_off[s_first] < lo;
   const bool tail_clip = a.seg_off[s_last + 1] > hi;
   if (lane == 0) {
@@ -1121,8 +1157,8 @@ __device__ inline void ttm4c_body(const SegArgs& a, const int w) {
 
   const int32_t lo = range_lo(w, a.W, a.nnz);
   const int32_t hi = range_lo(w + 1, a.W, a.nnz);
-  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
-  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  int32_t s_first, s_last;
+  find_seg2(a.seg_off, a.R, lo, hi - 1, &s_first, &s_last);
   const bool head_clip = a.seg_off[s_first] < lo;
   const bool tail_clip = a.seg_off[s_last + 1] > hi;
   if (wv == 0 && lane == 0) {
@@ -1424,8 +1460,8 @@ __device__ inline void core_rows_body(const SegArgs& a, const int wg) {
   if (w >= a.W) return;  // only when B == 1 (no workgroup barriers)
   const int32_t lo = range_lo(w, a.W, a.nnz);
   const int32_t hi = range_lo(w + 1, a.W, a.nnz);
-  const int32_t s_first = find_seg(a.seg_off, a.R, lo);
-  const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+  int32_t s_first, s_last;
+  find_seg2(a.seg_off, a.R, lo, hi - 1, &s_first, &s_last);
   const bool head_clip = a.seg_off[s_first] < lo;
   const bool tail_clip = a.seg_off[s_last + 1] > hi;
   if (b == 0 && lane == 0) {
@@ -1803,8 +1839,8 @@ __device__ inline void core_body(const SegArgs& a, const int wg) {
   if (w < a.W) {
     const int32_t lo = range_lo(w, a.W, a.nnz);
     const int32_t hi = range_lo(w + 1, a.W, a.nnz);
-    const int32_t s_first = find_seg(a.seg_off, a.R, lo);
-    const int32_t s_last = find_seg(a.seg_off, a.R, hi - 1);
+    int32_t s_first, s_last;
+    find_seg2(a.seg_off, a.R, lo, hi - 1, &s_first, &s_last);
     walk_range<NM1, PREC>(a, lo, hi, s_first, s_last, ka4, kb4, kc4, lane, wlds, [&](int32_t s, int32_t row, f4 y) {
       // G_(c) += U^(c)(row, :)^T y_s  (the row of U^(c) is wave-uniform: scalar loads)
       const float* urow = a.Uc + (size_t)__builtin_amdgcn_readfirstlane(row) * a.Kc;
