@@ -62,7 +62,7 @@ struct Scratch {
   float* carry;        // ranges_max * 2 * 32 floats: partial rows of split slices
   int32_t* meta;       // ranges_max * 4 ints
   double* orth_ws;     // CholeskyQR2 workspace (Gram partials, factors)
-  int32_t* status;     // device status flags [4]: breakdown, skipped updates, FP16 range, spare
+  int32_t* status;     // device status flags [4]: breakdown, skipped updates, FP16 range, slice-pool fault
   double* f_dev;       // scalars [64]
   double* fsweep;      // f after each sweep inside hoqri_run [kMaxSweeps + 1]
   double* gscr;        // gradient monitor: G_(n) G_(n)^T [32*32], block partials [4096], history

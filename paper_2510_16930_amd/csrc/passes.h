@@ -42,6 +42,7 @@ struct SegArgs {
   const int32_t* out_map;   // null: A rows in label order; else row r goes to out_map[r]
   float* yrow;              // non-null: the TTMcTC pass also stores every y_i, [R][B * 256] by label
   float* ycarry;            // with yrow: partial rows of split slices [W][2][B * 256]
+  int32_t* fault;           // set to 1 if a wait of the 2 x 2-block pass's slice pool timed out
   // core
   const float* Uc;          // factor of the pass mode
   int32_t Kc;

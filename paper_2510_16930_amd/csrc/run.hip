@@ -387,14 +387,16 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     if (T % opts->check_every == 0 || T == opts->max_sweeps) {
       double fv[2];
       double gsum = 0.0;
-      int32_t st = 0;
+      int32_t st = 0, pool_fault = 0;
       HOQRI_HIP_TRY(hipMemcpyAsync(fv, fsw + T - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
       HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HOQRI_HIP_TRY(hipMemcpyAsync(&pool_fault, status + 3, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       if (opts->grad_tol > 0.0) {
         hipLaunchKernelGGL(k_grad_sweep, dim3(1), dim3(64), 0, stream, (const double*)ghist, T - 1, N, p->sc.f_dev + 16);
         HOQRI_HIP_TRY(hipMemcpyAsync(&gsum, p->sc.f_dev + 16, sizeof(double), hipMemcpyDeviceToHost, stream));
       }
       HOQRI_HIP_TRY(hipStreamSynchronize(stream));
+      if (pool_fault != 0) return HOQRI_ERR_HIP;  // a slice-pool wait timed out: results are not valid
       if (st != 0) return HOQRI_ERR_BREAKDOWN;
       f_prev = fv[0];
       f_last = fv[1];
@@ -432,12 +434,14 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
     HOQRI_TRY(launch_orth_err(p->dims[n], p->K[n], d_U_inout[n], p->sc.f_dev + 8 + n, p->sc.orth_ws,
                               p->sc.orth_ws_bytes, stream));
   double fend = 0.0;
-  int32_t st = 0, skips = 0;
+  int32_t st = 0, skips = 0, pool_fault = 0;
   HOQRI_HIP_TRY(hipMemcpyAsync(errs, p->sc.f_dev + 8, N * sizeof(double), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipMemcpyAsync(&fend, fsw + T, sizeof(double), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipMemcpyAsync(&skips, status + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HOQRI_HIP_TRY(hipMemcpyAsync(&pool_fault, status + 3, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
   HOQRI_HIP_TRY(hipStreamSynchronize(stream));
+  if (pool_fault != 0) return HOQRI_ERR_HIP;
   if (st != 0) return HOQRI_ERR_BREAKDOWN;
   (void)have_prev;
   stats->skipped_updates = skips;

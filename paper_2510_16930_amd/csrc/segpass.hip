@@ -782,14 +782,50 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
   }
 }
 
-// The pass itself: one wave per range, SL slices staged per stage-two product.
-// Stage two reads the bfloat16 operand gtop16[kb][32][lane][8] with
+// The pass itself: one wave per range. Finished slices go into a pool of
+// the workgroup (two banks of 16 bfloat16 y_i in LDS); the wave that fills
+// the 16th slot of a bank multiplies all 16 by the bfloat16 G_(n)^T on
+// v_mfma_f32_16x16x32_bf16 (each of the 16 operand rows a slice) and stores
+// their rows of A, so stage two reads the core operand once per 16 slices
+// (a wave's own four staged slices used a quarter of each product and read
+// it once per four).
+// The core operand is gtop16[kb][32][lane][8] with
 // gtop16[kb][8 b + u][lane][t] = G_(n)^T[256 b + 32 u + 8 (lane/16) + t][16 kb + lane%16]
-// (inside block b, index c*16 + r), which k_prep_gtop writes for this pass.
-// The workgroup first copies it into LDS (KN2 x 32 KB): every stage two reads
-// all of it, and from LDS that costs a short latency instead of an L2 round
-// trip per step.
-template <int KN2, int SL, bool PAIR>
+// (inside block b, index c*16 + r), which k_prep_gtop writes for this pass;
+// the workgroup first copies it into LDS (KN2 x 32 KB).
+// Pool protocol (counters in LDS, atomics by lane 0):
+//  claim idx = claims++: bank (idx / 16) % 2, slot idx % 16, round idx / 32;
+//  wait until done[bank] == round (the bank's earlier rounds multiplied);
+//  write y_i and its (row, kind, range) into the slot, then filled[bank]++;
+//  the wave whose increment fills the bank multiplies it, sets filled = 0
+//  and then done[bank] = round + 1.
+// A claimed slot is written by its claimer right after its wait, and a wait
+// is only for an earlier round of the same bank, so by induction over rounds
+// every wait ends. The last wave of the workgroup to finish its range
+// multiplies the partly filled bank. Waits are still bounded (kPoolSpin
+// sleeps): past that a wave records a fault in *a.fault, tells the others to
+// stop waiting, and goes on, so a fault in the protocol cannot hang the GPU.
+constexpr int kPoolSlots = 16;
+constexpr int kPoolSpin = 1 << 22;
+struct PoolCounters {
+  uint32_t claims, finished, filled[2], done[2], abort, pad;
+};
+__host__ __device__ constexpr int ttm22_pool_bytes() {
+  return 2 * kPoolSlots * kYs22 * 2 + 2 * kPoolSlots * 3 * 4 + (int)sizeof(PoolCounters);
+}
+__host__ __device__ constexpr int ttm22_wave_bytes() { return 128 * 4; }  // the wave's slice-table window
+
+__device__ inline uint32_t lds_fetch_add(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline uint32_t lds_load_acq(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_store_rel(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int KN2, bool PAIR>
 __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63;
@@ -797,11 +833,11 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
   const int g = lane >> 4, q = lane & 15;
   const int32_t w = wg * a.RPW + wv;
   uint16_t* gl = reinterpret_cast<uint16_t*>(lds);
-  char* base = reinterpret_cast<char*>(lds) + KN2 * 32768 + wv * ttm22_wave_bytes(SL);
-  uint16_t* ybat = reinterpret_cast<uint16_t*>(base);
-  int32_t* slot_row = reinterpret_cast<int32_t*>(base + SL * kYs22 * 2);
-  int32_t* slot_kind = slot_row + SL;
-  int32_t* wlds = slot_kind + SL;  // slice-table window of this wave
+  char* pbase = reinterpret_cast<char*>(lds) + KN2 * 32768;
+  uint16_t* pool = reinterpret_cast<uint16_t*>(pbase);                                 // [2][16][kYs22]
+  int32_t* pmeta = reinterpret_cast<int32_t*>(pbase + 2 * kPoolSlots * kYs22 * 2);    // [2][16][3]
+  PoolCounters* pc = reinterpret_cast<PoolCounters*>(pmeta + 2 * kPoolSlots * 3);
+  int32_t* wlds = reinterpret_cast<int32_t*>(pbase + ttm22_pool_bytes()) + wv * 128;  // slice-table window
   {
     // eight 16-byte loads in flight per thread before their LDS stores
     const i4* src = reinterpret_cast<const i4*>(a.gtop);
@@ -820,9 +856,12 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
         if (i < KN2 * 2048) dst[i] = t[u];
       }
     }
+    if (threadIdx.x == 0) *pc = PoolCounters{};
     __syncthreads();
   }
-  if (w >= a.W) return;  // past the barrier: the waves are independent from here
+  if (w >= a.W) return;  // past the barrier: the waves meet only through the pool from here
+  // waves of this workgroup that walk a range
+  const int32_t nact = __builtin_amdgcn_readfirstlane(a.W - wg * a.RPW < a.RPW ? a.W - wg * a.RPW : a.RPW);
 
   const int32_t lo = range_lo(w, a.W, a.nnz);
   const int32_t hi = range_lo(w + 1, a.W, a.nnz);
@@ -839,17 +878,36 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
   const uint16_t* gt = gl + lane * 8;
   constexpr uint32_t yrowf = 1024;  // entries per stored row (4 blocks, bfloat16)
 
-  int slot = 0;
-  auto stage_two = [&]() {
-    wave_sync();
+  // one atomic per wave (lane 0), result on every lane
+  auto wave_add = [&](uint32_t* ctr) -> uint32_t {
+    uint32_t r = 0;
+    if (lane == 0) r = lds_fetch_add(ctr, 1u);
+    return __builtin_amdgcn_readfirstlane(r);
+  };
+  auto pool_wait = [&](int bank, uint32_t round) {
+    for (int spins = 0;; ++spins) {
+      const uint32_t dn = __builtin_amdgcn_readfirstlane(lds_load_acq(&pc->done[bank]));
+      const uint32_t ab = __builtin_amdgcn_readfirstlane(lds_load_acq(&pc->abort));
+      if (dn >= round || ab != 0) break;
+      if (spins >= kPoolSpin) {
+        if (lane == 0) {
+          lds_store_rel(&pc->abort, 1u);
+          *a.fault = 1;
+        }
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  };
+  // stage two of the first n slots of a bank: D[slot][kn] = y_slot . G_(n)^T[:, kn]
+  auto pool_product = [&](int bank, int n) {
     f4 d[KN2];
 #pragma unroll
     for (int kb = 0; kb < KN2; ++kb) d[kb] = f4{0.f, 0.f, 0.f, 0.f};
-    // rows q >= SL of the product re-read staged rows and are not used; lane
-    // group g takes the 8 consecutive indices 32 u + 8 g .. of each 32-wide
-    // step u (v_mfma_f32_16x16x32_bf16 contracts a lane group's 8 entries of
-    // A with the same group's 8 of B)
-    const uint16_t* yr = ybat + (q % SL) * kYs22 + 8 * g;
+    // lane group g takes the 8 consecutive indices 32 u + 8 g .. of each 32-wide
+    // step u (v_mfma_f32_16x16x32_bf16 contracts a lane group's 8 entries of A
+    // with the same group's 8 of B); rows of unfilled slots are not stored
+    const uint16_t* yr = pool + (bank * kPoolSlots + q) * kYs22 + 8 * g;
     // fully unrolled: every LDS address is a base register plus an immediate
 #pragma unroll
     for (int bu = 0; bu < 32; ++bu) {
@@ -863,22 +921,20 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int sl = 4 * g + v;
-      if (sl < slot) {
-        const int32_t row = slot_row[sl];
-        const int kind = slot_kind[sl];
+      if (sl < n) {
+        const int32_t* m = pmeta + (bank * kPoolSlots + sl) * 3;
+        const int32_t row = m[0], kind = m[1], rw = m[2];
 #pragma unroll
         for (int kb = 0; kb < KN2; ++kb) {
           const int kn = 16 * kb + q;
           if (kn < a.Kn) {
             const float val = d[kb][v];
             if (kind == KIND_COMPLETE) a.A[(size_t)row * a.Kn + kn] = val;
-            else a.carry[((size_t)w * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
+            else a.carry[((size_t)rw * 2 + (kind == KIND_TAIL ? 1 : 0)) * 32 + kn] = val;
           }
         }
       }
     }
-    wave_sync();
-    slot = 0;
   };
 
   walk_range22<PAIR>(a, lo, hi, s_first, s_last, (uint32_t)q * (PAIR ? 4u : 2u), lane, wlds,
@@ -886,18 +942,12 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
     int kind = KIND_COMPLETE;
     if (s == s_first && head_clip) kind = KIND_HEAD;
     else if (s == s_last && tail_clip) kind = KIND_TAIL;
-    // stage y_s in bfloat16 (nearest even), block b at 256 b + c*16 + r
-    uint16_t* ys = ybat + slot * kYs22 + q * 16 + 4 * g;
+    // y_s in bfloat16 (nearest even), block b at 256 b + c*16 + r
     u2 yb[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const b4 v = {(__bf16)y[b].x, (__bf16)y[b].y, (__bf16)y[b].z, (__bf16)y[b].w};
       yb[b] = __builtin_bit_cast(u2, v);
-      *reinterpret_cast<s4*>(ys + 256 * b) = __builtin_bit_cast(s4, v);
-    }
-    if (lane == 0) {
-      slot_row[slot] = a.out_map ? scalar_ld(a.out_map, row) : row;
-      slot_kind[slot] = kind;
     }
     if (a.yrow) {
       // the bfloat16 y_s for the core of the updated factor: row by label; a
@@ -918,25 +968,53 @@ __device__ inline void ttm22_body(const SegArgs& a, const int wg) {
         }
       }
     }
-    if (++slot == SL) stage_two();
+    // into the pool
+    const uint32_t idx = wave_add(&pc->claims);
+    const int bank = (int)((idx >> 4) & 1u), slot = (int)(idx & 15u);
+    const uint32_t round = idx >> 5;
+    pool_wait(bank, round);
+    uint16_t* ys = pool + (bank * kPoolSlots + slot) * kYs22 + q * 16 + 4 * g;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) *reinterpret_cast<u2*>(ys + 256 * b) = yb[b];
+    if (lane == 0) {
+      int32_t* m = pmeta + (bank * kPoolSlots + slot) * 3;
+      m[0] = a.out_map ? scalar_ld(a.out_map, row) : row;
+      m[1] = kind;
+      m[2] = w;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the slot's writes, every lane
+    if (wave_add(&pc->filled[bank]) == kPoolSlots - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      pool_product(bank, kPoolSlots);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // every lane's reads of the bank
+      if (lane == 0) {
+        lds_store_rel(&pc->filled[bank], 0u);
+        lds_store_rel(&pc->done[bank], round + 1);
+      }
+    }
   });
-  if (slot > 0) stage_two();
+  // the last wave of the workgroup to finish multiplies the partly filled bank
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (wave_add(&pc->finished) == (uint32_t)nact - 1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t c = __builtin_amdgcn_readfirstlane(lds_load_acq(&pc->claims));
+    const int n = (int)(c & 15u);
+    if (n > 0) pool_product((int)((c >> 4) & 1u), n);
+  }
 }
 
-// One workgroup per CU: the core operand plus up to 12 waves (three per SIMD,
-// what the registers allow; holding the pass to 128 registers spills in the
-// per-slice path and runs slower on short slices), four staged slices each.
-constexpr int kSlots22 = 4;
-constexpr int kMaxRpw22 = 12;
+// One workgroup per CU: the core operand, the slice pool and up to 16 waves
+// (four per SIMD: the pass fits in 128 registers).
+constexpr int kMaxRpw22 = 16;
 
 template <int KN2, bool PAIR>
 __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22(SegArgs a) {
-  ttm22_body<KN2, kSlots22, PAIR>(a, blockIdx.x);
+  ttm22_body<KN2, PAIR>(a, blockIdx.x);
 }
 template <int KN2, bool PAIR>
 __global__ __launch_bounds__(64 * kMaxRpw22) void k_ttm22_b(const SegArgs* d, const int32_t* first, int count) {
   const int r = batch_item(first, count, blockIdx.x);
-  ttm22_body<KN2, kSlots22, PAIR>(d[r], blockIdx.x - first[r]);
+  ttm22_body<KN2, PAIR>(d[r], blockIdx.x - first[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2211,6 +2289,7 @@ bool fill_common(SegArgs& a, const hoqri_plan* p, int mode, const PassGeom& g, c
   a.yscale = 1.f;
   if (op.prec == OP_FP16 && !fp16_scales(p, g.nm1, &a.ascale, &a.yscale)) return false;
   a.rec = md.rec;
+  a.fault = p->sc.status + 3;
   a.seg_off = md.seg_off;
   a.seg_row = md.seg_row;
   a.R = (int32_t)md.R;
@@ -2343,7 +2422,7 @@ int rpw22(int KN2) {
       v = 65536;
     lds_max = v;
   }
-  int r = (lds_max - KN2 * 32768) / ttm22_wave_bytes(kSlots22);
+  int r = (lds_max - KN2 * 32768 - ttm22_pool_bytes()) / ttm22_wave_bytes();
   return r > kMaxRpw22 ? kMaxRpw22 : (r < 1 ? 1 : r);
 }
 
@@ -2486,7 +2565,7 @@ hoqri_status prepare_ttm(hoqri_plan* p, int mode, const Operands& op, const floa
   a.yrow = rows ? p->sc.ybuf : nullptr;
   a.ycarry = rows ? p->sc.ycarry : nullptr;
   job->threads = wide ? 64 * a.RPW : nc4 ? 64 * nw4 : 64 * g.B * a.RPW;
-  job->shmem = wide  ? (size_t)KN2 * 32768 + (size_t)a.RPW * ttm22_wave_bytes(kSlots22)
+  job->shmem = wide  ? (size_t)KN2 * 32768 + ttm22_pool_bytes() + (size_t)a.RPW * ttm22_wave_bytes()
                : nc4 ? (size_t)ttm4c_bytes(g.B, nw4, KN2)
                      : (size_t)ttm_lds_floats(a, KN2) * 4;
   job->seg_blocks = (a.W + a.RPW - 1) / a.RPW;
