@@ -133,7 +133,7 @@ struct Layout {
   size_t fpart_doubles;  // per-block partial sums of ||G||^2 of the core reduction (one per 16 entries)
 };
 constexpr int kCoreChunk = 64;  // rows per partial of the core product U^(c)T Y (core-mode pass)
-constexpr int kYChunks = 256;  // most partials of the core product from stored rows
+constexpr int kYChunks = 128;  // most partials of the core product from stored rows
 // Partials of the core product from stored rows for nv rows: one per 1024
 // rows at least, a multiple of 8 (the product's blocks are spread over the
 // eight XCDs by chunk), at most kYChunks.
