@@ -320,10 +320,11 @@ __device__ inline void chol_body(const CholArgs& c) {
   // W(i, j) -= R(k, i) R(k, j) for k < i <= j. The step loop runs from the
   // instruction cache (a fully unrolled kernel runs once and is bound by
   // instruction fetch); register indices stay compile-time through selects.
+  // (steps k >= K would leave the identity padding as it is)
 #pragma unroll 1
-  for (int k = 0; k < kMaxRank; ++k) {
+  for (int k = 0; k < K; ++k) {
     const double piv = Rr[k][k];  // lane k's dj after step k - 1
-    if (k < K && (!(piv > kBreakRel * tr) || !(piv < 1e300))) bad = 1;
+    if (!(piv > kBreakRel * tr) || !(piv < 1e300)) bad = 1;
     const double d = sqrt(piv > 0.0 ? piv : 1.0);
     double wk = w[0];
 #pragma unroll
@@ -347,8 +348,9 @@ __device__ inline void chol_body(const CholArgs& c) {
   double ri[kMaxRank];
 #pragma unroll
   for (int k = 0; k < kMaxRank; ++k) ri[k] = 0.0;
+  // (rows i >= K: the padding, whose entries of the result are not stored)
 #pragma unroll 1
-  for (int i = kMaxRank - 1; i >= 0; --i) {
+  for (int i = K - 1; i >= 0; --i) {
     double s = i == j ? 1.0 : 0.0;
 #pragma unroll
     for (int k = 0; k < kMaxRank; ++k) s -= Rr[i][k] * ri[k];
