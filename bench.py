@@ -240,6 +240,31 @@ def cpu_baseline(idx_cpu, vals_cpu, dims, ranks, U0_cpu, nnz_full, budget_s=12.0
                                         f"QR {tq1:.2f} s"}}
 
 
+def serve_cpu_baseline(reqs, res, budget_s=15.0):
+    """The FP64 oracle on the request stream: one oracle sweep of each of the
+    first requests (in submission order) until about budget_s of host time,
+    each scaled by the number of sweeps that request ran when served."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    used = est = 0.0
+    k = sweeps = 0
+    for i, q in enumerate(reqs):
+        idx = q["idx"].cpu().numpy().astype(np.int64)
+        vals = q["vals"].cpu().numpy().astype(np.float64)
+        U0 = [u.cpu().numpy() for u in q["U0"]]
+        tp, tq = _oracle_sweep(idx, vals, q["ranks"], U0)
+        used += tp + tq
+        est += (tp + tq) * max(res[i].sweeps, 1)
+        sweeps += res[i].sweeps
+        k += 1
+        if used >= budget_s:
+            break
+    return {"value": k / est, "unit": "tensors/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one FP64 numpy sweep (N core + N TTMcTC slice passes + N QR) of each of the first {k} "
+                      f"requests ({used:.1f} s), each scaled by its sweep count in the served run ({sweeps} sweeps)"}
+
+
 def copy_calibration():
     """One device copy of exactly 1 GiB (read 1 GiB, write 1 GiB): what the
     FETCH_SIZE / WRITE_SIZE counters report for it gives their scale."""
@@ -280,15 +305,19 @@ def bench_serve(args, cfg):
     t_gen = time.perf_counter() - t0
     arena = int(cfg["arena_gib"] * (1 << 30))
 
-    def one_pass(arrivals, label, graphs):
+    ttm = {}
+
+    def one_pass(arrivals, label, graphs, timed=False):
         for q in reqs:
             q["U"] = [u.clone() for u in q["U0"]]
             q["G"] = torch.empty(q["ranks"], dtype=torch.float32, device=dev)
         torch.cuda.synchronize()
         srv = H.Server(arena, max_slots=cfg["max_slots"], max_sweeps=cfg["max_sweeps"], tol=cfg["tol"],
-                       use_graphs=graphs)
+                       use_graphs=graphs, time_passes=timed)
         print(f"[bench] {label}", file=sys.stderr, flush=True)
         res, lat, wall, steps = run_stream(srv, reqs, arrivals)
+        if timed:
+            ttm["stats"] = srv.ttm_stats()
         srv.close()
         bad = [r for r in res.values() if r.status != 0]
         if bad:
@@ -299,7 +328,8 @@ def bench_serve(args, cfg):
     # Poisson passes use the faster engine
     sat = {}
     for graphs in ((False, True) if args.graphs == "both" else ((args.graphs == "on"),)):
-        sat[graphs] = one_pass(np.zeros(n), f"saturated pass (all requests at t=0), graphs={graphs}", graphs)
+        sat[graphs] = one_pass(np.zeros(n), f"saturated pass (all requests at t=0), graphs={graphs}", graphs,
+                               timed=not graphs)
     use_g = max(sat, key=lambda g: n / sat[g][2])
     res0, lat0, wall0, steps0 = sat[use_g]
     mu = n / wall0
@@ -347,6 +377,28 @@ def bench_serve(args, cfg):
         "hoqri_iters_per_s": round(float(sweeps.sum()) / wall0, 1),
         "input_gen_s": round(t_gen, 1),
     }
+    if "stats" in ttm and ttm["stats"][0] > 0:
+        # the batched TTMcTC launches of the saturated pass with direct launches
+        # (HIP events on the engine's stream around each step's TTMcTC group)
+        st, ms, byts, flops = ttm["stats"]
+        avg = ms / st
+        bpl, fpl = byts / st, flops / st
+        hbm = bpl / (avg * 1e-3) / 1e9
+        tfl = fpl / (avg * 1e-3) / 1e12
+        mfma_bound = fpl / 157.3e12 > bpl / 8e12
+        line["roofline"] = {
+            "bound": "mfma" if mfma_bound else "hbm",
+            "achieved": round(tfl if mfma_bound else hbm, 2), "peak": 157.3 if mfma_bound else 8000.0,
+            "unit": "TFLOP/s" if mfma_bound else "GB/s",
+            "frac": round((tfl / 157.3) if mfma_bound else (hbm / 8000.0), 4), "traffic": None,
+            "kernel": "batched TTMcTC group of an engine step (stage-two operands, segment passes, split-slice "
+                      "fix-ups of every request in the step; FP32)",
+            "launches": int(st), "avg_launch_ms": round(avg, 4),
+            "algorithmic_bytes_per_launch": int(bpl), "algorithmic_flops_per_launch": int(fpl),
+            "hbm_GBps_algorithmic": round(hbm, 1), "mfma_TFLOPs_algorithmic": round(tfl, 2)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = serve_cpu_baseline(reqs, res0)
     print(json.dumps(line), flush=True)
     return 0
 

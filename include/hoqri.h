@@ -304,6 +304,8 @@ typedef struct {
   int32_t use_graphs;       /* nonzero: each step's batched launches are captured into a HIP graph and
                                replayed as one launch (the previous step's executable graph is updated
                                in place when its topology is unchanged); results are bitwise the same */
+  int32_t time_passes;      /* nonzero (and use_graphs zero): HIP events around each step's batched
+                               TTMcTC launches, read by hoqri_server_ttm_stats */
 } hoqri_server_opts;
 
 typedef struct {
@@ -344,6 +346,15 @@ hoqri_status hoqri_server_step(hoqri_server* server, hipStream_t stream, hoqri_r
                                int32_t* n_results);
 /* Requests queued, requests in flight, bytes of the arena in use. */
 hoqri_status hoqri_server_info(const hoqri_server* server, int32_t* queued, int32_t* active, size_t* arena_used);
+/* With time_passes: the steps whose TTMcTC launches were timed, their total
+ * duration (ms, HIP events on the step's stream around the batched stage-two
+ * operand, segment pass and split-slice fix-up launches) and the algorithmic
+ * HBM bytes and flops of the passes they ran (per request and mode: indices
+ * and values streamed once, the slice table, each needed factor row once in
+ * float32, A^(n) written once; 2 nnz prod_{m!=n} K_m + 2 R_n prod K flops).
+ * Steps whose events have not completed yet are not counted. Host only. */
+hoqri_status hoqri_server_ttm_stats(const hoqri_server* server, int64_t* steps, double* ms, double* bytes,
+                                    double* flops);
 /* Frees the server's host memory; nothing the caller owns. In-flight requests are dropped. */
 void hoqri_server_destroy(hoqri_server* server);
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "hoqri_status_string", "hoqri_timing_enable", "hoqri_timing_read",
     "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats", "hoqri_arena_destroy",
     "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info", "hoqri_server_destroy",
-    "hoqri_sketch_start", "hoqri_orth_noalloc", "hoqri_orth_noalloc_scratch_bytes",
+    "hoqri_server_ttm_stats", "hoqri_sketch_start", "hoqri_orth_noalloc", "hoqri_orth_noalloc_scratch_bytes",
     "hoqri_plan_get_tuning", "hoqri_plan_set_tuning", "hoqri_plan_max_ranges", "hoqri_autotune",
 )
 KERNEL = {"ttmctc": 0, "core": 1, "orth": 2, "fixup": 3}
@@ -68,7 +68,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double), ("max_admit_per_step", ctypes.c_int32),
                 ("report_orth_err", ctypes.c_int32), ("keep_on_breakdown", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("time_passes", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -134,11 +134,13 @@ def load() -> ctypes.CDLL:
     L.hoqri_server_info.argtypes = [vp, P(i32), P(i32), P(sz)]
     L.hoqri_server_destroy.argtypes = [vp]
     L.hoqri_server_destroy.restype = None
+    L.hoqri_server_ttm_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double),
+                                         P(ctypes.c_double)]
     for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
                  "hoqri_ttmctc", "hoqri_orth", "hoqri_orth_noalloc", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
                  "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats",
                  "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info",
-                 "hoqri_sketch_start", "hoqri_plan_get_tuning", "hoqri_plan_set_tuning", "hoqri_autotune"):
+                 "hoqri_server_ttm_stats", "hoqri_sketch_start", "hoqri_plan_get_tuning", "hoqri_plan_set_tuning", "hoqri_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -478,13 +480,13 @@ class Server:
 
     def __init__(self, arena_bytes: int, max_slots: int = 64, max_sweeps: int = 30, tol: float = 1e-6,
                  max_admit_per_step: int = 0, report_orth_err: bool = False, keep_on_breakdown: bool = True,
-                 device=None, use_graphs: bool = False):
+                 device=None, use_graphs: bool = False, time_passes: bool = False):
         import torch
         L = load()
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device or "cuda")
         opts = ServerOpts(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(max_slots), int(max_sweeps),
                           float(tol), int(max_admit_per_step), int(bool(report_orth_err)),
-                          int(bool(keep_on_breakdown)), int(bool(use_graphs)))
+                          int(bool(keep_on_breakdown)), int(bool(use_graphs)), int(bool(time_passes)))
         h = ctypes.c_void_p()
         _check(L.hoqri_server_create(ctypes.byref(opts), ctypes.byref(h)), "hoqri_server_create")
         self._h = h
@@ -530,6 +532,14 @@ class Server:
         _check(load().hoqri_server_info(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(used)),
                "hoqri_server_info")
         return int(q.value), int(a.value), int(used.value)
+
+    def ttm_stats(self):
+        """(steps timed, total ms, algorithmic bytes, algorithmic flops) of the
+        TTMcTC launches of the steps so far (time_passes=True)."""
+        st, ms, by, fl = ctypes.c_int64(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        _check(load().hoqri_server_ttm_stats(self._h, ctypes.byref(st), ctypes.byref(ms), ctypes.byref(by),
+                                             ctypes.byref(fl)), "hoqri_server_ttm_stats")
+        return int(st.value), ms.value, by.value, fl.value
 
     def close(self):
         if self._h:

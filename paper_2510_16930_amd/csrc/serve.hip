@@ -150,6 +150,13 @@ struct hoqri_server {
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap = nullptr;  // private stream the step is captured on (the caller's may be the null stream)
   int64_t graph_instantiations = 0, graph_updates = 0;
+  // time_passes: events around the last step's TTMcTC launches (read at the
+  // next step, after its synchronisation) and the totals so far
+  hipEvent_t ttm_ev[2] = {nullptr, nullptr};
+  bool ttm_pending = false;
+  double ttm_pending_bytes = 0.0, ttm_pending_flops = 0.0;
+  int64_t ttm_steps = 0;
+  double ttm_ms = 0.0, ttm_bytes = 0.0, ttm_flops = 0.0;
   // shared with the builder thread (guarded by mu)
   std::mutex mu;
   std::condition_variable cv_build;   // builder: work or memory became available
@@ -426,6 +433,16 @@ extern "C" hoqri_status hoqri_server_create(const hoqri_server_opts* opts, hoqri
     return HOQRI_ERR_NOMEM;
   }
   for (int i = slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+  if (opts->time_passes && !opts->use_graphs) {
+    for (auto& e : S->ttm_ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipHostFree(S->pinned);
+        delete S->arena;
+        delete S;
+        return HOQRI_ERR_HIP;
+      }
+    }
+  }
   // graph capture runs on a private stream of default priority
   if (opts->use_graphs && hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking) != hipSuccess) {
     S->cap = nullptr;
@@ -500,6 +517,15 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
     HOQRI_HIP_TRY(hipMemcpyAsync(S->h_stat, S->d_stat, (size_t)slots * 4, hipMemcpyDeviceToHost, s));
     HOQRI_HIP_TRY(hipMemcpyAsync(S->h_skip, S->d_skip, (size_t)slots * 4, hipMemcpyDeviceToHost, s));
     HOQRI_HIP_TRY(hipStreamSynchronize(s));
+    if (S->ttm_pending) {  // the previous step's TTMcTC launches are complete
+      float ms = 0.f;
+      HOQRI_HIP_TRY(hipEventElapsedTime(&ms, S->ttm_ev[0], S->ttm_ev[1]));
+      S->ttm_ms += ms;
+      S->ttm_bytes += S->ttm_pending_bytes;
+      S->ttm_flops += S->ttm_pending_flops;
+      ++S->ttm_steps;
+      S->ttm_pending = false;
+    }
 
     // 2. decisions at sweep boundaries (same rule as hoqri_run with check_every = 1)
     std::vector<int> finishing, going;
@@ -546,8 +572,34 @@ extern "C" hoqri_status hoqri_server_step(hoqri_server* S, hipStream_t s, hoqri_
       }
       // the launches of this step: table uploads from pinned memory and one
       // batched launch per kernel kind (no memset nodes)
+      const bool timed = S->ttm_ev[0] && !S->o.use_graphs;
+      if (timed) {
+        // algorithmic work of this step's passes (float32 operands)
+        double by = 0.0, fl = 0.0;
+        for (int i : going) {
+          const hoqri_plan* p = act[i].plan;
+          const int n = act[i].n, N = p->N;
+          double PK = 1.0, P = 1.0, rows = 0.0;
+          for (int m = 0; m < N; ++m) {
+            PK *= p->K[m];
+            if (m != n) {
+              P *= p->K[m];
+              rows += (double)p->md[m].R * p->K[m] * 4.0;
+            }
+          }
+          by += (double)p->nnz * 4.0 * N + 8.0 * (double)p->md[n].R + rows + 4.0 * (double)p->dims[n] * p->K[n];
+          fl += 2.0 * (double)p->nnz * P + 2.0 * (double)p->md[n].R * PK;
+        }
+        S->ttm_pending_bytes = by;
+        S->ttm_pending_flops = fl;
+      }
       auto launches = [&](hipStream_t ls) -> hoqri_status {
+        if (timed) HOQRI_HIP_TRY(hipEventRecord(S->ttm_ev[0], ls));
         HOQRI_TRY((run_groups<TtmJob, TtmGroup>(tj, st, ls, stage_ttm_group, launch_ttm_group)));
+        if (timed) {
+          HOQRI_HIP_TRY(hipEventRecord(S->ttm_ev[1], ls));
+          S->ttm_pending = true;
+        }
         std::vector<const OrthJob*> op(oj.size());
         for (size_t k = 0; k < oj.size(); ++k) op[k] = &oj[k];
         OrthGroup og;
@@ -638,6 +690,16 @@ extern "C" hoqri_status hoqri_server_info(const hoqri_server* S, int32_t* queued
   return HOQRI_OK;
 }
 
+extern "C" hoqri_status hoqri_server_ttm_stats(const hoqri_server* S, int64_t* steps, double* ms, double* bytes,
+                                               double* flops) {
+  if (!S || !steps || !ms || !bytes || !flops) return HOQRI_ERR_ARG;
+  *steps = S->ttm_steps;
+  *ms = S->ttm_ms;
+  *bytes = S->ttm_bytes;
+  *flops = S->ttm_flops;
+  return HOQRI_OK;
+}
+
 extern "C" void hoqri_server_destroy(hoqri_server* S) {
   if (!S) return;
   {
@@ -652,6 +714,8 @@ extern "C" void hoqri_server_destroy(hoqri_server* S) {
     if (a.plan) hoqri_plan_destroy(a.plan);
   if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
   if (S->cap) (void)hipStreamDestroy(S->cap);
+  for (hipEvent_t e : S->ttm_ev)
+    if (e) (void)hipEventDestroy(e);
   if (S->pinned) (void)hipHostFree(S->pinned);
   delete S->arena;
   delete S;

@@ -148,3 +148,34 @@ def test_errors_do_not_disturb_other_requests():
         Us, G, st = alone(reqs[i], 3, 0.0)
         assert results[i].status == 0 and results[i].sweeps == 3
         assert torch.equal(outs[i][1], G)
+
+
+def test_pass_timing_counts_the_ttmctc_work():
+    # time_passes: HIP events around each step's batched TTMcTC launches; the
+    # algorithmic bytes and flops are those of the passes that ran (one pass per
+    # request and step), so per timed step they lie between one request's
+    # smallest and all requests' largest pass
+    reqs = make_requests(4, seed=11)
+    srv = H.Server(1 << 30, max_slots=8, max_sweeps=3, tol=0.0, time_passes=True)
+    outs = {}
+    for i, q in enumerate(reqs):
+        outs[i] = ([u.clone() for u in q["U0"]], torch.empty(q["ranks"], dtype=torch.float32, device=DEV))
+        srv.submit(i, q["idx"], q["vals"], q["dims"], q["ranks"], outs[i][0], outs[i][1])
+    done = 0
+    while done < len(reqs):
+        done += len(srv.step())
+    steps, ms, byts, flops = srv.ttm_stats()
+    srv.close()
+    assert steps >= 3 and ms > 0.0
+    one = min(q["vals"].numel() * 4 * 3 for q in reqs)
+    assert byts / steps >= one
+    assert flops > 0.0
+    # with graph-captured steps nothing is timed
+    srv = H.Server(1 << 30, max_slots=8, max_sweeps=2, tol=0.0, use_graphs=True, time_passes=True)
+    q = reqs[0]
+    srv.submit(0, q["idx"], q["vals"], q["dims"], q["ranks"], [u.clone() for u in q["U0"]],
+               torch.empty(q["ranks"], dtype=torch.float32, device=DEV))
+    while not srv.step():
+        pass
+    assert srv.ttm_stats()[0] == 0
+    srv.close()
