@@ -116,6 +116,17 @@ hoqri_status hoqri_core(hoqri_plan* plan, const float* const* d_U, float* d_G, d
 hoqri_status hoqri_ttmctc(hoqri_plan* plan, int32_t mode, const float* const* d_U, const float* d_G,
                           float* d_A, hoqri_prec prec, hipStream_t stream);
 
+/* The core G = X x {U^T} (§2.2) by the route of hoqri_run's mode update with
+ * stored rows (§4.2): the TTMcTC pass of `mode` (core operand d_G_stage, its
+ * output A discarded) keeps the rows Y_(mode) of the nonempty slices, and
+ * G_(mode) = U^(mode)T Y_(mode) follows from them. Same arguments as
+ * hoqri_core (d_f optional), plus the pass's mode and core operand (C order,
+ * the caller's). For checking that route against the definition; hoqri_core
+ * computes G directly. HOQRI_ERR_UNSUPPORTED if the plan's passes cannot keep
+ * rows. Overwrites the plan's run scratch. */
+hoqri_status hoqri_core_rows(hoqri_plan* plan, int32_t mode, const float* const* d_U, const float* d_G_stage,
+                             float* d_G, double* d_f, hoqri_prec prec, hipStream_t stream);
+
 /* Device workspace bytes hoqri_orth needs for `rows` x `cols`. Host only. */
 size_t hoqri_orth_workspace_size(int64_t rows, int32_t cols);
 

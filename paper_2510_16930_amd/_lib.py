@@ -26,7 +26,7 @@ PREC = {"fp32": 1, "bf16": 2, "fp16": 3}
 # every symbol the header declares
 EXPORTS = (
     "hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_plan_destroy",
-    "hoqri_core", "hoqri_ttmctc", "hoqri_orth_workspace_size", "hoqri_orth", "hoqri_run",
+    "hoqri_core", "hoqri_core_rows", "hoqri_ttmctc", "hoqri_orth_workspace_size", "hoqri_orth", "hoqri_run",
     "hoqri_status_string", "hoqri_timing_enable", "hoqri_timing_read",
     "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats", "hoqri_arena_destroy",
     "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info", "hoqri_server_destroy",
@@ -105,6 +105,7 @@ def load() -> ctypes.CDLL:
     L.hoqri_plan_destroy.restype = None
     L.hoqri_core.argtypes = [vp, P(vp), vp, vp, ctypes.c_int, vp]
     L.hoqri_ttmctc.argtypes = [vp, i32, P(vp), vp, vp, ctypes.c_int, vp]
+    L.hoqri_core_rows.argtypes = [vp, i32, P(vp), vp, vp, vp, ctypes.c_int, vp]
     L.hoqri_orth_workspace_size.argtypes = [i64, i32]
     L.hoqri_orth_workspace_size.restype = sz
     L.hoqri_orth.argtypes = [i64, i32, vp, vp, vp, vp, vp, sz, vp]
@@ -136,7 +137,7 @@ def load() -> ctypes.CDLL:
     L.hoqri_server_destroy.restype = None
     L.hoqri_server_ttm_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_double),
                                          P(ctypes.c_double)]
-    for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core",
+    for name in ("hoqri_plan_workspace_size", "hoqri_plan_create", "hoqri_plan_info", "hoqri_core", "hoqri_core_rows",
                  "hoqri_ttmctc", "hoqri_orth", "hoqri_orth_noalloc", "hoqri_run", "hoqri_timing_enable", "hoqri_timing_read",
                  "hoqri_arena_create", "hoqri_arena_alloc", "hoqri_arena_free", "hoqri_arena_stats",
                  "hoqri_server_create", "hoqri_server_submit", "hoqri_server_step", "hoqri_server_info",
@@ -262,6 +263,21 @@ def hoqri_core(plan: Plan, Us, G=None, f=None, prec: str = "fp32", stream=None):
         G = torch.empty(plan.ranks, dtype=torch.float32, device=Us[0].device)
     _check(L.hoqri_core(plan.handle, _ptr_array(Us), _ptr(G), _ptr(f) if f is not None else None,
                         PREC[prec], _stream(stream)), "hoqri_core")
+    return G
+
+
+def hoqri_core_rows(plan: Plan, mode: int, Us, G_stage, G=None, f=None, prec: str = "fp32", stream=None):
+    """G = X x {U^T} by the stored-row route of a mode update (TTMcTC pass of
+    `mode` with core operand G_stage, then U^(mode)T Y_(mode)); returns G."""
+    import torch
+    L = load()
+    for U in Us:
+        _need_cuda(U, torch.float32, "U")
+    _need_cuda(G_stage, torch.float32, "G_stage")
+    if G is None:
+        G = torch.empty(plan.ranks, dtype=torch.float32, device=Us[0].device)
+    _check(L.hoqri_core_rows(plan.handle, int(mode), _ptr_array(Us), _ptr(G_stage), _ptr(G),
+                             _ptr(f) if f is not None else None, PREC[prec], _stream(stream)), "hoqri_core_rows")
     return G
 
 

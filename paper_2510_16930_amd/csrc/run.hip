@@ -261,6 +261,25 @@ extern "C" hoqri_status hoqri_ttmctc(hoqri_plan* p, int32_t mode, const float* c
   return launch_ttmctc(p, mode, plan_operands(p, op), d_G, d_A, p->md[mode].inv, stream);
 }
 
+extern "C" hoqri_status hoqri_core_rows(hoqri_plan* p, int32_t mode, const float* const* d_U,
+                                        const float* d_G_stage, float* d_G, double* d_f, hoqri_prec prec,
+                                        hipStream_t stream) {
+  HOQRI_TRY(check_plan(p));
+  if (mode < 0 || mode >= p->N || !d_U || !d_G_stage || !d_G) return HOQRI_ERR_ARG;
+  for (int n = 0; n < p->N; ++n)
+    if (!d_U[n]) return HOQRI_ERR_ARG;
+  int op = 0;
+  HOQRI_TRY(check_prec(prec, &op));
+  if (!p->yfuse) return HOQRI_ERR_UNSUPPORTED;
+  if (!segpass_supported(p, mode) && !(generic_supported(p) && (op == OP_FP32 || op == OP_BF16)))
+    return HOQRI_ERR_UNSUPPORTED;
+  HOQRI_TRY(to_labels(p, d_U, stream));
+  HOQRI_TRY(refresh16_checked(p, op, -1, stream));
+  const Operands ops = plan_operands(p, op);
+  HOQRI_TRY(launch_ttmctc(p, mode, ops, d_G_stage, p->sc.A, nullptr, stream, true));
+  return launch_ycore(p, mode, d_G, d_f ? d_f : p->sc.f_dev, stream, op != OP_FP32, ttm_rows_bf16(p, mode, op));
+}
+
 extern "C" hoqri_status hoqri_sketch_start(hoqri_plan* p, const float* const* d_Omega, const float* d_Gamma,
                                           float* const* d_U_out, hipStream_t stream) {
   HOQRI_TRY(check_plan(p));

@@ -85,6 +85,7 @@ def test_rank32_workload_keeps_stored_rows(lib):
 def test_null_plan_rejected(lib):
     assert lib.hoqri_core(None, None, None, None, 1, None) == -1
     assert lib.hoqri_ttmctc(None, 0, None, None, None, 1, None) == -1
+    assert lib.hoqri_core_rows(None, 0, None, None, None, None, 1, None) == -1
     assert lib.hoqri_run(None, None, None, None, None, None, None) == -1
     info = ctypes.c_int64()
     assert lib.hoqri_plan_info(None, ctypes.byref(info), None, None) == -1
