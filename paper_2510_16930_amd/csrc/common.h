@@ -200,9 +200,12 @@ constexpr int kGradParts = 4096;
 
 // CholeskyQR2 (orth.hip).
 size_t orth_ws_bytes(int64_t rows, int32_t cols);
+// Uh (optional): the 16-bit copy of the updated rows in form prec16, written
+// by the apply kernel with them (what launch_cast16 would write).
 hoqri_status launch_orth(int64_t rows, int32_t cols, const float* A, float* U, double* R,
                          int32_t* status, void* ws, size_t ws_bytes, hipStream_t s, bool sticky,
-                         int32_t* skipped = nullptr, int64_t zero_to = 0);
+                         int32_t* skipped = nullptr, int64_t zero_to = 0, uint16_t* Uh = nullptr,
+                         int prec16 = 0, int32_t* range_flag = nullptr);
 hoqri_status launch_orth_err(int64_t rows, int32_t cols, const float* U, double* err_out, void* ws,
                              size_t ws_bytes, hipStream_t s);
 

@@ -411,6 +411,9 @@ __global__ __launch_bounds__(kCholT) void k_chol_b(const CholArgs* d, const int3
 // U = A M (M upper triangular), rows staged in LDS so U may alias A, then
 // rows [rows, zero_to) of U set to zero. Skipped entirely when this
 // factorisation broke down (*flag != 0): U keeps its previous contents.
+// With a.Uh, every updated entry of U is also written to the 16-bit copy the
+// 16-bit passes read, rounded as k_cast16 rounds it (bfloat16, or float16 of
+// u 2^15 with the range flag), so no separate cast pass re-reads U.
 // Each 64-row tile is multiplied on the float64 matrix cores: wave w takes
 // rows 16w .. 16w+15, lane (gg, q) supplies A(row q, 4s + gg) (from LDS) and
 // M(4s + gg, 16 ct + q) (kept in registers), and receives U entries
@@ -442,6 +445,7 @@ __device__ inline void apply_body(const ApplyArgs& a, const int blk) {
   int64_t base = blk * (int64_t)64;
   if (base < rows) load_tile(base);
   if (*a.flag != 0) return;
+  bool bad = false;
   double mb[8][2];
 #pragma unroll
   for (int s = 0; s < 8; ++s)
@@ -479,11 +483,24 @@ __device__ inline void apply_body(const ApplyArgs& a, const int blk) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = rw + 4 * r + gg;
-          if (row < nr && cc < K) U[(base + row) * K + cc] = (float)D[ct][r];
+          if (row < nr && cc < K) {
+            const float uf = (float)D[ct][r];
+            const int64_t at = (base + row) * K + cc;
+            U[at] = uf;
+            if (a.Uh) {
+              if (a.prec16 == OP_BF16) {
+                a.Uh[at] = __builtin_bit_cast(uint16_t, (__bf16)uf);
+              } else {
+                bad |= !(__builtin_fabsf(uf) < 1.5f);
+                a.Uh[at] = __builtin_bit_cast(uint16_t, (_Float16)(uf * 32768.f));
+              }
+            }
+          }
         }
       }
     }
   }
+  if (bad && a.range_flag) *a.range_flag = 1;
   // rows [rows, zero_to) of U (rows of empty slices) become zero with the update
   const int64_t ztot = (a.zero_to - rows) * K;
   for (int64_t t = blk * (int64_t)kT + threadIdx.x; t < ztot; t += (int64_t)a.nblk * kT) U[rows * K + t] = 0.f;
@@ -578,9 +595,15 @@ hoqri_status prepare_orth(int64_t rows, int32_t K, const float* A, float* U, dou
 }
 
 hoqri_status launch_orth(int64_t rows, int32_t K, const float* A, float* U, double* R, int32_t* status, void* ws,
-                         size_t ws_bytes, hipStream_t s, bool sticky, int32_t* skipped, int64_t zero_to) {
+                         size_t ws_bytes, hipStream_t s, bool sticky, int32_t* skipped, int64_t zero_to, uint16_t* Uh,
+                         int prec16, int32_t* range_flag) {
   OrthJob j;
   HOQRI_TRY(prepare_orth(rows, K, A, U, R, status, ws, ws_bytes, sticky, &j, skipped, zero_to));
+  if (Uh && (prec16 == OP_BF16 || prec16 == OP_FP16)) {
+    j.ap.Uh = Uh;
+    j.ap.prec16 = prec16;
+    j.ap.range_flag = range_flag;
+  }
   hipLaunchKernelGGL(k_gram, dim3(j.gram_blocks), dim3(kT), 0, s, j.g1);
   hipLaunchKernelGGL(k_gram_reduce, dim3(j.red_blocks), dim3(kT), 0, s, j.r1);
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, s, j.c1);

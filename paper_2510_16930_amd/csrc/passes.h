@@ -212,6 +212,9 @@ struct ApplyArgs {
   const int32_t* flag;
   int32_t nblk;
   int64_t zero_to;  // rows [rows, zero_to) of U are zeroed with the update
+  uint16_t* Uh;       // non-null: the 16-bit copy of rows [0, rows) of U, written with them
+  int32_t prec16;     // its form (OP_BF16, OP_FP16: as k_cast16)
+  int32_t* range_flag;  // FP16: set when an entry has magnitude >= 1.5 (as k_cast16)
 };
 struct OrthJob {
   GramArgs g1, g2;  // Gram of A; Gram of Q1 = A R1^-1

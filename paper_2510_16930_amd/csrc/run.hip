@@ -389,11 +389,12 @@ extern "C" hoqri_status hoqri_run(hoqri_plan* p, float* const* d_U_inout, float*
       for (int it = 0; it < inner; ++it) {
         {
           TimerScope to(p, HOQRI_KERNEL_ORTH, stream);
-          // rows R_n.. (empty slices) of the new factor are zeroed by the same launch
+          // rows R_n.. (empty slices) of the new factor are zeroed by the same
+          // launch, and the 16-bit forms' copy of rows ..R_n is written with it
           HOQRI_TRY(launch_orth(Rn, p->K[n], p->sc.A, Up[n], nullptr, status, p->sc.orth_ws, p->sc.orth_ws_bytes,
-                                stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n]));
+                                stream, true, opts->keep_on_breakdown ? status + 1 : nullptr, p->dims[n],
+                                op != OP_FP32 ? p->sc.Uh[n] : nullptr, op, p->sc.status + 2));
         }
-        HOQRI_TRY(refresh16(p, op, n, stream));
         // the 16-bit forms take the core from the stored rows in split bfloat16
         // (the 2 x 2-block BF16 pass stores them in bfloat16)
         if (fuse) HOQRI_TRY(launch_ycore(p, n, d_G_out, fdst, stream, op != OP_FP32, ttm_rows_bf16(p, n, op)));
