@@ -260,16 +260,18 @@ __global__ __launch_bounds__(kT) void k_gram_reduce_b(const GRedArgs* d, const i
 
 // The two Cholesky steps, each in one wave: lane j < 32 holds column j of
 // the working matrix in registers (the K x K matrix padded to 32 x 32 with
-// the identity, which the factorisation and the inverse leave unchanged;
-// lanes 32..63 repeat lanes 0..31 and write nothing). Each finished row of
-// the factor, and each next pivot, is shared through LDS, where every lane
-// reads the same address; there is no workgroup barrier. Loops are unrolled
-// over 32 with compile-time indices. Operations and their order per entry are
-// those of the textbook right-looking factorisation and back substitution;
-// zero terms of the triangular factors added after the last nonzero one
-// change nothing. A step costs about 45-55 us at K = 32 either way (one
-// workgroup with a barrier per step, or this one wave): the chain of float64
-// square roots, divisions and dependent LDS reads is serial.
+// the identity, which the factorisation leaves unchanged), and lane 32 + c
+// column c of the identity appended to it: the row operations that turn W
+// into R turn that identity into R^-T (each step divides row k by the pivot's
+// square root and subtracts R(k, i) times it from rows i > k, so
+// [W | I] -> [R | L] with L W = R, L = R W^-1 = R^-T), and R^-1 comes out of
+// the same loop with no back substitution. Each finished row of [R | R^-T]
+// and each next pivot is shared through LDS, where every lane reads the same
+// address; there is no workgroup barrier. Operations and their order per
+// entry are those of the textbook right-looking factorisation; zero terms of
+// the triangular factors added after the last nonzero one change nothing. The
+// step loop is serial (float64 square roots, divisions and dependent LDS
+// reads).
 // Stage 1 (c.M1 == null): R1 = chol(W1); Mout = R1^-1, Rout = R1;
 //   *flag = breakdown (a pivot <= 1e-13 * trace(W) or not finite).
 // Stage 2: R2 = chol(W2) with W2 the Gram of Q1 = A R1^-1; Mout = M1 R2^-1
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(kT) void k_gram_reduce_b(const GRedArgs* d, const i
 //   `sticky` (then an earlier breakdown recorded in *status is kept).
 //   *flag = breakdown (read by the apply kernel).
 constexpr int kCholT = 64;
+constexpr int kCholLd = 2 * kMaxRank + 1;  // LDS row of [R | R^-T] (odd: rows fall on different banks)
 
 // orders this wave's LDS writes before its later LDS reads
 __device__ inline void lds_order() {
@@ -288,12 +291,13 @@ __device__ inline void lds_order() {
 }
 
 __device__ inline void chol_body(const CholArgs& c) {
-  __shared__ double Rr[kMaxRank][kMaxRank];  // input W, then the rows of the new factor
-  __shared__ double Mr[kMaxRank][kMaxRank];  // rows of M1 (stage 2)
+  __shared__ double Rr[kMaxRank][kCholLd];    // input W, then the rows of [R | R^-T]
+  __shared__ double Mr[kMaxRank][kMaxRank];   // rows of M1 (stage 2)
   __shared__ double R1s[kMaxRank][kMaxRank];  // R1 (stage 2)
   const int K = c.K;
   const int t = threadIdx.x;
-  const int j = t & (kMaxRank - 1);  // lanes 32..63 repeat lanes 0..31
+  const int j = t & (kMaxRank - 1);  // column of W (t < 32) or of the appended identity (t >= 32)
+  const bool aug = t >= kMaxRank;
   const bool mine = t < K;           // lanes writing a column of the K x K result
   const bool second = c.M1 != nullptr;
   // W padded with the identity
@@ -308,7 +312,7 @@ __device__ inline void chol_body(const CholArgs& c) {
   lds_order();
   double w[kMaxRank];
 #pragma unroll
-  for (int i = 0; i < kMaxRank; ++i) w[i] = Rr[i][j];
+  for (int i = 0; i < kMaxRank; ++i) w[i] = aug ? (i == j ? 1.0 : 0.0) : Rr[i][j];
   double dj = Rr[j][j];  // this column's diagonal entry, updated with w[j]
   // trace(W), summed in index order
   double tr = 0.0;
@@ -316,11 +320,12 @@ __device__ inline void chol_body(const CholArgs& c) {
   for (int k = 0; k < K; ++k) tr += Rr[k][k];
   int bad = second ? *c.flag : 0;
   lds_order();
-  // Right-looking factorisation: row k of R is W(k, k:) / sqrt(W(k, k)), then
-  // W(i, j) -= R(k, i) R(k, j) for k < i <= j. The step loop runs from the
-  // instruction cache (a fully unrolled kernel runs once and is bound by
-  // instruction fetch); register indices stay compile-time through selects.
-  // (steps k >= K would leave the identity padding as it is)
+  // Right-looking factorisation: row k of [R | R^-T] is row k of the working
+  // [W | I] divided by sqrt(W(k, k)), then row i -= R(k, i) row k for i > k.
+  // The step loop runs from the instruction cache (a fully unrolled kernel
+  // runs once and is bound by instruction fetch); register indices stay
+  // compile-time through selects. (Steps k >= K would leave the identity
+  // padding as it is.)
 #pragma unroll 1
   for (int k = 0; k < K; ++k) {
     const double piv = Rr[k][k];  // lane k's dj after step k - 1
@@ -329,9 +334,11 @@ __device__ inline void chol_body(const CholArgs& c) {
     double wk = w[0];
 #pragma unroll
     for (int i = 1; i < kMaxRank; ++i) wk = i == k ? w[i] : wk;
-    const double rk = j > k ? wk / d : (j == k ? d : 0.0);
+    // (R: zero left of the diagonal; R^-T: its zeros right of the diagonal
+    // come out of the elimination exactly)
+    const double rk = (aug || j > k) ? wk / d : (j == k ? d : 0.0);
     lds_order();
-    if (t < kMaxRank) Rr[k][j] = rk;
+    Rr[k][t] = rk;
     lds_order();
     // entries i < k (R(k, i) = 0) keep their value; i = k and those below
     // the diagonal change but are never read again
@@ -339,45 +346,28 @@ __device__ inline void chol_body(const CholArgs& c) {
     for (int i = 0; i < kMaxRank; ++i) w[i] -= Rr[k][i] * rk;
     // the same operation on the diagonal copy (Rr(k, j) = rk on this lane)
     if (j > k) dj = dj - rk * rk;
-    if (t < kMaxRank && j > k) Rr[j][j] = dj;  // next pivots
+    if (!aug && j > k) Rr[j][j] = dj;  // next pivots
     lds_order();
-  }
-  // R^-1 by columns, back substitution. Row i of R is zero left of the
-  // diagonal and ri(k) is still zero for k <= i, so the sum over all k adds
-  // exact zeros before the terms k = i+1 .. j in ascending order.
-  double ri[kMaxRank];
-#pragma unroll
-  for (int k = 0; k < kMaxRank; ++k) ri[k] = 0.0;
-  // (rows i >= K: the padding, whose entries of the result are not stored)
-#pragma unroll 1
-  for (int i = K - 1; i >= 0; --i) {
-    double s = i == j ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < kMaxRank; ++k) s -= Rr[i][k] * ri[k];
-    const double v = s / Rr[i][i];
-#pragma unroll
-    for (int k = 0; k < kMaxRank; ++k) ri[k] = k == i ? v : ri[k];
   }
   if (!second) {
-    // R^-1 through LDS (Mr is free in this stage), stored row by row
-    if (t < kMaxRank) {
-#pragma unroll
-      for (int i = 0; i < kMaxRank; ++i) Mr[i][j] = ri[i];
-    }
-    lds_order();
+    // Mout = R^-1 = (R^-T)^T, Rout = R, stored row by row
     for (int e = t; e < K * K; e += kCholT) {
       const int i = e / K, q = e - i * K;
-      c.Mout[e] = Mr[i][q];
+      c.Mout[e] = Rr[q][kMaxRank + i];
       c.Rout[e] = Rr[i][q];
     }
     if (t == 0) *c.flag = bad;
     return;
   }
   // M = M1 R2^-1 and R = R2 R1, k ascending (rows i of M1 and R2 are zero left
-  // of the diagonal: the sums start with exact zeros, as if they began at k = i)
-  double r1[kMaxRank];
+  // of the diagonal: the sums start with exact zeros, as if they began at k = i);
+  // lane j < 32 takes column j: R2^-1(k, j) = R2^-T(j, k)
+  double ri[kMaxRank], r1[kMaxRank];
 #pragma unroll
-  for (int k = 0; k < kMaxRank; ++k) r1[k] = R1s[k][j];
+  for (int k = 0; k < kMaxRank; ++k) {
+    ri[k] = k < K ? Rr[j][kMaxRank + k] : 0.0;
+    r1[k] = R1s[k][j];
+  }
 #pragma unroll 1
   for (int i = 0; i < K; ++i) {
     double m = 0.0, r = 0.0;
