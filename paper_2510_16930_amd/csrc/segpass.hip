@@ -643,20 +643,19 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
   // where they are loaded would make the loop wait for loads still in flight
   // (PAIR: ga[0][t] / gb[0][t] hold both entries of the lane's dword)
   struct Set {
-    int32_t rec;
     uint32_t ga[2][4];  // first other factor, entry 16 rb + q
     uint32_t gb[2][4];  // second other factor, entry 16 cb + q
   };
-  auto load_idx = [&](int32_t blk, Set& S) {
+  auto load_rec = [&](int32_t blk) -> int32_t {
     blk = blk <= bmax ? blk : bmax;
-    S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
   // the record holds byte offsets of the rows; entries 16..31 sit 32 bytes on
-  auto gather = [&](Set& S) {
+  auto gather = [&](int32_t rec, Set& S) {
     static_for<0, 4>([&](auto T) {
       constexpr int t = decltype(T)::value;
-      const uint32_t oa = bcast_add<t>(S.rec, k2);
-      const uint32_t ob = bcast_add<4 + t>(S.rec, k2);
+      const uint32_t oa = bcast_add<t>(rec, k2);
+      const uint32_t ob = bcast_add<4 + t>(rec, k2);
       if constexpr (PAIR) {
         S.ga[0][t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, oa, 0, 0);
         S.gb[0][t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, ob, 0, 0);
@@ -682,7 +681,9 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
   for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
   bool done = false;
 
-  auto step = [&](int32_t blk, Set& C, Set& N2) {
+  // block blk (record crec, rows in C); the rows of block blk + 3 (record
+  // nrec) go to N2
+  auto step = [&](int32_t blk, int32_t crec, Set& C, int32_t nrec, Set& N2) {
     // A operands (x U_a, rounded to bfloat16 once) of row blocks rb = 0, 1 and
     // B operands of column blocks 0, 1, both as two dwords of packed k-slots
     u2 pa[2];
@@ -693,8 +694,8 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
         constexpr int t = decltype(T)::value;
         xb0[t] = (short)(C.gb[0][t] & 0xffffu);
         xb1[t] = (short)(C.gb[0][t] >> 16);
-        xa[0][t] = bcast_mul<4 * NM1 + t>(C.rec, __builtin_bit_cast(float, C.ga[0][t] << 16));
-        xa[1][t] = bcast_mul<4 * NM1 + t>(C.rec, __builtin_bit_cast(float, C.ga[0][t] & 0xffff0000u));
+        xa[0][t] = bcast_mul<4 * NM1 + t>(crec, __builtin_bit_cast(float, C.ga[0][t] << 16));
+        xa[1][t] = bcast_mul<4 * NM1 + t>(crec, __builtin_bit_cast(float, C.ga[0][t] & 0xffff0000u));
       });
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
@@ -706,14 +707,13 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
       static_for<0, 4>([&](auto T) {
         constexpr int t = decltype(T)::value;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) xa[h][t] = bcast_mul<4 * NM1 + t>(C.rec, f16bits_to_f32<P_BF16>(C.ga[h][t]));
+        for (int h = 0; h < 2; ++h) xa[h][t] = bcast_mul<4 * NM1 + t>(crec, f16bits_to_f32<P_BF16>(C.ga[h][t]));
       });
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
         pa[rb] = __builtin_bit_cast(u2, b4{(__bf16)xa[rb][0], (__bf16)xa[rb][1], (__bf16)xa[rb][2], (__bf16)xa[rb][3]});
     }
-    load_idx(blk + kStages22, C);
-    gather(N2);
+    gather(nrec, N2);
     const int32_t eb = blk * 16;
     auto product = [&](u2 m) {
 #pragma unroll
@@ -745,7 +745,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
           done = true;
         } else {
           if (s + 1 - win.base >= 64) win.load(a, s, lane);
-          seg_lo = win.get_off(s);
+          seg_lo = seg_hi;  // = the start of slice s, which lies below hi
           const int32_t nx = win.get_off(s + 1);
           seg_hi = nx < hi ? nx : hi;
         }
@@ -753,32 +753,44 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
     }
   };
 
-  // kStages22 register sets rotated by renaming (the loop is unrolled that
-  // many times; every index into S is a constant). The prologue issues
-  // in the loop's own order (a record ahead of the previous block's rows), held
-  // by scheduling barriers, so the wait at the loop head covers only the loads
-  // the body needs instead of every load in flight
+  // Four register sets of rows rotated by renaming and the records in three
+  // groups of four blocks (the loop is unrolled over the four blocks of a
+  // group; every index is a constant): the rows of block b + 3 are gathered
+  // at block b, and the records of group i + 2 are loaded when group i
+  // starts, so a gather's record arrived long before and waiting for it does
+  // not drain the rows in flight (vector loads complete in order). By the
+  // end of group i its waits have covered the loads issued when it started,
+  // so the records move on between groups without waiting.
   constexpr int NS = kStages22;
+  static_assert(NS == 4, "the record groups have four blocks");
   Set S[NS];
-  load_idx(b0, S[0]);
-  load_idx(b0 + 1, S[1]);
-  gather(S[0]);
-  static_for<2, NS>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    load_idx(b0 + i, S[i]);
-    __builtin_amdgcn_sched_barrier(0);
-    gather(S[i - 1]);
-  });
+  int32_t qc[4], qn[4], qf[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) qc[j] = load_rec(b0 + j);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) qn[j] = load_rec(b0 + 4 + j);
+  __builtin_amdgcn_sched_barrier(0);
+  gather(qc[0], S[0]);
+  gather(qc[1], S[1]);
+  gather(qc[2], S[2]);
   __builtin_amdgcn_sched_barrier(0);
   for (int32_t ib = 0; ib < nblk; ib += NS) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) qf[j] = load_rec(b0 + ib + 8 + j);
+    __builtin_amdgcn_sched_barrier(0);
     bool stop = false;
     static_for<0, NS>([&](auto I) {
       constexpr int i = decltype(I)::value;
       if (stop) return;
-      step(b0 + ib + i, S[i], S[(i + NS - 1) % NS]);
+      step(b0 + ib + i, qc[i], S[i], i == 0 ? qc[3] : qn[i - 1], S[(i + NS - 1) % NS]);
       if (done || ib + i + 1 >= nblk) stop = true;
     });
     if (stop) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      qc[j] = qn[j];
+      qn[j] = qf[j];
+    }
   }
 }
 
