@@ -229,7 +229,6 @@ __device__ inline void lane_offsets(const SegArgs& a, int rb, int cb, int q, uin
 // two steps earlier.
 template <int NM1>
 struct PipeSet {
-  int32_t rec;     // this lane's dword of the block record (indices and values, see below)
   float ga[4];     // row-factor part of the A operand (float32)
   uint32_t gb[4];  // column-factor entry: float32 bits, or 16-bit raw bits
 };
@@ -282,42 +281,42 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
 
   // one dword per lane; the 16 lanes of group g then share the group's record
   // by row broadcasts (instead of every lane loading all of it)
-  auto load_idx = [&](int32_t blk, PipeSet<NM1>& S) {
+  auto load_rec = [&](int32_t blk) -> int32_t {
     blk = blk <= bmax ? blk : bmax;
-    S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
   // The record holds the byte offset of a row's first 16-bit entry (twice the
   // element offset): the 16-bit copies add the lane's entry offset to the
   // broadcast value directly, the float32 factors first double it.
-  auto gather = [&](PipeSet<NM1>& S) {
+  auto gather = [&](int32_t rec, PipeSet<NM1>& S) {
     static_for<0, 4>([&](auto T) {
       constexpr int t = decltype(T)::value;
       if constexpr (PREC == P_FP32) {
-        const uint32_t o0 = (uint32_t)row_bcast<t>(S.rec) << 1;
+        const uint32_t o0 = (uint32_t)row_bcast<t>(rec) << 1;
         if constexpr (NM1 == 1) {
           S.ga[t] = 1.f;
           S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU0, o0 + kc4, 0, 0);
         } else if constexpr (NM1 == 2) {
-          const uint32_t o1 = (uint32_t)row_bcast<4 + t>(S.rec) << 1;
+          const uint32_t o1 = (uint32_t)row_bcast<4 + t>(rec) << 1;
           S.ga[t] = ld_f(rU0, o0 + ka4);
           S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU1, o1 + kc4, 0, 0);
         } else {
-          const uint32_t o1 = (uint32_t)row_bcast<4 + t>(S.rec) << 1;
-          const uint32_t o2 = (uint32_t)row_bcast<8 + t>(S.rec) << 1;
+          const uint32_t o1 = (uint32_t)row_bcast<4 + t>(rec) << 1;
+          const uint32_t o2 = (uint32_t)row_bcast<8 + t>(rec) << 1;
           S.ga[t] = ld_f(rU0, o0 + ka4) * ld_f(rU1, o1 + kb4);
           S.gb[t] = __builtin_amdgcn_raw_buffer_load_b32(rU2, o2 + kc4, 0, 0);
         }
       } else {  // 16-bit copies: ka4 etc. hold 2 * k here
         if constexpr (NM1 == 1) {
           S.ga[t] = 1.f;
-          S.gb[t] = ld_u16(rU0, bcast_add<t>(S.rec, kc4));
+          S.gb[t] = ld_u16(rU0, bcast_add<t>(rec, kc4));
         } else if constexpr (NM1 == 2) {
-          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, bcast_add<t>(S.rec, ka4)));
-          S.gb[t] = ld_u16(rU1, bcast_add<4 + t>(S.rec, kc4));
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, bcast_add<t>(rec, ka4)));
+          S.gb[t] = ld_u16(rU1, bcast_add<4 + t>(rec, kc4));
         } else {
-          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, bcast_add<t>(S.rec, ka4))) *
-                    f16bits_to_f32<PREC>(ld_u16(rU1, bcast_add<4 + t>(S.rec, kb4)));
-          S.gb[t] = ld_u16(rU2, bcast_add<8 + t>(S.rec, kc4));
+          S.ga[t] = f16bits_to_f32<PREC>(ld_u16(rU0, bcast_add<t>(rec, ka4))) *
+                    f16bits_to_f32<PREC>(ld_u16(rU1, bcast_add<4 + t>(rec, kb4)));
+          S.gb[t] = ld_u16(rU2, bcast_add<8 + t>(rec, kc4));
         }
       }
     });
@@ -340,24 +339,23 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
   // set C then receives the indices of block blk+3. FP32: four products per
   // block (sub-steps t, chains acc[t]); 16-bit: one product per block, chain
   // acc[ci] (ci = position in the three-step unroll).
-  auto step = [&](int32_t blk, PipeSet<NM1>& C, PipeSet<NM1>& N2, const int ci) {
+  auto step = [&](int32_t blk, int32_t crec, PipeSet<NM1>& C, int32_t nrec, PipeSet<NM1>& N2, const int ci) {
     float xa[4];
     uint32_t xb[4];
     static_for<0, 4>([&](auto T) {
       constexpr int t = decltype(T)::value;
       // FP16: the scale goes first, so no intermediate can exceed the bound
       if constexpr (PREC == P_FP16) {
-        const float xv = bcast_mul<4 * NM1 + t>(C.rec, a.ascale);
+        const float xv = bcast_mul<4 * NM1 + t>(crec, a.ascale);
         xa[t] = (NM1 == 1) ? xv : xv * C.ga[t];
       } else if constexpr (NM1 == 1) {
-        xa[t] = __builtin_bit_cast(float, row_bcast<4 * NM1 + t>(C.rec));
+        xa[t] = __builtin_bit_cast(float, row_bcast<4 * NM1 + t>(crec));
       } else {
-        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, C.ga[t]);
+        xa[t] = bcast_mul<4 * NM1 + t>(crec, C.ga[t]);
       }
       xb[t] = C.gb[t];
     });
-    load_idx(blk + 3, C);
-    gather(N2);
+    gather(nrec, N2);
     const int32_t eb = blk * 16;  // uniform
     auto product = [&](const float* av) {
       if constexpr (PREC == P_FP32) {
@@ -400,24 +398,38 @@ __device__ inline void walk_range(const SegArgs& a, int32_t lo, int32_t hi, int3
     }
   };
 
+  // Three register sets of rows rotated by renaming and the records in
+  // three groups of three blocks: the rows of block b + 2 are gathered at
+  // block b, and the records of group i + 2 are loaded when group i starts,
+  // so waiting for a gather's record does not drain the rows in flight
+  // (vector loads complete in order); by the end of group i its waits have
+  // covered the loads issued when it started, so the records move on
+  // between groups without waiting.
   PipeSet<NM1> S0, S1, S2;
-  // prologue in the loop's own issue order (the record of b+2 ahead of the
-  // rows of b+1), held by scheduling barriers: the wait at the loop head then
-  // covers only the loads the body needs instead of every load in flight
-  load_idx(b0, S0);
-  load_idx(b0 + 1, S1);
-  gather(S0);
-  load_idx(b0 + 2, S2);
+  int32_t qc[3], qn[3], qf[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) qc[j] = load_rec(b0 + j);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) qn[j] = load_rec(b0 + 3 + j);
   __builtin_amdgcn_sched_barrier(0);
-  gather(S1);
+  gather(qc[0], S0);
+  gather(qc[1], S1);
   __builtin_amdgcn_sched_barrier(0);
   for (int32_t ib = 0; ib < nblk; ib += 3) {
-    step(b0 + ib, S0, S2, 0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) qf[j] = load_rec(b0 + ib + 6 + j);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b0 + ib, qc[0], S0, qc[2], S2, 0);
     if (done || ib + 1 >= nblk) break;
-    step(b0 + ib + 1, S1, S0, 1);
+    step(b0 + ib + 1, qc[1], S1, qn[0], S0, 1);
     if (done || ib + 2 >= nblk) break;
-    step(b0 + ib + 2, S2, S1, 2);
+    step(b0 + ib + 2, qc[2], S2, qn[1], S1, 2);
     if (done) break;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      qc[j] = qn[j];
+      qn[j] = qf[j];
+    }
   }
 }
 
@@ -643,6 +655,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
   // where they are loaded would make the loop wait for loads still in flight
   // (PAIR: ga[0][t] / gb[0][t] hold both entries of the lane's dword)
   struct Set {
+    int32_t rec;        // the block's record (unpaired gathers: kept with the rows)
     uint32_t ga[2][4];  // first other factor, entry 16 rb + q
     uint32_t gb[2][4];  // second other factor, entry 16 cb + q
   };
@@ -682,7 +695,8 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
   bool done = false;
 
   // block blk (record crec, rows in C); the rows of block blk + 3 (record
-  // nrec) go to N2
+  // nrec) go to N2; unpaired gathers: C first receives the record of block
+  // blk + kStages22
   auto step = [&](int32_t blk, int32_t crec, Set& C, int32_t nrec, Set& N2) {
     // A operands (x U_a, rounded to bfloat16 once) of row blocks rb = 0, 1 and
     // B operands of column blocks 0, 1, both as two dwords of packed k-slots
@@ -713,6 +727,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
       for (int rb = 0; rb < 2; ++rb)
         pa[rb] = __builtin_bit_cast(u2, b4{(__bf16)xa[rb][0], (__bf16)xa[rb][1], (__bf16)xa[rb][2], (__bf16)xa[rb][3]});
     }
+    if constexpr (!PAIR) C.rec = load_rec(blk + kStages22);
     gather(nrec, N2);
     const int32_t eb = blk * 16;
     auto product = [&](u2 m) {
@@ -745,7 +760,7 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
           done = true;
         } else {
           if (s + 1 - win.base >= 64) win.load(a, s, lane);
-          seg_lo = seg_hi;  // = the start of slice s, which lies below hi
+          seg_lo = win.get_off(s);
           const int32_t nx = win.get_off(s + 1);
           seg_hi = nx < hi ? nx : hi;
         }
@@ -753,43 +768,70 @@ __device__ inline void walk_range22(const SegArgs& a, int32_t lo, int32_t hi, in
     }
   };
 
-  // Four register sets of rows rotated by renaming and the records in three
-  // groups of four blocks (the loop is unrolled over the four blocks of a
-  // group; every index is a constant): the rows of block b + 3 are gathered
-  // at block b, and the records of group i + 2 are loaded when group i
-  // starts, so a gather's record arrived long before and waiting for it does
-  // not drain the rows in flight (vector loads complete in order). By the
-  // end of group i its waits have covered the loads issued when it started,
-  // so the records move on between groups without waiting.
+  // Four register sets of rows rotated by renaming (the loop is unrolled
+  // over them; every index is a constant); the rows of block b + 3 are
+  // gathered at block b. Paired gathers: the records come in groups of four
+  // blocks, and those of group i + 2 are loaded when group i starts, so a
+  // gather's record arrived long before and waiting for it does not drain
+  // the rows in flight (vector loads complete in order); by the end of group
+  // i its waits have covered the loads issued when it started, so the
+  // records move on between groups without waiting. Unpaired gathers (twice
+  // the rows per set, no registers to spare): each set keeps its block's
+  // record, loaded one block ahead of its gathers. The prologues issue in
+  // their loop's own order, held by scheduling barriers.
   constexpr int NS = kStages22;
   static_assert(NS == 4, "the record groups have four blocks");
   Set S[NS];
-  int32_t qc[4], qn[4], qf[4];
+  if constexpr (PAIR) {
+    int32_t qc[4], qn[4], qf[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) qc[j] = load_rec(b0 + j);
+    for (int j = 0; j < 4; ++j) qc[j] = load_rec(b0 + j);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) qn[j] = load_rec(b0 + 4 + j);
-  __builtin_amdgcn_sched_barrier(0);
-  gather(qc[0], S[0]);
-  gather(qc[1], S[1]);
-  gather(qc[2], S[2]);
-  __builtin_amdgcn_sched_barrier(0);
-  for (int32_t ib = 0; ib < nblk; ib += NS) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) qf[j] = load_rec(b0 + ib + 8 + j);
+    for (int j = 0; j < 4; ++j) qn[j] = load_rec(b0 + 4 + j);
     __builtin_amdgcn_sched_barrier(0);
-    bool stop = false;
-    static_for<0, NS>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if (stop) return;
-      step(b0 + ib + i, qc[i], S[i], i == 0 ? qc[3] : qn[i - 1], S[(i + NS - 1) % NS]);
-      if (done || ib + i + 1 >= nblk) stop = true;
-    });
-    if (stop) break;
+    gather(qc[0], S[0]);
+    gather(qc[1], S[1]);
+    gather(qc[2], S[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int32_t ib = 0; ib < nblk; ib += NS) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      qc[j] = qn[j];
-      qn[j] = qf[j];
+      for (int j = 0; j < 4; ++j) qf[j] = load_rec(b0 + ib + 8 + j);
+      __builtin_amdgcn_sched_barrier(0);
+      bool stop = false;
+      static_for<0, NS>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if (stop) return;
+        step(b0 + ib + i, qc[i], S[i], i == 0 ? qc[3] : qn[i - 1], S[(i + NS - 1) % NS]);
+        if (done || ib + i + 1 >= nblk) stop = true;
+      });
+      if (stop) break;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        qc[j] = qn[j];
+        qn[j] = qf[j];
+      }
+    }
+  } else {
+    S[0].rec = load_rec(b0);
+    S[1].rec = load_rec(b0 + 1);
+    gather(S[0].rec, S[0]);
+    static_for<2, NS>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      S[i].rec = load_rec(b0 + i);
+      __builtin_amdgcn_sched_barrier(0);
+      gather(S[i - 1].rec, S[i - 1]);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    for (int32_t ib = 0; ib < nblk; ib += NS) {
+      bool stop = false;
+      static_for<0, NS>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if (stop) return;
+        constexpr int pv = (i + NS - 1) % NS;
+        step(b0 + ib + i, S[i].rec, S[i], S[pv].rec, S[pv]);
+        if (done || ib + i + 1 >= nblk) stop = true;
+      });
+      if (stop) break;
     }
   }
 }
