@@ -1119,27 +1119,26 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
 
   // raw 16-bit entries of k-slots t = 0..3, one per register (see walk_range22)
   struct Set {
-    int32_t rec;
     uint32_t u0[4], u1[4], u2[4];
   };
-  auto load_idx = [&](int32_t blk, Set& S) {
+  auto load_rec = [&](int32_t blk) -> int32_t {
     blk = blk <= bmax ? blk : bmax;
-    S.rec = __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(rRec, goff, (uint32_t)blk * (64u * (NM1 + 1)), 0);
   };
   // records hold byte offsets of 16-bit rows (float32 rows: twice that)
-  auto gather = [&](Set& S) {
+  auto gather = [&](int32_t rec, Set& S) {
     static_for<0, 4>([&](auto T) {
       constexpr int t = decltype(T)::value;
       if constexpr (PREC == P_FP32) {
-        const uint32_t o0 = (uint32_t)row_bcast<t>(S.rec) << 1, o1 = (uint32_t)row_bcast<4 + t>(S.rec) << 1,
-                       o2 = (uint32_t)row_bcast<8 + t>(S.rec) << 1;
+        const uint32_t o0 = (uint32_t)row_bcast<t>(rec) << 1, o1 = (uint32_t)row_bcast<4 + t>(rec) << 1,
+                       o2 = (uint32_t)row_bcast<8 + t>(rec) << 1;
         S.u0[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU0, o0 + k2, 0, 0);
         S.u1[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU1, o1 + k2, 0, 0);
         S.u2[t] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rU2, o2 + k2c, 0, 0);
       } else {
-        S.u0[t] = ld_u16(rU0, bcast_add<t>(S.rec, k2));
-        S.u1[t] = ld_u16(rU1, bcast_add<4 + t>(S.rec, k2));
-        S.u2[t] = ld_u16(rU2, bcast_add<8 + t>(S.rec, k2c));
+        S.u0[t] = ld_u16(rU0, bcast_add<t>(rec, k2));
+        S.u1[t] = ld_u16(rU1, bcast_add<4 + t>(rec, k2));
+        S.u2[t] = ld_u16(rU2, bcast_add<8 + t>(rec, k2c));
       }
     });
   };
@@ -1157,25 +1156,24 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
   for (int c = 0; c < NC; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
   bool done = false;
 
-  auto step = [&](int32_t blk, Set& C, Set& N2) {
+  auto step = [&](int32_t blk, int32_t crec, Set& C, int32_t nrec, Set& N2) {
     float xa[4], uc[4];
     const s4 bv = {(short)C.u1[0], (short)C.u1[1], (short)C.u1[2], (short)C.u1[3]};
     static_for<0, 4>([&](auto T) {
       constexpr int t = decltype(T)::value;
       if constexpr (PREC == P_FP16) {
         // the scale goes first, so no intermediate can exceed the bound
-        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, a.ascale) * f16bits_to_f32<PREC>(C.u0[t]);
+        xa[t] = bcast_mul<4 * NM1 + t>(crec, a.ascale) * f16bits_to_f32<PREC>(C.u0[t]);
         uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
       } else if constexpr (PREC == P_FP32) {
-        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, __builtin_bit_cast(float, C.u0[t]));
+        xa[t] = bcast_mul<4 * NM1 + t>(crec, __builtin_bit_cast(float, C.u0[t]));
         uc[t] = __builtin_bit_cast(float, C.u2[t]);
       } else {
-        xa[t] = bcast_mul<4 * NM1 + t>(C.rec, f16bits_to_f32<PREC>(C.u0[t]));
+        xa[t] = bcast_mul<4 * NM1 + t>(crec, f16bits_to_f32<PREC>(C.u0[t]));
         uc[t] = f16bits_to_f32<PREC>(C.u2[t]);
       }
     });
-    load_idx(blk + 3, C);
-    gather(N2);
+    gather(nrec, N2);
     const int32_t eb = blk * 16;
     auto product = [&](const float* av) {
       if constexpr (PREC == P_FP16) {
@@ -1237,21 +1235,32 @@ __device__ inline void walk_range4c(const SegArgs& a, int32_t lo, int32_t hi, in
     }
   };
 
+  // records two groups of three blocks ahead of their gathers (see walk_range)
   Set S0, S1, S2;
-  load_idx(b0, S0);
-  load_idx(b0 + 1, S1);
-  gather(S0);
-  load_idx(b0 + 2, S2);
+  int32_t qc[3], qn[3], qf[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) qc[j] = load_rec(b0 + j);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) qn[j] = load_rec(b0 + 3 + j);
   __builtin_amdgcn_sched_barrier(0);
-  gather(S1);
+  gather(qc[0], S0);
+  gather(qc[1], S1);
   __builtin_amdgcn_sched_barrier(0);
   for (int32_t ib = 0; ib < nblk; ib += 3) {
-    step(b0 + ib, S0, S2);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) qf[j] = load_rec(b0 + ib + 6 + j);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b0 + ib, qc[0], S0, qc[2], S2);
     if (done || ib + 1 >= nblk) break;
-    step(b0 + ib + 1, S1, S0);
+    step(b0 + ib + 1, qc[1], S1, qn[0], S0);
     if (done || ib + 2 >= nblk) break;
-    step(b0 + ib + 2, S2, S1);
+    step(b0 + ib + 2, qc[2], S2, qn[1], S1);
     if (done) break;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      qc[j] = qn[j];
+      qn[j] = qf[j];
+    }
   }
 }
 
