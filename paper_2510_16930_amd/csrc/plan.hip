@@ -361,7 +361,7 @@ hoqri_status validate_shape(int32_t N, const int64_t* dims, const int32_t* K, in
 }
 
 // Stage-two operand size (floats) of the TTMcTC pass on mode n and the core
-// partial size (floats) of the core pass on mode n; see segpass_f32.hip.
+// partial size (floats) of the core pass on mode n; see segpass.hip.
 // Stage-two operand and core-partial sizes of mode n's segment pass (zero when
 // the shape is beyond the passes: then mode n takes the generic kernels).
 // Stage-two operand (any mode: the segment passes and the split-Kronecker
