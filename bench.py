@@ -279,6 +279,56 @@ def copy_calibration():
     return 0
 
 
+def gather_only(args, cfg):
+    """The gather-only pass of each mode (libhoqri_gather.so): the same index
+    streams as that mode's TTMcTC pass (the plan's order, degree labels), one
+    64-byte row of each other mode per nonzero and nothing else, with 4-byte
+    and with 16-byte loads per lane; median of `steps` timed launches after
+    `warmup`, HIP events on the launching stream. A reference point for the
+    pass's gathers, not a lower bound."""
+    import torch
+    from paper_2510_16930_amd import gather_only as GO
+
+    dims, ranks = cfg["dims"], cfg["ranks"]
+    esz = 4 if cfg["prec"] == "fp32" else 2
+    if len(dims) != 3 or any(k * esz != 64 for k in ranks):
+        print(json.dumps({"error": "the gather-only pass covers 3-way workloads whose factor rows are 64 bytes"}))
+        return 2
+    dev = torch.device("cuda:0")
+    idx, _ = make_input(cfg, dev)
+    labs = GO.degree_labels(idx, dims)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    tables = [torch.randn(d, 16, device=dev, generator=g) for d in dims]
+    grid = 4096
+    out = torch.empty(grid * 256, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for n in range(3):
+        i1, i2, o = GO.mode_stream(idx, labs, dims, n)
+        GO.check_operands(tables[o[0]], tables[o[1]], i1, i2, out, grid)
+        row = {}
+        for wide in (False, True):
+            ts = []
+            for rep in range(args.warmup + args.steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                GO.gather_only(tables[o[0]], tables[o[1]], i1, i2, wide, out, grid, stream, checked=True)
+                e1.record(stream)
+                e1.synchronize()
+                if rep >= args.warmup:
+                    ts.append(e0.elapsed_time(e1))
+            ts.sort()
+            row["16B" if wide else "4B"] = round(ts[len(ts) // 2], 4)
+        res[f"mode{n}"] = row
+        print(f"[bench] gather-only pass, mode {n}: {row} ms", file=sys.stderr, flush=True)
+        del i1, i2
+    print(json.dumps({"gather_only_ms": res, "row_bytes": 64, "grid": grid, "steps": args.steps,
+                      "warmup": args.warmup, "config": {"workload": cfg["desc"], "nnz": cfg["nnz"]}}), flush=True)
+    return 0
+
+
 def bench_serve(args, cfg):
     """Request stream through the server: saturated throughput first (every
     request queued at time 0), then Poisson arrivals at `load` times that rate;
@@ -424,6 +474,9 @@ def main():
                          "shapes and new ones are timed")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device-to-device copy and exit (scale for HBM byte counters)")
+    ap.add_argument("--gather-only", action="store_true",
+                    help="time a pass of only the factor-row gathers of each mode's TTMcTC pass on the workload's "
+                         "index streams (3-way workloads with 64-byte rows: c2, c3) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
@@ -437,6 +490,8 @@ def main():
     from paper_2510_16930_amd import _lib as H
 
     cfg = CONFIGS[args.config]
+    if args.gather_only:
+        return gather_only(args, cfg)
     if cfg.get("serve"):
         return bench_serve(args, cfg)
     dev = torch.device("cuda:0")

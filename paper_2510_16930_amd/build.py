@@ -1,4 +1,6 @@
-"""Builds libhoqri.so (the HIP library behind include/hoqri.h) for gfx950.
+"""Builds libhoqri.so (the HIP library behind include/hoqri.h) for gfx950,
+and libhoqri_gather.so (include/hoqri_gather.h), the gather-only measurement
+aid built from measure/*.hip.
 
 Each csrc/*.hip file is compiled separately with hipcc and linked into
 paper_2510_16930_amd/libhoqri.so. Packed float32 instructions are disabled
@@ -24,6 +26,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhoqri.so")
+MEASURE = os.path.join(PKG, "measure")
+GATHER_OUT = os.path.join(PKG, "libhoqri_gather.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 ARCH = os.environ.get("HOQRI_ARCH", "gfx950")
@@ -37,8 +41,8 @@ FLAGS = [
 ]
 
 
-def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+def sources(folder: str = CSRC):
+    return sorted(os.path.join(folder, f) for f in os.listdir(folder) if f.endswith(".hip"))
 
 
 # extra flags per translation unit
@@ -54,20 +58,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compiles every HIP source and links libhoqri.so; returns its path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sources()
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp"
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    """Compiles every HIP source, links libhoqri.so and libhoqri_gather.so;
+    returns the path of libhoqri.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    srcs, msrcs = sources(), sources(MEASURE)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, srcs + msrcs))
+    _link(objs[:len(srcs)], OUT)
+    _link(objs[len(srcs):], GATHER_OUT)
     if verbose:
-        print(f"built {OUT} from {len(srcs)} sources")
+        print(f"built {OUT} from {len(srcs)} sources, {GATHER_OUT} from {len(msrcs)}")
     return OUT
 
 
