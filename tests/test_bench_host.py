@@ -75,3 +75,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+@pytest.mark.parametrize("config", ["c4", "c3f32", "c1"])
+def test_gather_only_refuses_rows_other_than_64_bytes(config):
+    # the gather-only pass reads 64-byte rows of 3-way workloads (c2 at 16
+    # float32, c3 at 32 bfloat16); other workloads are refused before any
+    # device work
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", config, "--gather-only"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "64 bytes" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
